@@ -1,0 +1,208 @@
+/*
+ * hpt.h -- C ABI of the MI355X wave path tracer (HoloPathTracer, ACM TOG
+ * 45(4) 2026, Sec. 4).
+ *
+ * The library renders the T time-multiplexed complex fields U_m of a scene on
+ * a recording plane (SLM): every pixel sends rays into its recordable cone
+ * (Sec. 4.1), delta lobes extend a coherent path and add n_i L_i to the
+ * optical path length, the first non-delta hit is the real image point P
+ * whose amplitude comes from incoherent radiance rays (Sec. 4.2, Eq. 1), and
+ * every frame m accumulates A exp(i(k r + phi_m(Q))) with phi_m from a
+ * band-limited random field (Eq. 4, Eq. 5); all frames reuse one path set
+ * (Path Reuse, Sec. 4.3).
+ *
+ * Conventions
+ *  - Units are metres. The SLM is the plane z = 0 of hologram space, normal
+ *    +z; pixel (i, j) has its centre at ((i+1/2) - W/2) d, ((j+1/2) - H/2) d.
+ *  - Every call returns an hpt_status (0 = ok, < 0 = error) and never
+ *    throws. hpt_last_error() returns a thread-local message for the last
+ *    failing call of the calling thread.
+ *  - "host" pointers are ordinary CPU memory, owned by the caller and copied
+ *    before the call returns. "device" pointers are HIP device memory on the
+ *    context's device.
+ *  - Output fields are complex64 stored as interleaved (re, im) float pairs,
+ *    layout [channel][frame][crop_h][crop_w], normalised by 1/spp. The RS
+ *    prefactor 1/(i lambda) of Eq. 2 is left out (a global constant).
+ *  - Calls on one context are thread-safe. Jobs run asynchronously on the
+ *    context's own HIP stream; a caller-provided output buffer must stay
+ *    alive and untouched until hpt_job_wait() has returned HPT_OK.
+ */
+#ifndef HPT_H
+#define HPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HPT_OK = 0,
+  HPT_EINVAL = -1,     /* invalid argument; nothing was changed */
+  HPT_ENOMEM = -2,     /* device allocation failed */
+  HPT_EBUDGET = -3,    /* the request can never fit the context's HBM budget */
+  HPT_ENOTFOUND = -4,  /* unknown scene or job handle */
+  HPT_EBUSY = -5,      /* resource still used by a running job */
+  HPT_EDEVICE = -6,    /* HIP runtime or kernel error */
+  HPT_ETIMEOUT = -7,   /* hpt_job_wait timed out; the job keeps running */
+  HPT_ECANCELED = -8,  /* the job was cancelled */
+  HPT_ENODEV = -9      /* no usable gfx950 device */
+} hpt_status;
+
+typedef struct hpt_ctx hpt_ctx;
+
+/* Create a context on HIP device `device` with a device-memory budget in
+ * bytes for scenes, caches, random-phase tables, fields and path state
+ * (0 = 90% of the device's free memory). Spawns the scheduler thread. */
+hpt_status hpt_create(int device, uint64_t hbm_budget_bytes, hpt_ctx **out);
+/* Cancel queued work, wait for running batches, free everything. */
+void hpt_destroy(hpt_ctx *ctx);
+const char *hpt_last_error(void);
+const char *hpt_version(void);
+
+/* ---------------------------------------------------------------- scenes
+ * A scene is triangles (world space, any winding: the geometric normal is
+ * (v1-v0) x (v2-v0)) and analytic spheres, each with a material index.
+ * Primitive ids are global: spheres [0, n_sph), triangles [n_sph, n_sph +
+ * n_tri). Light sources are EMITTER triangles; they emit radiance `emit`
+ * on the side of their geometric normal and are black otherwise. */
+enum { HPT_LAMBERT = 0, HPT_GGX = 1, HPT_MIRROR = 2, HPT_DIELECTRIC = 3, HPT_EMITTER = 4 };
+
+typedef struct {
+  const float *tri;        /* host, [n_tri][3][3] vertex positions */
+  uint32_t n_tri;
+  const uint32_t *tri_mat; /* host, [n_tri] material index */
+  const float *sph;        /* host, [n_sph][4] centre xyz, radius > 0 */
+  uint32_t n_sph;
+  const uint32_t *sph_mat; /* host, [n_sph] */
+  uint32_t n_mat;
+  const uint32_t *mat_type;  /* host, [n_mat] HPT_LAMBERT .. HPT_EMITTER */
+  const float *mat_rgb;      /* host, [n_mat][3] Lambert albedo / GGX Schlick F0 */
+  const float *mat_rough;    /* host, [n_mat] GGX alpha in (0, 1] */
+  const float *mat_ior;      /* host, [n_mat] dielectric index > 1 */
+  const float *mat_emit;     /* host, [n_mat][3] emitter radiance >= 0 */
+  const float *env;          /* host, [3] radiance of rays leaving the scene */
+} hpt_scene_desc;
+
+typedef struct {
+  uint32_t n_nodes, n_prims, max_depth, reserved;
+  uint64_t device_bytes;
+  double build_ms;
+  double bounds[6]; /* lo xyz, hi xyz of all primitives */
+} hpt_scene_info;
+
+/* Validate (finite coordinates, indices in range, positive radii, known
+ * material types), build the BVH on the host and copy the scene to the
+ * device. Errors: EINVAL, EBUDGET, ENOMEM, EDEVICE. */
+hpt_status hpt_scene_upload(hpt_ctx *ctx, const hpt_scene_desc *desc, uint64_t *scene_out);
+hpt_status hpt_scene_info_get(hpt_ctx *ctx, uint64_t scene, hpt_scene_info *out);
+/* EBUSY while a job that uses the scene is queued or running. */
+hpt_status hpt_scene_release(hpt_ctx *ctx, uint64_t scene);
+
+/* ---------------------------------------------------------------- radiance cache
+ * Ambient radiance cache ("texture baking", Sec. 4.2; the paper defers its
+ * layout to a supplement). Grid: the scene bounds inflated by 1e-3 of their
+ * largest extent, res^3 cells; bins: a bins x bins octahedral map of
+ * direction. Entry (comp, cell, bin) = mean over spb paths of the radiance
+ * seen from a point uniform in the cell along a direction uniform in the
+ * bin's octahedral square, traced without the cache up to max_bounces
+ * interactions; stored as binary16 (round to nearest even), layout
+ * [comp 0..2][cell][bin], cell = (iz*res + iy)*res + ix, bin = bv*bins + bu.
+ * A job with use_cache != 0 ends its incoherent tail at the first non-delta
+ * lobe whose tail depth >= cache_depth with throughput * entry. */
+typedef struct {
+  uint32_t res, bins, spb, max_bounces;
+  uint64_t seed;
+} hpt_cache_desc;
+
+/* Build (or rebuild) the cache of `scene` on the device. Blocks until done. */
+hpt_status hpt_cache_build(hpt_ctx *ctx, uint64_t scene, const hpt_cache_desc *desc);
+/* Copy the cache to host memory: n = 3 * res^3 * bins^2 binary16 values. */
+hpt_status hpt_cache_export(hpt_ctx *ctx, uint64_t scene, uint16_t *host_out, size_t n);
+
+/* ---------------------------------------------------------------- jobs */
+enum { HPT_PHASE_FP64 = 0, HPT_PHASE_SPLIT = 1, HPT_PHASE_FP32 = 2 };
+
+typedef struct {
+  uint32_t width, height;   /* SLM resolution */
+  double pitch;             /* SLM pixel pitch d (m); cone: sin(theta) <= lambda/(2d) */
+  uint32_t n_ch;            /* 1..3 wavelengths, traced independently */
+  double lambda[3];         /* m */
+  uint32_t comp[3];         /* colour component (0..2) of materials used by channel c */
+  uint32_t spp;             /* samples per pixel (normalisation 1/spp) */
+  uint32_t max_bounces;     /* surface interactions per path, prefix + tail (1..31) */
+  uint32_t T;               /* time-multiplexed frames, 1..64 (Eq. 5) */
+  uint64_t seed;            /* path random numbers */
+  uint64_t grf_seed;        /* spectral phases of the random fields (Eq. 4) */
+  uint32_t grf_w, grf_h;    /* periodic random-field grid (texels at pitch d), >= W, H */
+  uint32_t phase_mode;      /* HPT_PHASE_FP64 / SPLIT / FP32: precision of the OPL/phase chain */
+  uint32_t random_phase;    /* 1: phi_m from the random fields; 0: phi = 0 */
+  uint32_t use_cache, cache_depth; /* radiance cache (built beforehand) */
+  uint32_t crop[4];         /* x0, y0, w, h of the rendered window; w = h = 0: whole SLM */
+  uint32_t spp_begin, spp_end;     /* sample range of this job ([0,0): all); resumable chunks */
+  double holo_from_world[12];      /* Eq. 3: affine T, row-major 3x4, x_holo = T x_world */
+  uint32_t debug;           /* bit 0: per-path records (<= 2^22 paths); bit 1: per-path
+                               per-frame contributions; bit 2: per-pixel signature sums */
+} hpt_job_desc;
+
+typedef struct {
+  uint64_t paths;            /* (channel, pixel, sample) paths traced */
+  uint64_t rays;             /* traversal queries */
+  uint64_t batches;
+  double queued_ms, run_ms;  /* submit -> first batch, first batch -> done */
+  double trace_gpu_ms;       /* device time of this job's batches (shared batches split by paths) */
+} hpt_job_stats;
+
+/* Per-path debug record, layout [channel][crop_h][crop_w][sample]. */
+typedef struct {
+  uint64_t sig;              /* FNV-1a over the path's events */
+  int32_t kind, bP, first_gid, n_hits;
+  double ell, r, A, W, amp, qx, qy, rev;
+} hpt_path_record;
+
+/* Queue a job. d_field: device buffer of n_ch*T*crop_h*crop_w complex64
+ * (nullable: the library allocates it). Validation (EINVAL): sizes zero,
+ * T not in [1,64], n_ch not in [1,3], lambda <= 0, lambda/(2 pitch) >= 1,
+ * grf smaller than the SLM, crop outside the SLM, spp range empty,
+ * max_bounces not in [1,31], non-finite or singular T, use_cache without a
+ * built cache. EBUDGET if the job can never fit the budget; otherwise it
+ * waits in the queue until memory frees up. */
+hpt_status hpt_trace_submit(hpt_ctx *ctx, uint64_t scene, const hpt_job_desc *job,
+                            void *d_field, uint64_t *job_out);
+/* Wait for completion; timeout_ms < 0 waits forever. */
+hpt_status hpt_job_wait(hpt_ctx *ctx, uint64_t job, int64_t timeout_ms);
+hpt_status hpt_job_stats_get(hpt_ctx *ctx, uint64_t job, hpt_job_stats *out);
+/* Copy the finished field to host memory (n_floats = 2 * elements). */
+hpt_status hpt_field_read(hpt_ctx *ctx, uint64_t job, float *host_out, size_t n_floats);
+/* Device pointer of the field (library-allocated or the caller's). */
+hpt_status hpt_field_device_ptr(hpt_ctx *ctx, uint64_t job, void **d_out);
+/* Copy per-path records (debug bit 0) / per-frame contributions (bit 1,
+ * complex64 [channel][crop_h][crop_w][sample][T]) / per-pixel signature sums
+ * (bit 2, uint64 [channel][crop_h][crop_w]) to host memory. */
+hpt_status hpt_paths_read(hpt_ctx *ctx, uint64_t job, hpt_path_record *host_out, size_t n);
+hpt_status hpt_contrib_read(hpt_ctx *ctx, uint64_t job, float *host_out, size_t n_floats);
+hpt_status hpt_sigsum_read(hpt_ctx *ctx, uint64_t job, uint64_t *host_out, size_t n);
+/* Remove a queued job or stop a running one at its next batch boundary. */
+hpt_status hpt_job_cancel(hpt_ctx *ctx, uint64_t job);
+/* Free the job's library-owned memory (its field too, unless caller-owned). */
+hpt_status hpt_job_release(hpt_ctx *ctx, uint64_t job);
+
+/* Random-phase table of Eq. 4 as the jobs use it: complex64 [grf_h][grf_w][T],
+ * r_t(x, y) = sum over DFT bins with f_x^2 + f_y^2 <= (1/2d)^2 of
+ * exp(i xi_t) exp(2 pi i (f_x x + f_y y)) / sqrt(#bins). Builds it (resident,
+ * shared by jobs with the same grid, T and seed) and copies it out. */
+hpt_status hpt_grf_read(hpt_ctx *ctx, uint32_t grf_w, uint32_t grf_h, uint32_t T,
+                        uint64_t grf_seed, float *host_out, size_t n_floats);
+
+/* Context-wide counters: bytes in use against the budget, batches run. */
+typedef struct {
+  uint64_t budget_bytes, used_bytes, batch_capacity_paths;
+  uint64_t batches, jobs_done, jobs_queued, jobs_running;
+} hpt_ctx_stats;
+hpt_status hpt_ctx_stats_get(hpt_ctx *ctx, hpt_ctx_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPT_H */

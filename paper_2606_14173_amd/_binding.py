@@ -1,0 +1,308 @@
+"""ctypes binding of libhpt.so (include/hpt.h): argument marshalling only.
+
+Every step of the wave path tracer runs in the library's gfx950 kernels.
+There is no CPU fallback: if the library or a gfx950 device is missing,
+loading or creating a context raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhpt.so")
+
+STATUS = {0: "HPT_OK", -1: "HPT_EINVAL", -2: "HPT_ENOMEM", -3: "HPT_EBUDGET", -4: "HPT_ENOTFOUND",
+          -5: "HPT_EBUSY", -6: "HPT_EDEVICE", -7: "HPT_ETIMEOUT", -8: "HPT_ECANCELED",
+          -9: "HPT_ENODEV"}
+PHASE_FP64, PHASE_SPLIT, PHASE_FP32 = 0, 1, 2
+
+
+class HptError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [("tri", C.c_void_p), ("n_tri", C.c_uint32), ("tri_mat", C.c_void_p),
+                ("sph", C.c_void_p), ("n_sph", C.c_uint32), ("sph_mat", C.c_void_p),
+                ("n_mat", C.c_uint32), ("mat_type", C.c_void_p), ("mat_rgb", C.c_void_p),
+                ("mat_rough", C.c_void_p), ("mat_ior", C.c_void_p), ("mat_emit", C.c_void_p),
+                ("env", C.c_void_p)]
+
+
+class SceneInfo(C.Structure):
+    _fields_ = [("n_nodes", C.c_uint32), ("n_prims", C.c_uint32), ("max_depth", C.c_uint32),
+                ("reserved", C.c_uint32), ("device_bytes", C.c_uint64), ("build_ms", C.c_double),
+                ("bounds", C.c_double * 6)]
+
+
+class CacheDesc(C.Structure):
+    _fields_ = [("res", C.c_uint32), ("bins", C.c_uint32), ("spb", C.c_uint32),
+                ("max_bounces", C.c_uint32), ("seed", C.c_uint64)]
+
+
+class JobDesc(C.Structure):
+    _fields_ = [("width", C.c_uint32), ("height", C.c_uint32), ("pitch", C.c_double),
+                ("n_ch", C.c_uint32), ("lam", C.c_double * 3), ("comp", C.c_uint32 * 3),
+                ("spp", C.c_uint32), ("max_bounces", C.c_uint32), ("T", C.c_uint32),
+                ("seed", C.c_uint64), ("grf_seed", C.c_uint64),
+                ("grf_w", C.c_uint32), ("grf_h", C.c_uint32),
+                ("phase_mode", C.c_uint32), ("random_phase", C.c_uint32),
+                ("use_cache", C.c_uint32), ("cache_depth", C.c_uint32),
+                ("crop", C.c_uint32 * 4), ("spp_begin", C.c_uint32), ("spp_end", C.c_uint32),
+                ("holo_from_world", C.c_double * 12), ("debug", C.c_uint32)]
+
+
+class JobStats(C.Structure):
+    _fields_ = [("paths", C.c_uint64), ("rays", C.c_uint64), ("batches", C.c_uint64),
+                ("queued_ms", C.c_double), ("run_ms", C.c_double), ("trace_gpu_ms", C.c_double)]
+
+
+class CtxStats(C.Structure):
+    _fields_ = [("budget_bytes", C.c_uint64), ("used_bytes", C.c_uint64),
+                ("batch_capacity_paths", C.c_uint64), ("batches", C.c_uint64),
+                ("jobs_done", C.c_uint64), ("jobs_queued", C.c_uint64),
+                ("jobs_running", C.c_uint64)]
+
+
+PATH_RECORD = np.dtype([("sig", np.uint64), ("kind", np.int32), ("bP", np.int32),
+                        ("first_gid", np.int32), ("n_hits", np.int32),
+                        ("ell", np.float64), ("r", np.float64), ("A", np.float64),
+                        ("W", np.float64), ("amp", np.float64), ("qx", np.float64),
+                        ("qy", np.float64), ("rev", np.float64)])
+
+# Every entry point declared in include/hpt.h, with its argument types.
+_vp, _u32, _u64, _i64, _sz = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int64, C.c_size_t
+SIGNATURES = {
+    "hpt_create": (C.c_int, [C.c_int, _u64, _vp]),
+    "hpt_destroy": (None, [_vp]),
+    "hpt_last_error": (C.c_char_p, []),
+    "hpt_version": (C.c_char_p, []),
+    "hpt_scene_upload": (C.c_int, [_vp, C.POINTER(SceneDesc), C.POINTER(_u64)]),
+    "hpt_scene_info_get": (C.c_int, [_vp, _u64, C.POINTER(SceneInfo)]),
+    "hpt_scene_release": (C.c_int, [_vp, _u64]),
+    "hpt_cache_build": (C.c_int, [_vp, _u64, C.POINTER(CacheDesc)]),
+    "hpt_cache_export": (C.c_int, [_vp, _u64, _vp, _sz]),
+    "hpt_trace_submit": (C.c_int, [_vp, _u64, C.POINTER(JobDesc), _vp, C.POINTER(_u64)]),
+    "hpt_job_wait": (C.c_int, [_vp, _u64, _i64]),
+    "hpt_job_stats_get": (C.c_int, [_vp, _u64, C.POINTER(JobStats)]),
+    "hpt_field_read": (C.c_int, [_vp, _u64, _vp, _sz]),
+    "hpt_field_device_ptr": (C.c_int, [_vp, _u64, C.POINTER(_vp)]),
+    "hpt_paths_read": (C.c_int, [_vp, _u64, _vp, _sz]),
+    "hpt_contrib_read": (C.c_int, [_vp, _u64, _vp, _sz]),
+    "hpt_sigsum_read": (C.c_int, [_vp, _u64, _vp, _sz]),
+    "hpt_job_cancel": (C.c_int, [_vp, _u64]),
+    "hpt_job_release": (C.c_int, [_vp, _u64]),
+    "hpt_grf_read": (C.c_int, [_vp, _u32, _u32, _u32, _u64, _vp, _sz]),
+    "hpt_ctx_stats_get": (C.c_int, [_vp, C.POINTER(CtxStats)]),
+}
+
+_LIB = None
+
+
+def load():
+    """Load libhpt.so (built by paper_2606_14173_amd.build); raise if absent."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libhpt.so is not built (run __graft_entry__.build()); "
+                              "the wave path tracer has no CPU fallback")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def _check(status):
+    if status != 0:
+        msg = load().hpt_last_error()
+        raise HptError(status, msg.decode() if msg else "")
+
+
+def _arr(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def job_desc(job):
+    """hpt_job_desc from a job dict (see scenes.jobs for the keys)."""
+    d = JobDesc()
+    d.width, d.height, d.pitch = job["width"], job["height"], job["pitch"]
+    lams = list(job["lambdas"])
+    d.n_ch = len(lams)
+    for i, l in enumerate(lams):
+        d.lam[i] = l
+        d.comp[i] = job["comps"][i]
+    d.spp, d.max_bounces, d.T = job["spp"], job["max_bounces"], job["T"]
+    d.seed, d.grf_seed = job["seed"], job["grf_seed"]
+    d.grf_w, d.grf_h = job["grf_w"], job["grf_h"]
+    d.phase_mode, d.random_phase = job["phase_mode"], job["random_phase"]
+    d.use_cache, d.cache_depth = job["use_cache"], job["cache_depth"]
+    for i in range(4):
+        d.crop[i] = job["crop"][i]
+    d.spp_begin, d.spp_end = job["spp_begin"], job["spp_end"]
+    for i in range(12):
+        d.holo_from_world[i] = job["holo_from_world"][i]
+    d.debug = job.get("debug", 0)
+    return d
+
+
+def crop_dims(job):
+    x0, y0, w, h = job["crop"]
+    return (job["width"], job["height"]) if (w == 0 or h == 0) else (w, h)
+
+
+def n_samples(job):
+    sb, se = job["spp_begin"], job["spp_end"]
+    return (se - sb) if (sb or se) else job["spp"]
+
+
+class Context:
+    """One hpt_ctx on a HIP device (one process per GPU)."""
+
+    def __init__(self, device=0, budget_bytes=0):
+        self.lib = load()
+        h = C.c_void_p()
+        _check(self.lib.hpt_create(device, budget_bytes, C.byref(h)))
+        self.h = h
+        self._scene_keep = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.hpt_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # scenes
+    def upload_scene(self, sc):
+        keep = [_arr(sc["tri"], np.float32), _arr(sc["tri_mat"], np.uint32),
+                _arr(sc["sph"], np.float32), _arr(sc["sph_mat"], np.uint32),
+                _arr(sc["mat_type"], np.uint32), _arr(sc["mat_rgb"], np.float32),
+                _arr(sc["mat_rough"], np.float32), _arr(sc["mat_ior"], np.float32),
+                _arr(sc["mat_emit"], np.float32), _arr(sc["env"], np.float32)]
+        d = SceneDesc(keep[0].ctypes.data, len(keep[1]), keep[1].ctypes.data,
+                      keep[2].ctypes.data, len(keep[3]), keep[3].ctypes.data,
+                      len(keep[4]), keep[4].ctypes.data, keep[5].ctypes.data,
+                      keep[6].ctypes.data, keep[7].ctypes.data, keep[8].ctypes.data,
+                      keep[9].ctypes.data)
+        sid = C.c_uint64()
+        _check(self.lib.hpt_scene_upload(self.h, C.byref(d), C.byref(sid)))
+        return sid.value
+
+    def scene_info(self, sid):
+        i = SceneInfo()
+        _check(self.lib.hpt_scene_info_get(self.h, sid, C.byref(i)))
+        return dict(n_nodes=i.n_nodes, n_prims=i.n_prims, max_depth=i.max_depth,
+                    device_bytes=i.device_bytes, build_ms=i.build_ms, bounds=list(i.bounds))
+
+    def release_scene(self, sid):
+        _check(self.lib.hpt_scene_release(self.h, sid))
+
+    def build_cache(self, sid, res=64, bins=8, spb=4, max_bounces=6, seed=7):
+        d = CacheDesc(res, bins, spb, max_bounces, seed)
+        _check(self.lib.hpt_cache_build(self.h, sid, C.byref(d)))
+
+    def export_cache(self, sid, res, bins):
+        out = np.zeros((3, res ** 3, bins * bins), dtype=np.uint16)
+        _check(self.lib.hpt_cache_export(self.h, sid, out.ctypes.data, out.size))
+        return out
+
+    # jobs
+    def submit(self, sid, job, field=None):
+        """Queue a job; `field` may be a device pointer (int) or a torch
+        tensor on the context's device with n_ch*T*h*w complex64 elements."""
+        d = job_desc(job)
+        ptr = None
+        if field is not None:
+            ptr = field if isinstance(field, int) else field.data_ptr()
+        jid = C.c_uint64()
+        _check(self.lib.hpt_trace_submit(self.h, sid, C.byref(d), ptr, C.byref(jid)))
+        return jid.value
+
+    def wait(self, jid, timeout_ms=-1):
+        _check(self.lib.hpt_job_wait(self.h, jid, timeout_ms))
+
+    def stats(self, jid):
+        s = JobStats()
+        _check(self.lib.hpt_job_stats_get(self.h, jid, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in JobStats._fields_}
+
+    def ctx_stats(self):
+        s = CtxStats()
+        _check(self.lib.hpt_ctx_stats_get(self.h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in CtxStats._fields_}
+
+    def read_field(self, jid, job):
+        w, h = crop_dims(job)
+        out = np.zeros((len(job["lambdas"]), job["T"], h, w), dtype=np.complex64)
+        _check(self.lib.hpt_field_read(self.h, jid, out.ctypes.data, out.size * 2))
+        return out
+
+    def read_paths(self, jid, job):
+        w, h = crop_dims(job)
+        out = np.zeros((len(job["lambdas"]), h, w, n_samples(job)), dtype=PATH_RECORD)
+        _check(self.lib.hpt_paths_read(self.h, jid, out.ctypes.data, out.size))
+        return out
+
+    def read_contrib(self, jid, job):
+        w, h = crop_dims(job)
+        out = np.zeros((len(job["lambdas"]), h, w, n_samples(job), job["T"]), dtype=np.complex64)
+        _check(self.lib.hpt_contrib_read(self.h, jid, out.ctypes.data, out.size * 2))
+        return out
+
+    def read_sigsum(self, jid, job):
+        w, h = crop_dims(job)
+        out = np.zeros((len(job["lambdas"]), h, w), dtype=np.uint64)
+        _check(self.lib.hpt_sigsum_read(self.h, jid, out.ctypes.data, out.size))
+        return out
+
+    def field_ptr(self, jid):
+        p = C.c_void_p()
+        _check(self.lib.hpt_field_device_ptr(self.h, jid, C.byref(p)))
+        return p.value
+
+    def cancel(self, jid):
+        _check(self.lib.hpt_job_cancel(self.h, jid))
+
+    def release_job(self, jid):
+        _check(self.lib.hpt_job_release(self.h, jid))
+
+    def grf(self, gw, gh, T, seed):
+        out = np.zeros((gh, gw, T), dtype=np.complex64)
+        _check(self.lib.hpt_grf_read(self.h, gw, gh, T, seed, out.ctypes.data, out.size * 2))
+        return out
+
+    def trace(self, sid, job, records=False, contrib=False, sigsum=False):
+        """Submit, wait and read back: field [n_ch, T, h, w] complex64 and the
+        optional debug outputs."""
+        j = dict(job)
+        j["debug"] = (1 if records else 0) | (2 if contrib else 0) | (4 if sigsum else 0)
+        jid = self.submit(sid, j)
+        try:
+            self.wait(jid)
+            out = [self.read_field(jid, j)]
+            if records:
+                out.append(self.read_paths(jid, j))
+            if contrib:
+                out.append(self.read_contrib(jid, j))
+            if sigsum:
+                out.append(self.read_sigsum(jid, j))
+        finally:
+            self.release_job(jid)
+        return out[0] if len(out) == 1 else tuple(out)

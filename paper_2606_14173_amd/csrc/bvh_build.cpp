@@ -1,0 +1,227 @@
+// Host BVH builder: binned SAH over primitive centroids, leaves of at most 4
+// primitives, flattened into BVH2 nodes of 64 bytes that hold both child
+// boxes (one node fetch tests two boxes) and primitive records in leaf order.
+//
+// Node layout (4 x float4):
+//   a = (c0.lo.x, c0.hi.x, c0.lo.y, c0.hi.y)
+//   b = (c1.lo.x, c1.hi.x, c1.lo.y, c1.hi.y)
+//   c = (c0.lo.z, c0.hi.z, c1.lo.z, c1.hi.z)
+//   d = (link0, link1, 0, 0)   link >= 0: inner node; link < 0: leaf ~(first << 3 | count-1)
+// Primitive record (3 x float4):
+//   triangle: (v0, gid bits) (v1, 0) (v2, 0)
+//   sphere:   (centre, gid bits) (radius, 0, 0, 1) (0)
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "bvh_build.hpp"
+
+namespace hpt {
+namespace {
+
+struct AABB {
+  float lo[3], hi[3];
+  void reset() {
+    for (int a = 0; a < 3; ++a) { lo[a] = INFINITY; hi[a] = -INFINITY; }
+  }
+  void grow(const AABB &b) {
+    for (int a = 0; a < 3; ++a) { lo[a] = std::min(lo[a], b.lo[a]); hi[a] = std::max(hi[a], b.hi[a]); }
+  }
+  void grow(const float *p) {
+    for (int a = 0; a < 3; ++a) { lo[a] = std::min(lo[a], p[a]); hi[a] = std::max(hi[a], p[a]); }
+  }
+  float area() const {
+    float dx = hi[0] - lo[0], dy = hi[1] - lo[1], dz = hi[2] - lo[2];
+    if (dx < 0 || dy < 0 || dz < 0) return 0.f;
+    return 2.f * (dx * dy + dy * dz + dz * dx);
+  }
+};
+
+struct Builder {
+  const float *tri;
+  const float *sph;
+  uint32_t n_sph, n_tri;
+  std::vector<AABB> box;        // per global id
+  std::vector<float> cen;       // 3 per global id
+  std::vector<uint32_t> ids;    // permutation being partitioned
+  std::vector<float> nodes;     // 16 floats per node
+  uint32_t max_depth = 0;
+
+  static constexpr int kBins = 16;
+  static constexpr int kLeaf = 4;
+
+  int32_t leaf_link(uint32_t first, uint32_t count) {
+    return ~(int32_t)((first << 3) | (count - 1));
+  }
+
+  // Conservative float box: grown by a relative 2^-20 so FP32 slab tests
+  // never cull a true hit because of rounding.
+  static void pad(AABB &b) {
+    for (int a = 0; a < 3; ++a) {
+      float e = 1e-12f + std::max(std::fabs(b.lo[a]), std::fabs(b.hi[a])) * 9.5367431640625e-07f;
+      b.lo[a] -= e; b.hi[a] += e;
+    }
+  }
+
+  AABB range_box(uint32_t first, uint32_t count) {
+    AABB b; b.reset();
+    for (uint32_t i = 0; i < count; ++i) b.grow(box[ids[first + i]]);
+    return b;
+  }
+
+  // Choose a split of ids[first, first+count); returns the number in the left part.
+  uint32_t split(uint32_t first, uint32_t count, uint32_t depth) {
+    AABB cb; cb.reset();
+    for (uint32_t i = 0; i < count; ++i) cb.grow(&cen[3 * ids[first + i]]);
+    int axis = 0;
+    float ext[3] = {cb.hi[0] - cb.lo[0], cb.hi[1] - cb.lo[1], cb.hi[2] - cb.lo[2]};
+    if (ext[1] > ext[axis]) axis = 1;
+    if (ext[2] > ext[axis]) axis = 2;
+    auto *beg = ids.data() + first, *end = ids.data() + first + count;
+    auto median = [&]() {
+      uint32_t mid = count / 2;
+      std::nth_element(beg, beg + mid, end, [&](uint32_t a, uint32_t b) {
+        float ca = cen[3 * a + axis], cbv = cen[3 * b + axis];
+        return ca < cbv || (ca == cbv && a < b);
+      });
+      return mid;
+    };
+    if (ext[axis] <= 0.f || depth >= 40) return median();
+    AABB bb[kBins];
+    uint32_t bc[kBins] = {0};
+    for (auto &b : bb) b.reset();
+    float scale = kBins / ext[axis];
+    auto bin_of = [&](uint32_t id) {
+      int k = (int)((cen[3 * id + axis] - cb.lo[axis]) * scale);
+      return std::min(std::max(k, 0), kBins - 1);
+    };
+    for (uint32_t i = 0; i < count; ++i) {
+      uint32_t id = ids[first + i];
+      int k = bin_of(id);
+      bb[k].grow(box[id]);
+      bc[k]++;
+    }
+    float left_area[kBins], right_area[kBins];
+    uint32_t left_n[kBins], right_n[kBins];
+    AABB acc; acc.reset();
+    uint32_t n = 0;
+    for (int k = 0; k < kBins; ++k) {
+      acc.grow(bb[k]); n += bc[k];
+      left_area[k] = acc.area(); left_n[k] = n;
+    }
+    acc.reset(); n = 0;
+    for (int k = kBins - 1; k >= 0; --k) {
+      acc.grow(bb[k]); n += bc[k];
+      right_area[k] = acc.area(); right_n[k] = n;
+    }
+    float best = INFINITY;
+    int best_k = -1;
+    for (int k = 0; k < kBins - 1; ++k) {
+      if (left_n[k] == 0 || right_n[k + 1] == 0) continue;
+      float c = left_area[k] * left_n[k] + right_area[k + 1] * right_n[k + 1];
+      if (c < best) { best = c; best_k = k; }
+    }
+    if (best_k < 0) return median();
+    auto *m = std::partition(beg, end, [&](uint32_t id) { return bin_of(id) <= best_k; });
+    uint32_t nl = (uint32_t)(m - beg);
+    if (nl == 0 || nl == count) return median();
+    return nl;
+  }
+
+  // Emit the link to the subtree over ids[first, first+count).
+  int32_t build(uint32_t first, uint32_t count, uint32_t depth) {
+    max_depth = std::max(max_depth, depth);
+    if (count <= (uint32_t)kLeaf) return leaf_link(first, count);
+    uint32_t nl = split(first, count, depth);
+    uint32_t node = (uint32_t)(nodes.size() / 16);
+    nodes.resize(nodes.size() + 16, 0.f);
+    AABB l = range_box(first, nl), r = range_box(first + nl, count - nl);
+    pad(l); pad(r);
+    int32_t c0 = build(first, nl, depth + 1);
+    int32_t c1 = build(first + nl, count - nl, depth + 1);
+    write_node(node, l, r, c0, c1);
+    return (int32_t)node;
+  }
+
+  void write_node(uint32_t node, const AABB &l, const AABB &r, int32_t c0, int32_t c1) {
+    float *n = &nodes[16 * node];
+    n[0] = l.lo[0]; n[1] = l.hi[0]; n[2] = l.lo[1]; n[3] = l.hi[1];
+    n[4] = r.lo[0]; n[5] = r.hi[0]; n[6] = r.lo[1]; n[7] = r.hi[1];
+    n[8] = l.lo[2]; n[9] = l.hi[2]; n[10] = r.lo[2]; n[11] = r.hi[2];
+    std::memcpy(&n[12], &c0, 4);
+    std::memcpy(&n[13], &c1, 4);
+    n[14] = 0.f; n[15] = 0.f;
+  }
+};
+
+}  // namespace
+
+bool build_bvh(const float *tri, uint32_t n_tri, const float *sph, uint32_t n_sph, BvhResult &out) {
+  auto t0 = std::chrono::steady_clock::now();
+  Builder B;
+  B.tri = tri; B.sph = sph; B.n_sph = n_sph; B.n_tri = n_tri;
+  uint32_t n = n_sph + n_tri;
+  if (n == 0 || n >= (1u << 27)) return false;
+  B.box.resize(n);
+  B.cen.resize(3 * (size_t)n);
+  AABB all; all.reset();
+  for (uint32_t g = 0; g < n; ++g) {
+    AABB b; b.reset();
+    if (g < n_sph) {
+      const float *s = sph + 4 * g;
+      for (int a = 0; a < 3; ++a) { b.lo[a] = s[a] - s[3]; b.hi[a] = s[a] + s[3]; }
+    } else {
+      const float *t = tri + 9 * (size_t)(g - n_sph);
+      b.grow(t); b.grow(t + 3); b.grow(t + 6);
+    }
+    B.box[g] = b;
+    for (int a = 0; a < 3; ++a) B.cen[3 * g + a] = 0.5f * (b.lo[a] + b.hi[a]);
+    all.grow(b);
+  }
+  B.ids.resize(n);
+  for (uint32_t g = 0; g < n; ++g) B.ids[g] = g;
+  B.nodes.reserve(16 * (size_t)n);
+  if (n <= (uint32_t)Builder::kLeaf) {
+    // a root that holds one leaf and one empty child (inverted box)
+    B.nodes.resize(16, 0.f);
+    AABB l = B.range_box(0, n), e;
+    Builder::pad(l);
+    for (int a = 0; a < 3; ++a) { e.lo[a] = INFINITY; e.hi[a] = -INFINITY; }
+    B.write_node(0, l, e, B.leaf_link(0, n), B.leaf_link(0, n));
+  } else {
+    int32_t root = B.build(0, n, 0);
+    (void)root;  // the first node emitted is the root (index 0)
+  }
+  out.nodes.swap(B.nodes);
+  out.prims.assign(12 * (size_t)n, 0.f);
+  for (uint32_t i = 0; i < n; ++i) {
+    uint32_t g = B.ids[i];
+    float *p = &out.prims[12 * (size_t)i];
+    uint32_t gid = g;
+    if (g < n_sph) {
+      const float *s = sph + 4 * g;
+      p[0] = s[0]; p[1] = s[1]; p[2] = s[2];
+      std::memcpy(&p[3], &gid, 4);
+      p[4] = s[3]; p[5] = 0.f; p[6] = 0.f;
+      uint32_t one = 1;
+      std::memcpy(&p[7], &one, 4);
+    } else {
+      const float *t = tri + 9 * (size_t)(g - n_sph);
+      p[0] = t[0]; p[1] = t[1]; p[2] = t[2];
+      std::memcpy(&p[3], &gid, 4);
+      p[4] = t[3]; p[5] = t[4]; p[6] = t[5]; p[7] = 0.f;
+      p[8] = t[6]; p[9] = t[7]; p[10] = t[8]; p[11] = 0.f;
+    }
+  }
+  out.n_nodes = (uint32_t)(out.nodes.size() / 16);
+  out.max_depth = B.max_depth + 1;
+  for (int a = 0; a < 3; ++a) { out.bounds[a] = all.lo[a]; out.bounds[3 + a] = all.hi[a]; }
+  out.build_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return out.max_depth < kBvhDepthMax;
+}
+
+}  // namespace hpt

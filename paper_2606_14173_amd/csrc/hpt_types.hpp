@@ -1,0 +1,109 @@
+// Plain data shared by the host runtime and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/hpt.h"
+
+namespace hpt {
+
+constexpr int kMaxT = 64;
+constexpr int kStackMax = 64;        // BVH depth bound enforced by the builder
+constexpr float kTmin = 1e-7f;       // self-intersection guard (metres)
+constexpr double kTminD = 1e-7;
+
+enum Stage : uint32_t { STAGE_PREFIX = 0, STAGE_TAIL = 1 };
+enum UnitKind : uint32_t { UNIT_HOLO = 0, UNIT_CACHE = 1 };
+
+// Path events hashed into the signature (same codes as the FP64 reference).
+enum : uint32_t { EV_MIRROR = 1, EV_DIEL_REFL = 2, EV_DIEL_REFR = 3, EV_LAMBERT = 4, EV_GGX = 5,
+                  EV_ABSORB = 6, EV_EMIT = 7, EV_IMAGE_POINT = 8 };
+enum : int32_t { K_NONE = 0, K_ESCAPE_PREFIX = 1, K_MAXB_PREFIX = 2, K_EMITTER = 3, K_ENV = 4,
+                 K_MAXB_TAIL = 5, K_CACHE = 6, K_ABSORBED = 7 };
+
+struct MaterialDev {
+  uint32_t type;
+  float rgb[3];
+  float rough, ior;
+  float emit[3];
+  float pad;
+};
+
+// Device view of one resident scene.
+struct SceneDev {
+  const float4 *nodes;       // BVH2: 4 x float4 per node (two child boxes + links)
+  const float4 *prims;       // 3 x float4 per primitive in leaf order
+  const float *tri_v;        // [n_tri][9] original float32 vertices
+  const double4 *tri_plane;  // [n_tri] unit normal (v1-v0)x(v2-v0) and offset n.v0, in FP64
+  const float *sph;          // [n_sph][4]
+  const uint32_t *prim_mat;  // [n_sph + n_tri] by global id
+  const MaterialDev *mats;
+  uint32_t n_sph, n_tri, n_mat, n_nodes;
+  float env[3];
+  uint32_t pad0;
+  // radiance cache
+  const uint16_t *cache;     // [3][res^3][bins^2] binary16, or null
+  uint32_t cache_res, cache_bins;
+  float cache_lo[3], cache_scale[3];   // cell index = floor((x - lo) * scale)
+  double cache_lo_d[3], cache_hi_d[3];
+};
+
+// Device view of a job (or of a cache build).
+struct JobDev {
+  uint32_t width, height;
+  double pitch;
+  uint32_t crop_x0, crop_y0, crop_w, crop_h;
+  uint32_t n_ch;
+  uint32_t comp[3];
+  double lambda[3], inv_lambda[3], s_cone[3];
+  float lambda_f[3], inv_lambda_f[3], s_cone_f[3];
+  uint32_t spp, max_bounces, T, phase_mode, random_phase, use_cache, cache_depth, debug;
+  uint64_t seed;
+  double Tm[12], Ti[12];
+  uint32_t identity_T;
+  uint32_t grf_w, grf_h;
+  const float2 *grf;         // [grf_h][grf_w][T]
+  float2 *field;             // [n_ch][T][crop_h][crop_w]
+  hpt_path_record *rec;      // debug bit 0
+  float2 *contrib;           // debug bit 1: [n_ch][crop_h][crop_w][n_s][T]
+  unsigned long long *sigsum;// debug bit 2: [n_ch][crop_h][crop_w]
+  uint32_t spp_lo, n_s;      // sample range of the job
+  const SceneDev *scene;
+  // cache build
+  uint16_t *cache_out;       // [3][res^3][bins^2]
+  uint32_t cache_res, cache_bins, cache_spb, pad1;
+};
+
+// A contiguous block of paths of one job: pixels [p_lo, p_lo + p_n) of the
+// crop (row-major) x samples [s_lo, s_lo + s_n) of one channel; or cache
+// entries x paths per entry of one colour component.
+struct UnitDev {
+  uint32_t kind, ch;
+  uint32_t p_lo, p_n, s_lo, s_n;
+  uint32_t slot_base, acc_base;
+  const JobDev *job;
+};
+
+// Path state, records and queues of one batch (structure of arrays).
+struct BatchDev {
+  const UnitDev *units;
+  uint32_t n_units, n_paths, n_acc, lds_unused;
+  uint32_t *s_meta;          // stage | b << 1 | bP << 7 | glass << 13
+  uint32_t *s_unit, *s_ka, *s_kb;
+  double *s_ox, *s_oy, *s_oz, *s_dx, *s_dy, *s_dz, *s_ell, *s_al, *s_be;
+  float *s_bpre, *s_beta, *s_L, *s_W;
+  unsigned long long *s_sig;
+  int32_t *s_first;
+  // per-path results consumed by the accumulation
+  float *r_amp, *r_rev, *r_fx, *r_fy;
+  double *r_r64;
+  uint32_t *r_tex;
+  // two ray queues
+  uint32_t *q_slot[2];
+  float4 *q_ray[2];          // 2 per entry: (o, tmin), (d, exclude id bits)
+  float *q_t[2];
+  int32_t *q_gid[2];
+  uint32_t *counters;        // [0], [1]: queue lengths; [2]: rays traced
+};
+
+}  // namespace hpt

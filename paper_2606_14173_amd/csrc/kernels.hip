@@ -1,0 +1,726 @@
+// gfx950 kernels of the wave path tracer (wavefront organisation).
+//
+// One batch = a set of units (blocks of (channel, pixel, sample) paths of
+// one or several jobs). Per batch:
+//   k_raygen        s1-s2: cone directions from Philox, world-space rays
+//   k_trace/k_shade  s3-s5, once per interaction: FP32 closest hit, then the
+//                   coherent delta prefix (FP64 or split OPL), the image
+//                   point (s6-s7) and the incoherent radiance tail; live rays
+//                   are compacted into the next queue with one atomic per wave
+//   k_accumulate    s8-s9: Eq. 5 for all T frames of every path (Path Reuse)
+// Random-phase tables (Eq. 4) are built by k_grf_* once per grid/T/seed.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace hpt {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ uint32_t find_unit(const UnitDev *U, uint32_t n, uint32_t i, bool acc) {
+  uint32_t lo = 0, hi = n;  // last unit with base <= i
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) >> 1;
+    uint32_t base = acc ? U[mid].acc_base : U[mid].slot_base;
+    if (base <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Workgroup index remapped so that each of the 8 XCDs (which receive
+// workgroups round-robin) works on one contiguous range of the grid.
+__device__ __forceinline__ uint32_t xcd_block() {
+  uint32_t g = gridDim.x, b = blockIdx.x;
+  if (g % 8u) return b;
+  return (b % 8u) * (g / 8u) + b / 8u;
+}
+
+__device__ __forceinline__ const float *tri_ptr(const SceneDev &S, int32_t gid) {
+  return S.tri_v + 9 * (size_t)(gid - (int32_t)S.n_sph);
+}
+
+__device__ __forceinline__ F3 normal32(const SceneDev &S, int32_t gid, F3 x) {
+  if (gid < (int32_t)S.n_sph) {
+    const float *s = S.sph + 4 * gid;
+    return (1.0f / s[3]) * (x - f3(s[0], s[1], s[2]));
+  }
+  const float *v = tri_ptr(S, gid);
+  return normalize(cross(f3(v[3] - v[0], v[4] - v[1], v[5] - v[2]),
+                         f3(v[6] - v[0], v[7] - v[1], v[8] - v[2])));
+}
+
+__device__ __forceinline__ size_t rec_index(const JobDev &J, const UnitDev &U, uint32_t p_local,
+                                            uint32_t s_local) {
+  uint32_t p = U.p_lo + p_local;
+  return ((size_t)U.ch * J.crop_w * J.crop_h + p) * J.n_s + (U.s_lo + s_local - J.spp_lo);
+}
+
+__device__ __forceinline__ void push_ray(const BatchDev &B, int q, uint32_t pos, uint32_t slot, F3 o,
+                                         F3 d, int32_t excl) {
+  B.q_slot[q][pos] = slot;
+  B.q_ray[q][2 * pos] = make_float4(o.x, o.y, o.z, kTmin);
+  B.q_ray[q][2 * pos + 1] = make_float4(d.x, d.y, d.z, __int_as_float(excl));
+}
+
+// ------------------------------------------------------------------ raygen
+__global__ void __launch_bounds__(kBlock) k_raygen(BatchDev B) {
+  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) { B.counters[0] = B.n_paths; B.counters[1] = 0; }
+  if (i >= B.n_paths) return;
+  uint32_t u = find_unit(B.units, B.n_units, i, false);
+  const UnitDev U = B.units[u];
+  const JobDev &J = *U.job;
+  uint32_t l = i - U.slot_base;
+  uint32_t s_local = l / U.p_n, p_local = l - s_local * U.p_n;
+  B.s_unit[i] = u;
+  B.s_L[i] = 0.f;
+  B.s_beta[i] = 1.f;
+  B.s_bpre[i] = 1.f;
+  B.s_first[i] = -1;
+  B.s_sig[i] = kSigInit;
+  B.r_amp[i] = 0.f;
+  if (U.kind == UNIT_HOLO) {
+    uint32_t comp = J.comp[U.ch];
+    uint32_t p = U.p_lo + p_local;
+    uint32_t px = J.crop_x0 + p % J.crop_w, py = J.crop_y0 + p / J.crop_w;
+    uint32_t gpix = py * J.width + px, smp = U.s_lo + s_local;
+    B.s_ka[i] = gpix;
+    B.s_kb[i] = smp;
+    U4 w = philox(gpix, smp, 0u, comp << 16, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
+    D3 xp = {((double)px + 0.5 - 0.5 * (double)J.width) * J.pitch,
+             ((double)py + 0.5 - 0.5 * (double)J.height) * J.pitch, 0.0};
+    D3 O, d;
+    double al, be;
+    if (J.phase_mode != HPT_PHASE_FP32) {
+      // s1: direction cosines uniform on the disc of radius lambda/(2d)
+      double rad = J.s_cone[U.ch] * sqrt(ud(w.x));
+      double sn, cs;
+      sincospi(2.0 * ud(w.y), &sn, &cs);
+      al = rad * cs; be = rad * sn;
+      D3 v = {al, be, sqrt(1.0 - al * al - be * be)};
+      if (J.identity_T) {
+        O = xp;
+        d = normalize(v);
+      } else {  // s2: into world space through the inverse of T (Eq. 3)
+        const double *M = J.Ti;
+        O = {M[0] * xp.x + M[1] * xp.y + M[2] * xp.z + M[3], M[4] * xp.x + M[5] * xp.y + M[6] * xp.z + M[7],
+             M[8] * xp.x + M[9] * xp.y + M[10] * xp.z + M[11]};
+        d = normalize(D3{M[0] * v.x + M[1] * v.y + M[2] * v.z, M[4] * v.x + M[5] * v.y + M[6] * v.z,
+                         M[8] * v.x + M[9] * v.y + M[10] * v.z});
+      }
+    } else {
+      float rad = J.s_cone_f[U.ch] * sqrtf(uf(w.x));
+      float sn, cs;
+      sincospif(2.0f * uf(w.y), &sn, &cs);
+      float alf = rad * cs, bef = rad * sn;
+      F3 v = f3(alf, bef, sqrtf(1.0f - alf * alf - bef * bef));
+      al = alf; be = bef;
+      F3 O32, d32;
+      if (J.identity_T) {
+        O32 = to_f(xp);
+        d32 = normalize(v);
+      } else {
+        float M[12];
+        for (int k = 0; k < 12; ++k) M[k] = (float)J.Ti[k];
+        F3 x = to_f(xp);
+        O32 = f3(M[0] * x.x + M[1] * x.y + M[2] * x.z + M[3], M[4] * x.x + M[5] * x.y + M[6] * x.z + M[7],
+                 M[8] * x.x + M[9] * x.y + M[10] * x.z + M[11]);
+        d32 = normalize(f3(M[0] * v.x + M[1] * v.y + M[2] * v.z, M[4] * v.x + M[5] * v.y + M[6] * v.z,
+                           M[8] * v.x + M[9] * v.y + M[10] * v.z));
+      }
+      O = to_d(O32); d = to_d(d32);
+    }
+    B.s_al[i] = al; B.s_be[i] = be;
+    B.s_ox[i] = O.x; B.s_oy[i] = O.y; B.s_oz[i] = O.z;
+    B.s_dx[i] = d.x; B.s_dy[i] = d.y; B.s_dz[i] = d.z;
+    B.s_ell[i] = 0.0;
+    B.s_W[i] = 1.0f;  // refractive index of the current medium while in the prefix
+    B.s_meta[i] = STAGE_PREFIX;
+    push_ray(B, 0, i, i, to_f(O), to_f(d), -1);
+  } else {
+    // radiance-cache path: a point uniform in the cell, a direction uniform
+    // in the bin's octahedral square
+    const SceneDev &S = *J.scene;
+    uint32_t comp = U.ch;
+    uint32_t e = U.p_lo + p_local, j = U.s_lo + s_local;
+    uint32_t nb = J.cache_bins * J.cache_bins;
+    uint32_t cell = e / nb, bin = e - cell * nb;
+    uint32_t res = J.cache_res;
+    uint32_t ix = cell % res, iy = (cell / res) % res, iz = cell / (res * res);
+    uint32_t bu = bin % J.cache_bins, bv = bin / J.cache_bins;
+    uint32_t ka = cell, kb = (bin << 16) | j;
+    uint32_t sw = (comp << 16) | 2u;
+    U4 w0 = philox(ka, kb, 0u, sw, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
+    U4 w1 = philox(ka, kb, 1u, sw, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
+    D3 lo = {S.cache_lo_d[0], S.cache_lo_d[1], S.cache_lo_d[2]};
+    D3 ext = {S.cache_hi_d[0] - lo.x, S.cache_hi_d[1] - lo.y, S.cache_hi_d[2] - lo.z};
+    D3 x = {lo.x + (ix + ud(w0.x)) / res * ext.x, lo.y + (iy + ud(w0.y)) / res * ext.y,
+            lo.z + (iz + ud(w0.z)) / res * ext.z};
+    double pu = -1.0 + 2.0 * (bu + ud(w0.w)) / J.cache_bins;
+    double pv = -1.0 + 2.0 * (bv + ud(w1.x)) / J.cache_bins;
+    D3 d = oct_decode64(pu, pv);
+    B.s_ka[i] = ka;
+    B.s_kb[i] = kb;
+    B.s_meta[i] = STAGE_TAIL;  // b = 0, bP = 0
+    push_ray(B, 0, i, i, to_f(x), to_f(d), -1);
+  }
+}
+
+// ------------------------------------------------------------------ trace
+__global__ void __launch_bounds__(kBlock) k_trace(BatchDev B, int q) {
+  uint32_t n = B.counters[q];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    B.counters[q ^ 1] = 0;
+    B.counters[2] += n;
+  }
+  uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t i = xcd_block() * blockDim.x + threadIdx.x; i < n; i += stride) {
+    uint32_t slot = B.q_slot[q][i];
+    const SceneDev &S = *B.units[B.s_unit[slot]].job->scene;
+    float4 r0 = B.q_ray[q][2 * i], r1 = B.q_ray[q][2 * i + 1];
+    Hit h = closest_hit(S, f3(r0.x, r0.y, r0.z), f3(r1.x, r1.y, r1.z), r0.w, __float_as_int(r1.w));
+    B.q_t[q][i] = h.t;
+    B.q_gid[q][i] = h.gid;
+  }
+}
+
+// ------------------------------------------------------------------ shade
+struct Emit { bool on; F3 o, d; int32_t excl; };
+
+__device__ __forceinline__ void write_rec_tail(const JobDev &J, const UnitDev &U, const BatchDev &B,
+                                               uint32_t slot, int32_t kind, uint32_t b, float A,
+                                               float amp, unsigned long long sig) {
+  uint32_t l = slot - U.slot_base;
+  uint32_t s_local = l / U.p_n, p_local = l - s_local * U.p_n;
+  hpt_path_record *R = J.rec + rec_index(J, U, p_local, s_local);
+  R->sig = sig; R->kind = kind; R->n_hits = (int32_t)b; R->A = A; R->amp = amp;
+  R->first_gid = B.s_first[slot];
+}
+
+// End of a hologram path or a cache path.
+__device__ __forceinline__ void finish(const BatchDev &B, const UnitDev &U, const JobDev &J, uint32_t slot,
+                                       int32_t kind, uint32_t b, float L, unsigned long long sig,
+                                       bool has_image) {
+  sig_add(sig, 0x100u | (uint32_t)kind);
+  B.s_sig[slot] = sig;
+  if (U.kind == UNIT_CACHE) { B.r_amp[slot] = L; return; }
+  float A = 0.f, amp = 0.f;
+  if (has_image) {
+    A = sqrtf(B.s_bpre[slot] * L);
+    amp = A * B.s_W[slot] / (float)J.spp;
+  }
+  B.r_amp[slot] = amp;
+  if (J.debug & 1u) write_rec_tail(J, U, B, slot, kind, b, A, amp, sig);
+}
+
+// s6-s7: image point of a path whose coherent prefix ended at a non-delta
+// hit after optical path length ell: P' = O + ell v, Q = T P',
+// r = |Q - x_p|, weight W = r / p(v) with p(v) = v_z / (pi s^2); phase
+// record and the random-field texel that Q falls in.
+__device__ __forceinline__ void image_point(const BatchDev &B, const UnitDev &U, const JobDev &J,
+                                            uint32_t slot, double ell, uint32_t bP) {
+  uint32_t gpix = B.s_ka[slot];
+  uint32_t px = gpix % J.width, py = gpix / J.width;
+  double al = B.s_al[slot], be = B.s_be[slot];
+  double s = J.s_cone[U.ch];
+  double r, qx, qy, u, v, rev;
+  float W;
+  if (J.phase_mode != HPT_PHASE_FP32) {
+    D3 xp = {((double)px + 0.5 - 0.5 * (double)J.width) * J.pitch,
+             ((double)py + 0.5 - 0.5 * (double)J.height) * J.pitch, 0.0};
+    double vz = sqrt(1.0 - al * al - be * be);
+    D3 Q;
+    if (J.identity_T) {
+      D3 dv = normalize(D3{al, be, vz});
+      Q = xp + ell * dv;
+    } else {
+      const double *Ti = J.Ti, *M = J.Tm;
+      D3 O = {Ti[0] * xp.x + Ti[1] * xp.y + Ti[2] * xp.z + Ti[3],
+              Ti[4] * xp.x + Ti[5] * xp.y + Ti[6] * xp.z + Ti[7],
+              Ti[8] * xp.x + Ti[9] * xp.y + Ti[10] * xp.z + Ti[11]};
+      D3 dw = normalize(D3{Ti[0] * al + Ti[1] * be + Ti[2] * vz, Ti[4] * al + Ti[5] * be + Ti[6] * vz,
+                           Ti[8] * al + Ti[9] * be + Ti[10] * vz});
+      D3 P = O + ell * dw;
+      Q = {M[0] * P.x + M[1] * P.y + M[2] * P.z + M[3], M[4] * P.x + M[5] * P.y + M[6] * P.z + M[7],
+           M[8] * P.x + M[9] * P.y + M[10] * P.z + M[11]};
+    }
+    D3 dq = Q - xp;
+    r = sqrt(dot(dq, dq));
+    W = (float)(r * (M_PI * s * s) / vz);
+    double x = r * J.inv_lambda[U.ch];
+    rev = x - floor(x);
+    qx = Q.x; qy = Q.y;
+    u = Q.x / J.pitch + 0.5 * (double)J.width - 0.5;
+    v = Q.y / J.pitch + 0.5 * (double)J.height - 0.5;
+    B.r_r64[slot] = r;
+  } else {
+    float alf = (float)al, bef = (float)be;
+    float vz = sqrtf(1.0f - alf * alf - bef * bef);
+    F3 xp = f3(((float)px + 0.5f - 0.5f * (float)J.width) * (float)J.pitch,
+               ((float)py + 0.5f - 0.5f * (float)J.height) * (float)J.pitch, 0.f);
+    F3 Q;
+    float ellf = (float)ell;
+    if (J.identity_T) {
+      Q = xp + ellf * normalize(f3(alf, bef, vz));
+    } else {
+      float Ti[12], M[12];
+      for (int k = 0; k < 12; ++k) { Ti[k] = (float)J.Ti[k]; M[k] = (float)J.Tm[k]; }
+      F3 O = f3(Ti[0] * xp.x + Ti[1] * xp.y + Ti[2] * xp.z + Ti[3],
+                Ti[4] * xp.x + Ti[5] * xp.y + Ti[6] * xp.z + Ti[7],
+                Ti[8] * xp.x + Ti[9] * xp.y + Ti[10] * xp.z + Ti[11]);
+      F3 dw = normalize(f3(Ti[0] * alf + Ti[1] * bef + Ti[2] * vz, Ti[4] * alf + Ti[5] * bef + Ti[6] * vz,
+                           Ti[8] * alf + Ti[9] * bef + Ti[10] * vz));
+      F3 P = O + ellf * dw;
+      Q = f3(M[0] * P.x + M[1] * P.y + M[2] * P.z + M[3], M[4] * P.x + M[5] * P.y + M[6] * P.z + M[7],
+             M[8] * P.x + M[9] * P.y + M[10] * P.z + M[11]);
+    }
+    F3 dq = Q - xp;
+    float rf = sqrtf(dot(dq, dq));
+    float sf = J.s_cone_f[U.ch];
+    W = rf * (3.14159265358979f * sf * sf) / vz;
+    float x = rf * J.inv_lambda_f[U.ch];
+    rev = x - floorf(x);
+    r = rf; qx = Q.x; qy = Q.y;
+    u = Q.x / (float)J.pitch + 0.5f * (float)J.width - 0.5f;
+    v = Q.y / (float)J.pitch + 0.5f * (float)J.height - 0.5f;
+    B.r_r64[slot] = r;
+  }
+  double fu = floor(u), fv = floor(v);
+  int64_t i0 = (int64_t)fu % (int64_t)J.grf_w, j0 = (int64_t)fv % (int64_t)J.grf_h;
+  if (i0 < 0) i0 += J.grf_w;
+  if (j0 < 0) j0 += J.grf_h;
+  B.r_tex[slot] = (uint32_t)i0 | ((uint32_t)j0 << 16);
+  B.r_fx[slot] = (float)(u - fu);
+  B.r_fy[slot] = (float)(v - fv);
+  B.r_rev[slot] = (float)rev;
+  B.s_W[slot] = W;
+  if (J.debug & 1u) {
+    uint32_t l = slot - U.slot_base;
+    uint32_t s_local = l / U.p_n, p_local = l - s_local * U.p_n;
+    hpt_path_record *R = J.rec + rec_index(J, U, p_local, s_local);
+    R->bP = (int32_t)bP; R->ell = ell; R->r = r; R->W = W; R->qx = qx; R->qy = qy; R->rev = rev;
+  }
+}
+
+// One interaction of the incoherent tail at x (index b), reached along d_in
+// on primitive gid. Returns a ray to trace in `e`, or finishes the path.
+__device__ __forceinline__ void tail_interaction(const BatchDev &B, const UnitDev &U, const JobDev &J,
+                                                 const SceneDev &S, uint32_t slot, F3 x, F3 d_in,
+                                                 int32_t gid, uint32_t b, uint32_t bP, uint32_t comp,
+                                                 uint32_t stream, float beta, float L,
+                                                 unsigned long long sig, Emit &e) {
+  const MaterialDev m = S.mats[S.prim_mat[gid]];
+  F3 ng = normal32(S, gid, x);
+  bool holo = U.kind == UNIT_HOLO;
+  if (m.type == HPT_EMITTER) {
+    sig_add(sig, EV_EMIT);
+    if (dot(d_in, ng) < 0.f) L += beta * (comp == 0 ? m.emit[0] : (comp == 1 ? m.emit[1] : m.emit[2]));
+    finish(B, U, J, slot, K_EMITTER, b, L, sig, holo);
+    return;
+  }
+  if (b >= J.max_bounces) { finish(B, U, J, slot, K_MAXB_TAIL, b, L, sig, holo); return; }
+  U4 w = philox(B.s_ka[slot], B.s_kb[slot], b << 8, stream, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
+  Lobe lb = sample_lobe(m, comp, d_in, ng, uf(w.x), uf(w.y), uf(w.z));
+  sig_add(sig, lb.ev);
+  if (lb.w == 0.f) { finish(B, U, J, slot, K_ABSORBED, b, L, sig, holo); return; }
+  beta *= lb.w;
+  if (holo && J.use_cache && !lb.delta && (b - bP + 1) >= J.cache_depth) {
+    uint32_t res = S.cache_res, nb = S.cache_bins * S.cache_bins;
+    int ix = (int)floorf((x.x - S.cache_lo[0]) * S.cache_scale[0]);
+    int iy = (int)floorf((x.y - S.cache_lo[1]) * S.cache_scale[1]);
+    int iz = (int)floorf((x.z - S.cache_lo[2]) * S.cache_scale[2]);
+    ix = min(max(ix, 0), (int)res - 1); iy = min(max(iy, 0), (int)res - 1); iz = min(max(iz, 0), (int)res - 1);
+    uint32_t cell = ((uint32_t)iz * res + (uint32_t)iy) * res + (uint32_t)ix;
+    uint32_t bin = oct_bin(lb.d, S.cache_bins);
+    sig_add(sig, 0x40000000u | cell);
+    sig_add(sig, 0x50000000u | bin);
+    size_t ce = (size_t)comp * res * res * res * nb + (size_t)cell * nb + bin;
+    L += beta * __half2float(__ushort_as_half(S.cache[ce]));
+    finish(B, U, J, slot, K_CACHE, b, L, sig, true);
+    return;
+  }
+  B.s_beta[slot] = beta;
+  B.s_L[slot] = L;
+  B.s_sig[slot] = sig;
+  B.s_meta[slot] = STAGE_TAIL | (b << 1) | (bP << 7);
+  e.on = true; e.o = x; e.d = lb.d;
+  e.excl = gid >= (int32_t)S.n_sph ? gid : -1;
+}
+
+__device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, Emit &e) {
+  uint32_t slot = B.q_slot[q][i];
+  const UnitDev &U = B.units[B.s_unit[slot]];
+  const JobDev &J = *U.job;
+  const SceneDev &S = *J.scene;
+  uint32_t meta = B.s_meta[slot];
+  uint32_t stage = meta & 1u, b = (meta >> 1) & 63u, bP = (meta >> 7) & 63u;
+  float t = B.q_t[q][i];
+  int32_t gid = B.q_gid[q][i];
+  unsigned long long sig = B.s_sig[slot];
+  bool holo = U.kind == UNIT_HOLO;
+  uint32_t comp = holo ? J.comp[U.ch] : U.ch;
+  uint32_t stream = (comp << 16) | (holo ? 0u : 2u);
+  if (stage == STAGE_PREFIX) {
+    if (gid < 0) {
+      sig_add(sig, 0xFFFFFFFFu);
+      finish(B, U, J, slot, K_ESCAPE_PREFIX, b, 0.f, sig, false);
+      return;
+    }
+    b += 1;
+    if (b == 1) B.s_first[slot] = gid;
+    sig_add(sig, (uint32_t)gid + 1u);
+    if (b > J.max_bounces) { finish(B, U, J, slot, K_MAXB_PREFIX, b, 0.f, sig, false); return; }
+    D3 o = {B.s_ox[slot], B.s_oy[slot], B.s_oz[slot]};
+    D3 d = {B.s_dx[slot], B.s_dy[slot], B.s_dz[slot]};
+    double ell = B.s_ell[slot];
+    float ncur = B.s_W[slot];
+    bool tri = gid >= (int32_t)S.n_sph;
+    const MaterialDev m = S.mats[S.prim_mat[gid]];
+    bool delta = m.type == HPT_MIRROR || m.type == HPT_DIELECTRIC;
+    double t64;
+    double4 pl = tri ? S.tri_plane[gid - (int32_t)S.n_sph] : make_double4(0, 0, 0, 0);
+    if (J.phase_mode == HPT_PHASE_FP32) {
+      t64 = (double)t;
+      ell = (double)((float)ell + ncur * t);
+    } else {
+      t64 = tri ? tri_t64(pl, o, d) : sph_t64(S.sph + 4 * gid, o, d, kTminD);
+      ell += (double)ncur * t64;
+    }
+    D3 x = o + t64 * d;
+    if (J.phase_mode == HPT_PHASE_FP32) x = to_d(to_f(o) + t * to_f(d));
+    if (delta) {
+      U4 w = philox(B.s_ka[slot], B.s_kb[slot], b << 8, stream, (uint32_t)J.seed,
+                    (uint32_t)(J.seed >> 32));
+      D3 ng;
+      if (tri) ng = D3{pl.x, pl.y, pl.z};
+      else {
+        const float *s = S.sph + 4 * gid;
+        ng = (1.0 / (double)s[3]) * (x - D3{s[0], s[1], s[2]});
+      }
+      double dn = dot(d, ng);
+      D3 nf = dn < 0 ? ng : (-1.0) * ng;
+      double wgt = 1.0;
+      uint32_t ev;
+      if (m.type == HPT_MIRROR) {
+        d = reflect(d, nf); ev = EV_MIRROR;
+      } else {
+        bool entering = dn < 0;
+        double eta_i = entering ? 1.0 : (double)m.ior, eta_t = entering ? (double)m.ior : 1.0;
+        double cos_i = fabs(dn), cos_t;
+        double F = fresnel64(cos_i, eta_i, eta_t, cos_t);
+        if (ud(w.x) < F) {
+          d = reflect(d, nf); ev = EV_DIEL_REFL;
+        } else {
+          double et = eta_i / eta_t;
+          d = normalize(et * d + (et * cos_i - cos_t) * nf);
+          wgt = et * et; ev = EV_DIEL_REFR;
+          ncur = (float)eta_t;
+        }
+      }
+      if (J.phase_mode == HPT_PHASE_FP32) d = to_d(normalize(to_f(d)));
+      sig_add(sig, ev);
+      B.s_bpre[slot] *= (float)wgt;
+      B.s_ox[slot] = x.x; B.s_oy[slot] = x.y; B.s_oz[slot] = x.z;
+      B.s_dx[slot] = d.x; B.s_dy[slot] = d.y; B.s_dz[slot] = d.z;
+      B.s_ell[slot] = ell;
+      B.s_W[slot] = ncur;
+      B.s_sig[slot] = sig;
+      B.s_meta[slot] = STAGE_PREFIX | (b << 1);
+      e.on = true; e.o = to_f(x); e.d = to_f(d); e.excl = tri ? gid : -1;
+      return;
+    }
+    // first non-delta hit: the real image point P
+    sig_add(sig, EV_IMAGE_POINT);
+    image_point(B, U, J, slot, ell, b);
+    tail_interaction(B, U, J, S, slot, to_f(x), to_f(d), gid, b, b, comp, stream, 1.0f, 0.0f, sig, e);
+    return;
+  }
+  // incoherent tail (or cache path)
+  float beta = B.s_beta[slot], L = B.s_L[slot];
+  float4 r0 = B.q_ray[q][2 * i], r1 = B.q_ray[q][2 * i + 1];
+  if (gid < 0) {
+    L += beta * S.env[comp];
+    sig_add(sig, 0xFFFFFFFEu);
+    finish(B, U, J, slot, K_ENV, b, L, sig, holo);
+    return;
+  }
+  b += 1;
+  sig_add(sig, (uint32_t)gid + 1u);
+  F3 d_in = f3(r1.x, r1.y, r1.z);
+  F3 x = f3(r0.x, r0.y, r0.z) + t * d_in;
+  tail_interaction(B, U, J, S, slot, x, d_in, gid, b, bP, comp, stream, beta, L, sig, e);
+}
+
+__global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
+  uint32_t n = B.counters[q];
+  int qo = q ^ 1;
+  uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
+    uint32_t i = base + threadIdx.x;
+    Emit e;
+    e.on = false;
+    if (i < n) shade_one(B, q, i, e);
+    // compaction: one atomic per wave, lane offsets from the ballot
+    unsigned long long m = __ballot(e.on);
+    uint32_t cnt = (uint32_t)__popcll(m);
+    if (cnt == 0) continue;
+    uint32_t lane = __lane_id();
+    uint32_t before = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    uint32_t first = (uint32_t)__ffsll((long long)m) - 1u;
+    uint32_t pos0 = 0;
+    if (lane == first) pos0 = atomicAdd(&B.counters[qo], cnt);
+    pos0 = __shfl(pos0, (int)first);
+    if (e.on) push_ray(B, qo, pos0 + before, B.q_slot[q][i], e.o, e.d, e.excl);
+  }
+}
+
+// ------------------------------------------------------------------ accumulate
+// s8-s9 and Path Reuse: each thread owns one pixel of a unit, walks the
+// unit's samples in order and adds A W exp(i(k r + phi_t(Q))) / spp to the
+// frames, TB at a time, then adds its partial sums to the field. Only the
+// random-field phase depends on the frame; amplitude, weight and k r are
+// computed once per path and frame block.
+template <int TB, bool F64>
+__global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
+  uint32_t idx = xcd_block() * blockDim.x + threadIdx.x;
+  if (idx >= B.n_acc) return;
+  uint32_t u = find_unit(B.units, B.n_units, idx, true);
+  const UnitDev U = B.units[u];
+  if (U.kind != UNIT_HOLO) return;
+  const JobDev &J = *U.job;
+  if (F64 != (J.phase_mode == HPT_PHASE_FP64)) return;
+  uint32_t p_local = idx - U.acc_base;
+  uint32_t p = U.p_lo + p_local;
+  uint32_t cx = p % J.crop_w, cy = p / J.crop_w;
+  using R = typename std::conditional<F64, double, float>::type;
+  const uint32_t T = J.T, gw = J.grf_w, gh = J.grf_h;
+  const float2 *G = J.grf;
+  const size_t plane = (size_t)J.crop_h * J.crop_w;
+  float2 *F = J.field + (size_t)U.ch * T * plane + (size_t)cy * J.crop_w + cx;
+  unsigned long long sigsum = 0;
+  for (uint32_t t0 = 0; t0 < T; t0 += TB) {
+    const uint32_t nt = T - t0 < (uint32_t)TB ? T - t0 : (uint32_t)TB;
+    R ar[TB], ai[TB];
+#pragma unroll
+    for (int t = 0; t < TB; ++t) { ar[t] = 0; ai[t] = 0; }
+    for (uint32_t s = 0; s < U.s_n; ++s) {
+      uint32_t slot = U.slot_base + s * U.p_n + p_local;
+      if ((J.debug & 4u) && t0 == 0) sigsum += B.s_sig[slot];
+      float amp = B.r_amp[slot];
+      if (amp == 0.f) {
+        if (J.debug & 2u) {
+          size_t base = rec_index(J, U, p_local, s) * T + t0;
+          for (uint32_t t = 0; t < nt; ++t) J.contrib[base + t] = make_float2(0.f, 0.f);
+        }
+        continue;
+      }
+      R br, bi;
+      if (F64) {
+        double x = B.r_r64[slot] * J.inv_lambda[U.ch];
+        double f = x - floor(x);
+        double sn, cs;
+        sincospi(2.0 * f, &sn, &cs);
+        br = (R)((double)amp * cs); bi = (R)((double)amp * sn);
+      } else {
+        float sn, cs;
+        sincospif(2.0f * B.r_rev[slot], &sn, &cs);
+        br = (R)(amp * cs); bi = (R)(amp * sn);
+      }
+      if (J.random_phase) {
+        uint32_t tex = B.r_tex[slot];
+        uint32_t i0 = tex & 0xFFFFu, j0 = tex >> 16;
+        uint32_t i1 = i0 + 1 == gw ? 0 : i0 + 1, j1 = j0 + 1 == gh ? 0 : j0 + 1;
+        float fx = B.r_fx[slot], fy = B.r_fy[slot];
+        float w00 = (1.f - fx) * (1.f - fy), w10 = fx * (1.f - fy), w01 = (1.f - fx) * fy, w11 = fx * fy;
+        const float2 *g00 = G + ((size_t)j0 * gw + i0) * T + t0, *g10 = G + ((size_t)j0 * gw + i1) * T + t0;
+        const float2 *g01 = G + ((size_t)j1 * gw + i0) * T + t0, *g11 = G + ((size_t)j1 * gw + i1) * T + t0;
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+          if ((uint32_t)t < nt) {
+            float2 a = g00[t], bq = g10[t], c = g01[t], d = g11[t];
+            float zr = w00 * a.x + w10 * bq.x + w01 * c.x + w11 * d.x;
+            float zi = w00 * a.y + w10 * bq.y + w01 * c.y + w11 * d.y;
+            float m2 = zr * zr + zi * zi;
+            float inv = m2 > 0.f ? rsqrtf(m2) : 0.f;
+            R pr = m2 > 0.f ? (R)(zr * inv) : (R)1, pi = (R)(zi * inv);
+            R cr = br * pr - bi * pi, ci = br * pi + bi * pr;
+            ar[t] += cr; ai[t] += ci;
+            if (J.debug & 2u)
+              J.contrib[rec_index(J, U, p_local, s) * T + t0 + t] = make_float2((float)cr, (float)ci);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int t = 0; t < TB; ++t) {
+          if ((uint32_t)t < nt) {
+            ar[t] += br; ai[t] += bi;
+            if (J.debug & 2u)
+              J.contrib[rec_index(J, U, p_local, s) * T + t0 + t] = make_float2((float)br, (float)bi);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < TB; ++t) {
+      if ((uint32_t)t < nt) {
+        float2 v = F[(t0 + t) * plane];
+        v.x += (float)ar[t]; v.y += (float)ai[t];
+        F[(t0 + t) * plane] = v;
+      }
+    }
+  }
+  if (J.debug & 4u) J.sigsum[(size_t)U.ch * plane + (size_t)cy * J.crop_w + cx] += sigsum;
+}
+
+// Mean radiance of each cache entry over its paths, rounded to binary16.
+__global__ void __launch_bounds__(kBlock) k_cache_reduce(BatchDev B) {
+  uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= B.n_acc) return;
+  uint32_t u = find_unit(B.units, B.n_units, idx, true);
+  const UnitDev U = B.units[u];
+  if (U.kind != UNIT_CACHE) return;
+  const JobDev &J = *U.job;
+  uint32_t e_local = idx - U.acc_base;
+  float sum = 0.f;
+  for (uint32_t s = 0; s < U.s_n; ++s) sum += B.r_amp[U.slot_base + s * U.p_n + e_local];
+  float mean = sum / (float)J.cache_spb;
+  size_t n_entries = (size_t)J.cache_res * J.cache_res * J.cache_res * J.cache_bins * J.cache_bins;
+  J.cache_out[(size_t)U.ch * n_entries + U.p_lo + e_local] = __half_as_ushort(__float2half_rn(mean));
+}
+
+// ------------------------------------------------------------------ Eq. 4 tables
+// Spectrum: exp(i xi_t(jx, jy)) inside the passband (sx/gw)^2 + (sy/gh)^2 <= 1/4
+// (exact integer test), 0 outside; xi = 2 pi u from Philox stream 3.
+__global__ void k_grf_spectrum(double2 *spec, uint32_t gw, uint32_t gh, uint32_t T, uint64_t seed) {
+  size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t n = (size_t)T * gh * gw;
+  if (idx >= n) return;
+  uint32_t jx = idx % gw, jy = (idx / gw) % gh, t = idx / ((size_t)gw * gh);
+  int64_t sx = jx < (gw + 1) / 2 ? (int64_t)jx : (int64_t)jx - gw;
+  int64_t sy = jy < (gh + 1) / 2 ? (int64_t)jy : (int64_t)jy - gh;
+  bool in = 4 * (sx * sx * (int64_t)gh * gh + sy * sy * (int64_t)gw * gw) <= (int64_t)gw * gw * (int64_t)gh * gh;
+  double2 v = make_double2(0.0, 0.0);
+  if (in) {
+    U4 w = philox(jx, jy, t, 3u, (uint32_t)seed, (uint32_t)(seed >> 32));
+    double sn, cs;
+    sincospi(2.0 * ud(w.x), &sn, &cs);
+    v = make_double2(cs, sn);
+  }
+  spec[idx] = v;
+}
+
+// Inverse DFT along x of one spectrum row (t, jy): only passband bins.
+__global__ void k_grf_rows(const double2 *spec, double2 *rows, uint32_t gw, uint32_t gh) {
+  extern __shared__ double2 tw[];  // exp(2 pi i m / gw)
+  uint32_t row = blockIdx.x;       // t * gh + jy
+  for (uint32_t m = threadIdx.x; m < gw; m += blockDim.x) {
+    double sn, cs;
+    sincospi(2.0 * (double)m / (double)gw, &sn, &cs);
+    tw[m] = make_double2(cs, sn);
+  }
+  __syncthreads();
+  uint32_t jy = row % gh;
+  int64_t sy = jy < (gh + 1) / 2 ? (int64_t)jy : (int64_t)jy - gh;
+  // passband half-width along x for this row
+  int64_t lim2 = (int64_t)gw * gw * (int64_t)gh * gh - 4 * sy * sy * (int64_t)gw * gw;  // >= 4 sx^2 gh^2
+  int64_t smax = 0;
+  while (4 * (smax + 1) * (smax + 1) * (int64_t)gh * gh <= lim2 && smax + 1 <= (int64_t)gw / 2) ++smax;
+  // signed bins [lo, hi]; an even grid's Nyquist bin is -gw/2 only
+  int64_t lo = -(smax < (int64_t)gw / 2 ? smax : (int64_t)gw / 2);
+  int64_t hi = smax < ((int64_t)gw - 1) / 2 ? smax : ((int64_t)gw - 1) / 2;
+  const double2 *S = spec + (size_t)row * gw;
+  for (uint32_t x = threadIdx.x; x < gw; x += blockDim.x) {
+    double re = 0.0, im = 0.0;
+    uint32_t jx = (uint32_t)(lo < 0 ? lo + gw : lo);
+    uint32_t m = (uint32_t)(((uint64_t)jx * x) % gw);  // jx * x mod gw, then stepped
+    for (int64_t sx = lo; sx <= hi; ++sx) {
+      double2 a = S[jx];
+      double2 w = tw[m];
+      re += a.x * w.x - a.y * w.y;
+      im += a.x * w.y + a.y * w.x;
+      jx = jx + 1 == gw ? 0 : jx + 1;
+      m += x;
+      if (m >= gw) m -= gw;
+    }
+    rows[(size_t)row * gw + x] = make_double2(re, im);
+  }
+}
+
+// Inverse DFT along y, scaling by 1/sqrt(#passband bins), written as
+// complex64 into the table [gh][gw][T].
+__global__ void k_grf_cols(const double2 *rows, float2 *table, uint32_t gw, uint32_t gh, uint32_t T,
+                           double scale) {
+  extern __shared__ double2 tw[];
+  uint32_t x = blockIdx.x % gw, t = blockIdx.x / gw;
+  for (uint32_t m = threadIdx.x; m < gh; m += blockDim.x) {
+    double sn, cs;
+    sincospi(2.0 * (double)m / (double)gh, &sn, &cs);
+    tw[m] = make_double2(cs, sn);
+  }
+  __syncthreads();
+  const double2 *Rr = rows + (size_t)t * gh * gw + x;
+  for (uint32_t y = threadIdx.x; y < gh; y += blockDim.x) {
+    double re = 0.0, im = 0.0;
+    uint32_t m = 0;
+    for (uint32_t jy = 0; jy < gh; ++jy) {
+      double2 a = Rr[(size_t)jy * gw];
+      double2 w = tw[m];
+      re += a.x * w.x - a.y * w.y;
+      im += a.x * w.y + a.y * w.x;
+      m += y;
+      if (m >= gh) m -= gh;
+    }
+    table[((size_t)y * gw + x) * T + t] = make_float2((float)(re * scale), (float)(im * scale));
+  }
+}
+
+// ------------------------------------------------------------------ host launchers
+static inline uint32_t grid_for(uint64_t n) { return (uint32_t)((n + kBlock - 1) / kBlock); }
+static inline uint32_t round8(uint32_t g) { return (g + 7u) & ~7u; }
+
+hipError_t launch_raygen(const BatchDev &B, hipStream_t st) {
+  hipLaunchKernelGGL(k_raygen, dim3(grid_for(B.n_paths)), dim3(kBlock), 0, st, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_bounce(const BatchDev &B, int q, hipStream_t st) {
+  uint32_t g = round8(grid_for(B.n_paths));
+  hipLaunchKernelGGL(k_trace, dim3(g), dim3(kBlock), 0, st, B, q);
+  hipLaunchKernelGGL(k_shade, dim3(grid_for(B.n_paths)), dim3(kBlock), 0, st, B, q);
+  return hipGetLastError();
+}
+
+// tb: frames per pass (1, 8 or 24); one launch per precision present in the batch.
+hipError_t launch_accumulate(const BatchDev &B, uint32_t tb, bool has_f64, bool has_f32, hipStream_t st) {
+  uint32_t g = round8(grid_for(B.n_acc));
+  if (has_f32) {
+    if (tb >= 24) hipLaunchKernelGGL((k_accumulate<24, false>), dim3(g), dim3(kBlock), 0, st, B);
+    else if (tb >= 8) hipLaunchKernelGGL((k_accumulate<8, false>), dim3(g), dim3(kBlock), 0, st, B);
+    else hipLaunchKernelGGL((k_accumulate<1, false>), dim3(g), dim3(kBlock), 0, st, B);
+  }
+  if (has_f64) {
+    if (tb >= 24) hipLaunchKernelGGL((k_accumulate<24, true>), dim3(g), dim3(kBlock), 0, st, B);
+    else if (tb >= 8) hipLaunchKernelGGL((k_accumulate<8, true>), dim3(g), dim3(kBlock), 0, st, B);
+    else hipLaunchKernelGGL((k_accumulate<1, true>), dim3(g), dim3(kBlock), 0, st, B);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_cache_reduce(const BatchDev &B, hipStream_t st) {
+  hipLaunchKernelGGL(k_cache_reduce, dim3(grid_for(B.n_acc)), dim3(kBlock), 0, st, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_grf(double2 *spec, double2 *rows, float2 *table, uint32_t gw, uint32_t gh, uint32_t T,
+                      uint64_t seed, double scale, hipStream_t st) {
+  size_t n = (size_t)T * gh * gw;
+  hipLaunchKernelGGL(k_grf_spectrum, dim3(grid_for(n)), dim3(kBlock), 0, st, spec, gw, gh, T, seed);
+  hipLaunchKernelGGL(k_grf_rows, dim3(T * gh), dim3(kBlock), gw * sizeof(double2), st, spec, rows, gw, gh);
+  hipLaunchKernelGGL(k_grf_cols, dim3(T * gw), dim3(kBlock), gh * sizeof(double2), st, rows, table, gw, gh, T,
+                     scale);
+  return hipGetLastError();
+}
+
+}  // namespace hpt

@@ -1,0 +1,1033 @@
+// Host runtime of the wave path tracer: context, resident scenes, radiance
+// caches and random-phase tables, and a continuous-batching scheduler.
+//
+// A job is split, once and independently of other jobs, into units of
+// (channel, pixel block, sample chunk). The scheduler thread admits queued
+// jobs while their device memory fits the budget, packs units of all
+// running jobs into batches of at most `capacity` paths, runs the kernel
+// sequence of a batch on the context stream and retires units. Units of one
+// (channel, pixel block) never share a batch and retire in sample order, so
+// a job's field is bitwise the same whether it runs alone or among others.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/hpt.h"
+#include "bvh_build.hpp"
+#include "hpt_types.hpp"
+#include "kernels.hpp"
+
+using namespace hpt;
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+thread_local std::string g_err;
+
+hpt_status fail(hpt_status s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+
+double ms_between(Clock::time_point a, Clock::time_point b) {
+  return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+constexpr uint32_t kMaxUnitsPerBatch = 4096;
+constexpr size_t kBytesPerPath = 4 * 4 + 9 * 8 + 4 * 4 + 8 + 4 + 4 * 4 + 8 + 4 + 2 * (4 + 32 + 4 + 4);
+
+struct Scene {
+  uint64_t id = 0;
+  std::vector<void *> bufs;
+  size_t bytes = 0;
+  SceneDev host{};
+  SceneDev *dev = nullptr;
+  hpt_scene_info info{};
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  uint16_t *cache = nullptr;
+  size_t cache_bytes = 0;
+  hpt_cache_desc cache_desc{};
+  int users = 0;
+};
+
+struct Grf {
+  uint32_t gw = 0, gh = 0, T = 0;
+  uint64_t seed = 0;
+  float2 *d = nullptr;
+  size_t bytes = 0;
+  int users = 0;
+};
+
+enum JobState { JS_QUEUED, JS_RUNNING, JS_DONE, JS_FAILED, JS_CANCELED };
+
+struct Unit {
+  uint32_t kind, ch, p_lo, p_n, s_lo, s_n, key;
+};
+
+struct Job {
+  uint64_t id = 0;
+  hpt_job_desc desc{};
+  Scene *scene = nullptr;
+  Grf *grf = nullptr;
+  bool cache_build = false;
+  JobDev host{};
+  JobDev *dev = nullptr;
+  float2 *field = nullptr;
+  bool own_field = false;
+  size_t field_elems = 0;
+  hpt_path_record *rec = nullptr;
+  float2 *contrib = nullptr;
+  unsigned long long *sigsum = nullptr;
+  size_t n_rec = 0, n_contrib = 0, n_sig = 0;
+  std::vector<Unit> units;
+  size_t next = 0, done = 0;
+  JobState state = JS_QUEUED;
+  hpt_status status = HPT_OK;
+  std::string err;
+  bool cancel = false;
+  size_t bytes = 0;       // device bytes it holds while admitted (not counting the table)
+  size_t grf_bytes = 0;   // bytes of its random-phase table if it must be built
+  Clock::time_point t_submit, t_start, t_end;
+  bool started = false;
+  hpt_job_stats stats{};
+};
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+bool affine_inverse(const double *M, double *Ti) {
+  double a = M[0], b = M[1], c = M[2], d = M[4], e = M[5], f = M[6], g = M[8], h = M[9], i = M[10];
+  double c00 = e * i - f * h, c01 = f * g - d * i, c02 = d * h - e * g;
+  double det = a * c00 + b * c01 + c * c02;
+  if (!(std::fabs(det) > 1e-300) || !std::isfinite(det)) return false;
+  double inv[9] = {c00, c * h - b * i, b * f - c * e,
+                   c01, a * i - c * g, c * d - a * f,
+                   c02, b * g - a * h, a * e - b * d};
+  for (int k = 0; k < 9; ++k) inv[k] /= det;
+  for (int r = 0; r < 3; ++r) {
+    for (int k = 0; k < 3; ++k) Ti[4 * r + k] = inv[3 * r + k];
+    Ti[4 * r + 3] = -(inv[3 * r] * M[3] + inv[3 * r + 1] * M[7] + inv[3 * r + 2] * M[11]);
+  }
+  return true;
+}
+
+}  // namespace
+
+struct hpt_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr, aux = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  uint64_t budget = 0, used = 0;
+  uint32_t capacity = 0;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::thread worker;
+  bool stop = false;
+  uint64_t next_id = 1;
+  std::map<uint64_t, std::unique_ptr<Scene>> scenes;
+  std::map<uint64_t, std::unique_ptr<Job>> jobs;
+  std::deque<Job *> queue;     // submitted, not yet admitted
+  std::vector<Job *> running;  // admitted, units left
+  std::vector<std::unique_ptr<Grf>> grfs;
+  // batch buffers
+  std::vector<void *> batch_bufs;
+  BatchDev batch{};
+  UnitDev *d_units = nullptr, *h_units = nullptr;
+  uint64_t batches = 0, jobs_done = 0;
+
+  hipError_t alloc(void **p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes ? bytes : 16);
+    if (e == hipSuccess) used += bytes;
+    return e;
+  }
+  void release(void *p, size_t bytes) {
+    if (p) { (void)hipFree(p); used -= std::min<uint64_t>(used, bytes); }
+  }
+};
+
+namespace {
+
+// ---------------------------------------------------------------- random tables
+Grf *find_grf(hpt_ctx *C, uint32_t gw, uint32_t gh, uint32_t T, uint64_t seed) {
+  for (auto &g : C->grfs)
+    if (g->gw == gw && g->gh == gh && g->T == T && g->seed == seed) return g.get();
+  return nullptr;
+}
+
+size_t grf_table_bytes(uint32_t gw, uint32_t gh, uint32_t T) { return (size_t)gw * gh * T * sizeof(float2); }
+size_t grf_temp_bytes(uint32_t gw, uint32_t gh, uint32_t T) { return 2 * (size_t)gw * gh * T * sizeof(double2); }
+
+uint64_t passband_bins(uint32_t gw, uint32_t gh) {
+  uint64_t n = 0;
+  for (uint32_t jy = 0; jy < gh; ++jy) {
+    int64_t sy = jy < (gh + 1) / 2 ? (int64_t)jy : (int64_t)jy - gh;
+    for (uint32_t jx = 0; jx < gw; ++jx) {
+      int64_t sx = jx < (gw + 1) / 2 ? (int64_t)jx : (int64_t)jx - gw;
+      if (4 * (sx * sx * (int64_t)gh * gh + sy * sy * (int64_t)gw * gw) <= (int64_t)gw * gw * (int64_t)gh * gh) ++n;
+    }
+  }
+  return n;
+}
+
+// Drop tables no running job uses until `need` more bytes fit the budget.
+void evict_grfs(hpt_ctx *C, size_t need) {
+  for (size_t k = 0; k < C->grfs.size() && C->used + need > C->budget;) {
+    if (C->grfs[k]->users == 0) {
+      C->release(C->grfs[k]->d, C->grfs[k]->bytes);
+      C->grfs.erase(C->grfs.begin() + k);
+    } else {
+      ++k;
+    }
+  }
+}
+
+// Build a table (caller holds the lock); synchronous on `st`.
+hpt_status build_grf(hpt_ctx *C, uint32_t gw, uint32_t gh, uint32_t T, uint64_t seed, hipStream_t st,
+                     Grf **out) {
+  if (Grf *g = find_grf(C, gw, gh, T, seed)) { *out = g; return HPT_OK; }
+  size_t tb = grf_table_bytes(gw, gh, T), tmp = grf_temp_bytes(gw, gh, T);
+  evict_grfs(C, tb + tmp);
+  if (C->used + tb + tmp > C->budget) return fail(HPT_EBUDGET, "random-phase table does not fit the budget");
+  auto g = std::make_unique<Grf>();
+  g->gw = gw; g->gh = gh; g->T = T; g->seed = seed; g->bytes = tb;
+  void *spec = nullptr, *rows = nullptr;
+  if (C->alloc((void **)&g->d, tb) != hipSuccess) return fail(HPT_ENOMEM, "table allocation failed");
+  if (C->alloc(&spec, tmp / 2) != hipSuccess || C->alloc(&rows, tmp / 2) != hipSuccess) {
+    C->release(spec, tmp / 2);
+    C->release(g->d, tb);
+    return fail(HPT_ENOMEM, "table scratch allocation failed");
+  }
+  double scale = 1.0 / std::sqrt((double)passband_bins(gw, gh));
+  hipError_t e = launch_grf((double2 *)spec, (double2 *)rows, g->d, gw, gh, T, seed, scale, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  C->release(spec, tmp / 2);
+  C->release(rows, tmp / 2);
+  if (e != hipSuccess) {
+    C->release(g->d, tb);
+    return fail(HPT_EDEVICE, std::string("table build failed: ") + hipGetErrorString(e));
+  }
+  *out = g.get();
+  C->grfs.push_back(std::move(g));
+  return HPT_OK;
+}
+
+// ---------------------------------------------------------------- jobs
+void split_units(Job *J) {
+  uint32_t P = J->host.crop_w * J->host.crop_h, S = J->host.n_s;
+  uint32_t Pu = std::min<uint32_t>(P, 1u << 16);
+  uint32_t Su = std::max<uint32_t>(1u, std::min<uint32_t>(S, (1u << 20) / Pu));
+  uint32_t nblk = (P + Pu - 1) / Pu;
+  for (uint32_t s0 = 0; s0 < S; s0 += Su)
+    for (uint32_t c = 0; c < J->host.n_ch; ++c)
+      for (uint32_t r = 0; r < nblk; ++r) {
+        Unit u;
+        u.kind = UNIT_HOLO; u.ch = c;
+        u.p_lo = r * Pu; u.p_n = std::min(Pu, P - r * Pu);
+        u.s_lo = J->host.spp_lo + s0; u.s_n = std::min(Su, S - s0);
+        u.key = c * nblk + r;
+        J->units.push_back(u);
+      }
+}
+
+void split_cache_units(Job *J) {
+  uint32_t E = J->host.cache_res * J->host.cache_res * J->host.cache_res * J->host.cache_bins *
+               J->host.cache_bins;
+  uint32_t spb = J->host.cache_spb;
+  uint32_t Eu = std::max<uint32_t>(1u, std::min<uint32_t>(E, (1u << 20) / spb));
+  uint32_t nblk = (E + Eu - 1) / Eu;
+  for (uint32_t c = 0; c < 3; ++c)
+    for (uint32_t r = 0; r < nblk; ++r) {
+      Unit u;
+      u.kind = UNIT_CACHE; u.ch = c;
+      u.p_lo = r * Eu; u.p_n = std::min(Eu, E - r * Eu);
+      u.s_lo = 0; u.s_n = spb;
+      u.key = c * nblk + r;
+      J->units.push_back(u);
+    }
+}
+
+void free_job_buffers(hpt_ctx *C, Job *J) {
+  if (J->own_field) C->release(J->field, J->field_elems * sizeof(float2));
+  C->release(J->rec, J->n_rec * sizeof(hpt_path_record));
+  C->release(J->contrib, J->n_contrib * sizeof(float2));
+  C->release(J->sigsum, J->n_sig * sizeof(unsigned long long));
+  C->release(J->dev, sizeof(JobDev));
+  J->field = nullptr; J->rec = nullptr; J->contrib = nullptr; J->sigsum = nullptr; J->dev = nullptr;
+}
+
+void retire(hpt_ctx *C, Job *J, JobState st, hpt_status status, const std::string &err) {
+  J->state = st;
+  J->status = status;
+  J->err = err;
+  J->t_end = Clock::now();
+  if (!J->started) J->t_start = J->t_end;
+  J->stats.queued_ms = ms_between(J->t_submit, J->t_start);
+  J->stats.run_ms = ms_between(J->t_start, J->t_end);
+  if (J->scene) J->scene->users--;
+  if (J->grf) J->grf->users--;
+  C->running.erase(std::remove(C->running.begin(), C->running.end(), J), C->running.end());
+  C->jobs_done++;
+  C->cv.notify_all();
+}
+
+// Allocate what a queued job needs and move it to the running set.
+hpt_status admit(hpt_ctx *C, Job *J) {
+  if (!J->cache_build) {
+    const hpt_job_desc &d = J->desc;
+    hpt_status s = build_grf(C, d.grf_w, d.grf_h, d.T, d.grf_seed, C->stream, &J->grf);
+    if (s != HPT_OK) return s;
+    J->grf->users++;
+    J->host.grf = J->grf->d;
+  }
+  bool ok = true;
+  if (J->own_field) ok &= C->alloc((void **)&J->field, J->field_elems * sizeof(float2)) == hipSuccess;
+  if (J->n_rec) ok &= C->alloc((void **)&J->rec, J->n_rec * sizeof(hpt_path_record)) == hipSuccess;
+  if (J->n_contrib) ok &= C->alloc((void **)&J->contrib, J->n_contrib * sizeof(float2)) == hipSuccess;
+  if (J->n_sig) ok &= C->alloc((void **)&J->sigsum, J->n_sig * sizeof(unsigned long long)) == hipSuccess;
+  ok &= C->alloc((void **)&J->dev, sizeof(JobDev)) == hipSuccess;
+  if (!ok) {
+    free_job_buffers(C, J);
+    if (J->grf) { J->grf->users--; J->grf = nullptr; }
+    return fail(HPT_ENOMEM, "job allocation failed");
+  }
+  J->host.field = J->field;
+  J->host.rec = J->rec;
+  J->host.contrib = J->contrib;
+  J->host.sigsum = J->sigsum;
+  hipError_t e = hipSuccess;
+  if (J->field && !J->cache_build) e = hipMemsetAsync(J->field, 0, J->field_elems * sizeof(float2), C->stream);
+  if (e == hipSuccess && J->rec) e = hipMemsetAsync(J->rec, 0, J->n_rec * sizeof(hpt_path_record), C->stream);
+  if (e == hipSuccess && J->contrib) e = hipMemsetAsync(J->contrib, 0, J->n_contrib * sizeof(float2), C->stream);
+  if (e == hipSuccess && J->sigsum)
+    e = hipMemsetAsync(J->sigsum, 0, J->n_sig * sizeof(unsigned long long), C->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(J->dev, &J->host, sizeof(JobDev), hipMemcpyHostToDevice, C->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(C->stream);
+  if (e != hipSuccess) {
+    free_job_buffers(C, J);
+    return fail(HPT_EDEVICE, std::string("job set-up failed: ") + hipGetErrorString(e));
+  }
+  J->state = JS_RUNNING;
+  C->running.push_back(J);
+  return HPT_OK;
+}
+
+struct Picked { Job *job; size_t unit; };
+
+// Fill one batch round-robin over the running jobs.
+std::vector<Picked> pick_batch(hpt_ctx *C) {
+  std::vector<Picked> out;
+  uint64_t paths = 0;
+  std::vector<std::vector<uint32_t>> keys(C->running.size());
+  std::vector<bool> blocked(C->running.size(), false);
+  bool progress = true;
+  while (progress && out.size() < kMaxUnitsPerBatch) {
+    progress = false;
+    for (size_t j = 0; j < C->running.size() && out.size() < kMaxUnitsPerBatch; ++j) {
+      Job *J = C->running[j];
+      if (blocked[j] || J->cancel || J->next >= J->units.size()) continue;
+      const Unit &u = J->units[J->next];
+      uint64_t np = (uint64_t)u.p_n * u.s_n;
+      if (paths + np > C->capacity ||
+          std::find(keys[j].begin(), keys[j].end(), u.key) != keys[j].end()) {
+        blocked[j] = true;
+        continue;
+      }
+      keys[j].push_back(u.key);
+      out.push_back({J, J->next});
+      J->next++;
+      paths += np;
+      progress = true;
+    }
+  }
+  return out;
+}
+
+// Run one batch on the context stream (lock not held).
+hpt_status run_batch(hpt_ctx *C, const std::vector<Picked> &P, double &gpu_ms, uint64_t &rays) {
+  uint32_t slot = 0, acc = 0, max_b = 0, max_T = 1;
+  bool has_f64 = false, has_f32 = false, has_holo = false, has_cache = false;
+  for (size_t k = 0; k < P.size(); ++k) {
+    const Unit &u = P[k].job->units[P[k].unit];
+    UnitDev &d = C->h_units[k];
+    d.kind = u.kind; d.ch = u.ch; d.p_lo = u.p_lo; d.p_n = u.p_n; d.s_lo = u.s_lo; d.s_n = u.s_n;
+    d.slot_base = slot; d.acc_base = acc; d.job = P[k].job->dev;
+    slot += u.p_n * u.s_n;
+    acc += u.p_n;
+    const JobDev &J = P[k].job->host;
+    max_b = std::max(max_b, J.max_bounces);
+    if (u.kind == UNIT_HOLO) {
+      has_holo = true;
+      max_T = std::max(max_T, J.T);
+      if (J.phase_mode == HPT_PHASE_FP64) has_f64 = true; else has_f32 = true;
+    } else {
+      has_cache = true;
+    }
+  }
+  BatchDev B = C->batch;
+  B.units = C->d_units;
+  B.n_units = (uint32_t)P.size();
+  B.n_paths = slot;
+  B.n_acc = acc;
+  hipError_t e = hipMemcpyAsync(C->d_units, C->h_units, P.size() * sizeof(UnitDev), hipMemcpyHostToDevice,
+                                C->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(B.counters, 0, 4 * sizeof(uint32_t), C->stream);
+  if (e == hipSuccess) e = hipEventRecord(C->ev0, C->stream);
+  if (e == hipSuccess) e = launch_raygen(B, C->stream);
+  for (uint32_t it = 0; e == hipSuccess && it <= max_b; ++it) e = launch_bounce(B, (int)(it & 1u), C->stream);
+  if (e == hipSuccess && has_holo) {
+    uint32_t tb = max_T >= 24 ? 24 : (max_T >= 8 ? 8 : 1);
+    e = launch_accumulate(B, tb, has_f64, has_f32, C->stream);
+  }
+  if (e == hipSuccess && has_cache) e = launch_cache_reduce(B, C->stream);
+  if (e == hipSuccess) e = hipEventRecord(C->ev1, C->stream);
+  if (e == hipSuccess) e = hipEventSynchronize(C->ev1);
+  uint32_t cnt[4] = {0, 0, 0, 0};
+  if (e == hipSuccess) e = hipMemcpy(cnt, B.counters, sizeof(cnt), hipMemcpyDeviceToHost);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, C->ev0, C->ev1);
+  if (e != hipSuccess) return fail(HPT_EDEVICE, std::string("batch failed: ") + hipGetErrorString(e));
+  gpu_ms = ms;
+  rays = cnt[2];
+  return HPT_OK;
+}
+
+void scheduler(hpt_ctx *C) {
+  (void)hipSetDevice(C->device);
+  std::unique_lock<std::mutex> lk(C->mu);
+  for (;;) {
+    C->cv.wait(lk, [&] {
+      if (C->stop) return true;
+      for (Job *J : C->running)
+        if (J->cancel || J->next < J->units.size()) return true;
+      return !C->queue.empty();
+    });
+    if (C->stop) break;
+    // cancellations at the batch boundary
+    for (size_t k = 0; k < C->running.size();) {
+      Job *J = C->running[k];
+      if (J->cancel) retire(C, J, JS_CANCELED, HPT_ECANCELED, "cancelled");
+      else ++k;
+    }
+    // admission in arrival order while memory allows
+    while (!C->queue.empty()) {
+      Job *J = C->queue.front();
+      if (J->cancel) {
+        C->queue.pop_front();
+        J->state = JS_CANCELED; J->status = HPT_ECANCELED;
+        if (J->scene) J->scene->users--;
+        C->cv.notify_all();
+        continue;
+      }
+      size_t need = J->bytes + (J->cache_build || find_grf(C, J->desc.grf_w, J->desc.grf_h, J->desc.T,
+                                                           J->desc.grf_seed)
+                                     ? 0
+                                     : J->grf_bytes);
+      if (C->used + need > C->budget) evict_grfs(C, need);
+      if (C->used + need > C->budget && !C->running.empty()) break;  // wait for memory
+      C->queue.pop_front();
+      hpt_status s = admit(C, J);
+      if (s != HPT_OK) {
+        J->state = JS_FAILED; J->status = s; J->err = g_err;
+        if (J->scene) J->scene->users--;
+        C->cv.notify_all();
+      }
+    }
+    std::vector<Picked> P = pick_batch(C);
+    if (P.empty()) continue;
+    for (auto &p : P)
+      if (!p.job->started) { p.job->started = true; p.job->t_start = Clock::now(); }
+    lk.unlock();
+    double gpu_ms = 0.0;
+    uint64_t rays = 0;
+    hpt_status s = run_batch(C, P, gpu_ms, rays);
+    std::string err = s == HPT_OK ? std::string() : g_err;
+    lk.lock();
+    C->batches++;
+    uint64_t total = 0;
+    for (auto &p : P) total += (uint64_t)p.job->units[p.unit].p_n * p.job->units[p.unit].s_n;
+    for (auto &p : P) {
+      Job *J = p.job;
+      uint64_t np = (uint64_t)J->units[p.unit].p_n * J->units[p.unit].s_n;
+      J->stats.paths += np;
+      J->stats.rays += total ? rays * np / total : 0;
+      J->stats.trace_gpu_ms += total ? gpu_ms * (double)np / (double)total : 0.0;
+      J->done++;
+    }
+    std::vector<Job *> seen;
+    for (auto &p : P) {
+      Job *J = p.job;
+      if (std::find(seen.begin(), seen.end(), J) != seen.end()) continue;
+      seen.push_back(J);
+      J->stats.batches++;
+      if (J->state != JS_RUNNING) continue;
+      if (s != HPT_OK) retire(C, J, JS_FAILED, s, err);
+      else if (J->done == J->units.size()) retire(C, J, JS_DONE, HPT_OK, "");
+    }
+  }
+  // drain: everything still queued or running is cancelled
+  for (Job *J : C->queue) {
+    J->state = JS_CANCELED; J->status = HPT_ECANCELED;
+    if (J->scene) J->scene->users--;
+  }
+  C->queue.clear();
+  while (!C->running.empty()) retire(C, C->running.front(), JS_CANCELED, HPT_ECANCELED, "context destroyed");
+  C->cv.notify_all();
+}
+
+hpt_status alloc_batch(hpt_ctx *C) {
+  uint32_t N = C->capacity;
+  BatchDev &B = C->batch;
+  auto A = [&](void **p, size_t bytes) {
+    if (C->alloc(p, bytes) != hipSuccess) return false;
+    C->batch_bufs.push_back(*p);
+    return true;
+  };
+  bool ok = true;
+  ok &= A((void **)&B.s_meta, 4ull * N) && A((void **)&B.s_unit, 4ull * N) && A((void **)&B.s_ka, 4ull * N) &&
+        A((void **)&B.s_kb, 4ull * N);
+  ok &= A((void **)&B.s_ox, 8ull * N) && A((void **)&B.s_oy, 8ull * N) && A((void **)&B.s_oz, 8ull * N) &&
+        A((void **)&B.s_dx, 8ull * N) && A((void **)&B.s_dy, 8ull * N) && A((void **)&B.s_dz, 8ull * N) &&
+        A((void **)&B.s_ell, 8ull * N) && A((void **)&B.s_al, 8ull * N) && A((void **)&B.s_be, 8ull * N);
+  ok &= A((void **)&B.s_bpre, 4ull * N) && A((void **)&B.s_beta, 4ull * N) && A((void **)&B.s_L, 4ull * N) &&
+        A((void **)&B.s_W, 4ull * N) && A((void **)&B.s_sig, 8ull * N) && A((void **)&B.s_first, 4ull * N);
+  ok &= A((void **)&B.r_amp, 4ull * N) && A((void **)&B.r_rev, 4ull * N) && A((void **)&B.r_fx, 4ull * N) &&
+        A((void **)&B.r_fy, 4ull * N) && A((void **)&B.r_r64, 8ull * N) && A((void **)&B.r_tex, 4ull * N);
+  for (int q = 0; q < 2 && ok; ++q)
+    ok &= A((void **)&B.q_slot[q], 4ull * N) && A((void **)&B.q_ray[q], 32ull * N) &&
+          A((void **)&B.q_t[q], 4ull * N) && A((void **)&B.q_gid[q], 4ull * N);
+  ok &= A((void **)&B.counters, 64);
+  ok &= A((void **)&C->d_units, kMaxUnitsPerBatch * sizeof(UnitDev));
+  if (!ok) return fail(HPT_ENOMEM, "batch buffer allocation failed");
+  if (hipHostMalloc((void **)&C->h_units, kMaxUnitsPerBatch * sizeof(UnitDev), hipHostMallocDefault) !=
+      hipSuccess)
+    return fail(HPT_ENOMEM, "pinned unit table allocation failed");
+  return HPT_OK;
+}
+
+Job *find_job(hpt_ctx *C, uint64_t id) {
+  auto it = C->jobs.find(id);
+  return it == C->jobs.end() ? nullptr : it->second.get();
+}
+
+Scene *find_scene(hpt_ctx *C, uint64_t id) {
+  auto it = C->scenes.find(id);
+  return it == C->scenes.end() ? nullptr : it->second.get();
+}
+
+bool finite3(const float *p) { return std::isfinite(p[0]) && std::isfinite(p[1]) && std::isfinite(p[2]); }
+
+}  // namespace
+
+// =================================================================== ABI
+extern "C" {
+
+const char *hpt_last_error(void) { return g_err.c_str(); }
+const char *hpt_version(void) { return "hpt-mi355x 0.1 (gfx950)"; }
+
+hpt_status hpt_create(int device, uint64_t budget, hpt_ctx **out) {
+  if (!out) return fail(HPT_EINVAL, "out is null");
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
+    return fail(HPT_ENODEV, "no such HIP device");
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) return fail(HPT_ENODEV, "device query failed");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(HPT_ENODEV, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+  if (hipSetDevice(device) != hipSuccess) return fail(HPT_ENODEV, "hipSetDevice failed");
+  auto C = std::make_unique<hpt_ctx>();
+  C->device = device;
+  size_t free_b = 0, total_b = 0;
+  (void)hipMemGetInfo(&free_b, &total_b);
+  C->budget = budget ? budget : (uint64_t)(0.9 * (double)free_b);
+  // path capacity: at most 2^24, at most a quarter of the budget
+  uint64_t cap = std::min<uint64_t>(1ull << 24, C->budget / 4 / kBytesPerPath);
+  uint32_t c = 1u << 16;
+  while ((uint64_t)c * 2 <= cap) c *= 2;
+  if ((uint64_t)c * kBytesPerPath > C->budget) return fail(HPT_EBUDGET, "budget too small for path state");
+  C->capacity = c;
+  if (hipStreamCreateWithFlags(&C->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&C->aux, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreate(&C->ev0) != hipSuccess || hipEventCreate(&C->ev1) != hipSuccess)
+    return fail(HPT_EDEVICE, "stream/event creation failed");
+  hpt_status s = alloc_batch(C.get());
+  if (s != HPT_OK) {
+    for (void *p : C->batch_bufs) (void)hipFree(p);
+    return s;
+  }
+  hpt_ctx *raw = C.release();
+  raw->worker = std::thread(scheduler, raw);
+  *out = raw;
+  return HPT_OK;
+}
+
+void hpt_destroy(hpt_ctx *C) {
+  if (!C) return;
+  {
+    std::lock_guard<std::mutex> g(C->mu);
+    C->stop = true;
+    for (Job *J : C->running) J->cancel = true;
+  }
+  C->cv.notify_all();
+  if (C->worker.joinable()) C->worker.join();
+  (void)hipSetDevice(C->device);
+  (void)hipStreamSynchronize(C->stream);
+  for (auto &kv : C->jobs) free_job_buffers(C, kv.second.get());
+  for (auto &g : C->grfs) (void)hipFree(g->d);
+  for (auto &kv : C->scenes) {
+    for (void *p : kv.second->bufs) (void)hipFree(p);
+    (void)hipFree(kv.second->dev);
+    (void)hipFree(kv.second->cache);
+  }
+  for (void *p : C->batch_bufs) (void)hipFree(p);
+  if (C->h_units) (void)hipHostFree(C->h_units);
+  (void)hipEventDestroy(C->ev0);
+  (void)hipEventDestroy(C->ev1);
+  (void)hipStreamDestroy(C->stream);
+  (void)hipStreamDestroy(C->aux);
+  delete C;
+}
+
+hpt_status hpt_ctx_stats_get(hpt_ctx *C, hpt_ctx_stats *out) {
+  if (!C || !out) return fail(HPT_EINVAL, "null argument");
+  std::lock_guard<std::mutex> g(C->mu);
+  out->budget_bytes = C->budget;
+  out->used_bytes = C->used;
+  out->batch_capacity_paths = C->capacity;
+  out->batches = C->batches;
+  out->jobs_done = C->jobs_done;
+  out->jobs_queued = C->queue.size();
+  out->jobs_running = C->running.size();
+  return HPT_OK;
+}
+
+hpt_status hpt_scene_upload(hpt_ctx *C, const hpt_scene_desc *d, uint64_t *out) {
+  if (!C || !d || !out) return fail(HPT_EINVAL, "null argument");
+  if ((d->n_tri && (!d->tri || !d->tri_mat)) || (d->n_sph && (!d->sph || !d->sph_mat)))
+    return fail(HPT_EINVAL, "missing primitive arrays");
+  if (d->n_mat == 0 || !d->mat_type || !d->mat_rgb || !d->mat_rough || !d->mat_ior || !d->mat_emit || !d->env)
+    return fail(HPT_EINVAL, "missing material arrays");
+  if ((uint64_t)d->n_tri + d->n_sph >= (1ull << 27)) return fail(HPT_EINVAL, "too many primitives");
+  for (uint32_t i = 0; i < d->n_mat; ++i) {
+    if (d->mat_type[i] > HPT_EMITTER) return fail(HPT_EINVAL, "unknown material type");
+    if (d->mat_type[i] == HPT_GGX && !(d->mat_rough[i] > 0.f && d->mat_rough[i] <= 1.f))
+      return fail(HPT_EINVAL, "GGX roughness must be in (0, 1]");
+    if (d->mat_type[i] == HPT_DIELECTRIC && !(d->mat_ior[i] > 1.f && std::isfinite(d->mat_ior[i])))
+      return fail(HPT_EINVAL, "dielectric index must be > 1");
+    if (!finite3(d->mat_rgb + 3 * i) || !finite3(d->mat_emit + 3 * i)) return fail(HPT_EINVAL, "non-finite material");
+  }
+  if (!finite3(d->env)) return fail(HPT_EINVAL, "non-finite environment");
+  for (uint32_t i = 0; i < d->n_tri; ++i) {
+    if (d->tri_mat[i] >= d->n_mat) return fail(HPT_EINVAL, "triangle material index out of range");
+    for (int k = 0; k < 3; ++k)
+      if (!finite3(d->tri + 9 * (size_t)i + 3 * k)) return fail(HPT_EINVAL, "non-finite vertex");
+  }
+  for (uint32_t i = 0; i < d->n_sph; ++i) {
+    if (d->sph_mat[i] >= d->n_mat) return fail(HPT_EINVAL, "sphere material index out of range");
+    if (!finite3(d->sph + 4 * i) || !(d->sph[4 * i + 3] > 0.f) || !std::isfinite(d->sph[4 * i + 3]))
+      return fail(HPT_EINVAL, "bad sphere");
+  }
+  // host BVH build without the lock
+  auto S = std::make_unique<Scene>();
+  BvhResult bvh;
+  uint32_t n = d->n_tri + d->n_sph;
+  if (n > 0 && !build_bvh(d->tri, d->n_tri, d->sph, d->n_sph, bvh))
+    return fail(HPT_EINVAL, "BVH build failed (tree deeper than the traversal stack)");
+  // bounds in FP64 from the float32 data (the radiance-cache grid uses them)
+  for (int a = 0; a < 3; ++a) { S->lo[a] = INFINITY; S->hi[a] = -INFINITY; }
+  for (uint32_t i = 0; i < d->n_sph; ++i)
+    for (int a = 0; a < 3; ++a) {
+      double c = d->sph[4 * i + a], r = d->sph[4 * i + 3];
+      S->lo[a] = std::min(S->lo[a], c - r); S->hi[a] = std::max(S->hi[a], c + r);
+    }
+  for (size_t i = 0; i < 3 * (size_t)d->n_tri; ++i)
+    for (int a = 0; a < 3; ++a) {
+      double v = d->tri[3 * i + a];
+      S->lo[a] = std::min(S->lo[a], v); S->hi[a] = std::max(S->hi[a], v);
+    }
+  if (n == 0)
+    for (int a = 0; a < 3; ++a) { S->lo[a] = 0; S->hi[a] = 0; }
+  std::vector<MaterialDev> mats(d->n_mat);
+  for (uint32_t i = 0; i < d->n_mat; ++i) {
+    MaterialDev &m = mats[i];
+    m.type = d->mat_type[i];
+    for (int c = 0; c < 3; ++c) { m.rgb[c] = d->mat_rgb[3 * i + c]; m.emit[c] = d->mat_emit[3 * i + c]; }
+    m.rough = d->mat_rough[i]; m.ior = d->mat_ior[i]; m.pad = 0.f;
+  }
+  // FP64 plane of every triangle for the coherent-prefix refinement
+  std::vector<double> planes(4 * std::max<size_t>(d->n_tri, 1), 0.0);
+  for (uint32_t i = 0; i < d->n_tri; ++i) {
+    const float *v = d->tri + 9 * (size_t)i;
+    double e1[3] = {(double)v[3] - v[0], (double)v[4] - v[1], (double)v[5] - v[2]};
+    double e2[3] = {(double)v[6] - v[0], (double)v[7] - v[1], (double)v[8] - v[2]};
+    double nx = e1[1] * e2[2] - e1[2] * e2[1], ny = e1[2] * e2[0] - e1[0] * e2[2],
+           nz = e1[0] * e2[1] - e1[1] * e2[0];
+    double len = std::sqrt(nx * nx + ny * ny + nz * nz);
+    if (len > 0) { nx /= len; ny /= len; nz /= len; }
+    planes[4 * i] = nx; planes[4 * i + 1] = ny; planes[4 * i + 2] = nz;
+    planes[4 * i + 3] = nx * v[0] + ny * v[1] + nz * v[2];
+  }
+  std::vector<uint32_t> prim_mat(std::max<uint32_t>(n, 1));
+  for (uint32_t i = 0; i < d->n_sph; ++i) prim_mat[i] = d->sph_mat[i];
+  for (uint32_t i = 0; i < d->n_tri; ++i) prim_mat[d->n_sph + i] = d->tri_mat[i];
+  std::lock_guard<std::mutex> g(C->mu);
+  (void)hipSetDevice(C->device);
+  size_t need = bvh.nodes.size() * 4 + bvh.prims.size() * 4 + 68ull * d->n_tri + 16ull * d->n_sph +
+                4ull * prim_mat.size() + sizeof(MaterialDev) * mats.size() + sizeof(SceneDev);
+  if (C->used + need > C->budget) evict_grfs(C, need);
+  if (C->used + need > C->budget) return fail(HPT_EBUDGET, "scene does not fit the budget");
+  auto put = [&](const void *src, size_t bytes, void **dst) {
+    if (C->alloc(dst, bytes) != hipSuccess) return false;
+    S->bufs.push_back(*dst);
+    S->bytes += bytes;
+    return bytes == 0 || hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+  };
+  bool ok = true;
+  void *p;
+  SceneDev &h = S->host;
+  std::memset(&h, 0, sizeof(h));
+  if (n > 0) {
+    ok &= put(bvh.nodes.data(), bvh.nodes.size() * 4, &p); h.nodes = (const float4 *)p;
+    ok &= put(bvh.prims.data(), bvh.prims.size() * 4, &p); h.prims = (const float4 *)p;
+  }
+  ok &= put(d->tri, 36ull * d->n_tri, &p); h.tri_v = (const float *)p;
+  ok &= put(planes.data(), 32ull * d->n_tri, &p); h.tri_plane = (const double4 *)p;
+  ok &= put(d->sph, 16ull * d->n_sph, &p); h.sph = (const float *)p;
+  ok &= put(prim_mat.data(), 4ull * prim_mat.size(), &p); h.prim_mat = (const uint32_t *)p;
+  ok &= put(mats.data(), sizeof(MaterialDev) * mats.size(), &p); h.mats = (const MaterialDev *)p;
+  h.n_sph = d->n_sph; h.n_tri = d->n_tri; h.n_mat = d->n_mat; h.n_nodes = n ? bvh.n_nodes : 0;
+  for (int c = 0; c < 3; ++c) h.env[c] = d->env[c];
+  ok &= C->alloc((void **)&S->dev, sizeof(SceneDev)) == hipSuccess;
+  if (ok) S->bytes += sizeof(SceneDev);
+  ok = ok && hipMemcpy(S->dev, &h, sizeof(SceneDev), hipMemcpyHostToDevice) == hipSuccess;
+  if (!ok) {
+    for (void *q : S->bufs) C->release(q, 0);
+    C->used -= std::min<uint64_t>(C->used, S->bytes);
+    if (S->dev) (void)hipFree(S->dev);
+    return fail(HPT_ENOMEM, "scene upload failed");
+  }
+  S->id = C->next_id++;
+  S->info.n_nodes = h.n_nodes;
+  S->info.n_prims = n;
+  S->info.max_depth = bvh.max_depth;
+  S->info.device_bytes = S->bytes;
+  S->info.build_ms = bvh.build_ms;
+  for (int a = 0; a < 3; ++a) { S->info.bounds[a] = S->lo[a]; S->info.bounds[3 + a] = S->hi[a]; }
+  *out = S->id;
+  C->scenes[S->id] = std::move(S);
+  return HPT_OK;
+}
+
+hpt_status hpt_scene_info_get(hpt_ctx *C, uint64_t scene, hpt_scene_info *out) {
+  if (!C || !out) return fail(HPT_EINVAL, "null argument");
+  std::lock_guard<std::mutex> g(C->mu);
+  Scene *S = find_scene(C, scene);
+  if (!S) return fail(HPT_ENOTFOUND, "unknown scene");
+  *out = S->info;
+  return HPT_OK;
+}
+
+hpt_status hpt_scene_release(hpt_ctx *C, uint64_t scene) {
+  if (!C) return fail(HPT_EINVAL, "null context");
+  std::lock_guard<std::mutex> g(C->mu);
+  Scene *S = find_scene(C, scene);
+  if (!S) return fail(HPT_ENOTFOUND, "unknown scene");
+  if (S->users > 0) return fail(HPT_EBUSY, "scene in use by a job");
+  for (auto &kv : C->jobs)
+    if (kv.second->scene == S) kv.second->scene = nullptr;
+  for (void *p : S->bufs) (void)hipFree(p);
+  (void)hipFree(S->dev);
+  if (S->cache) (void)hipFree(S->cache);
+  C->used -= std::min<uint64_t>(C->used, S->bytes + S->cache_bytes);
+  C->scenes.erase(scene);
+  return HPT_OK;
+}
+
+hpt_status hpt_cache_build(hpt_ctx *C, uint64_t scene, const hpt_cache_desc *cd) {
+  if (!C || !cd) return fail(HPT_EINVAL, "null argument");
+  if (cd->res < 1 || cd->res > 256 || cd->bins < 1 || cd->bins > 64 || cd->spb < 1 || cd->spb > 4096 ||
+      cd->max_bounces < 1 || cd->max_bounces > 31)
+    return fail(HPT_EINVAL, "cache parameters out of range");
+  uint64_t entries = (uint64_t)cd->res * cd->res * cd->res * cd->bins * cd->bins;
+  if (entries >= (1ull << 31) || cd->bins * cd->bins > 65536 || cd->spb > 65535)
+    return fail(HPT_EINVAL, "cache too large");
+  uint64_t id;
+  {
+    std::unique_lock<std::mutex> lk(C->mu);
+    Scene *S = find_scene(C, scene);
+    if (!S) return fail(HPT_ENOTFOUND, "unknown scene");
+    if (S->users > 0) return fail(HPT_EBUSY, "scene in use by a job");
+    (void)hipSetDevice(C->device);
+    size_t bytes = 3 * entries * sizeof(uint16_t);
+    if (S->cache) { C->release(S->cache, S->cache_bytes); S->cache = nullptr; S->cache_bytes = 0; }
+    if (C->used + bytes > C->budget) evict_grfs(C, bytes);
+    if (C->used + bytes > C->budget) return fail(HPT_EBUDGET, "cache does not fit the budget");
+    if (C->alloc((void **)&S->cache, bytes) != hipSuccess) return fail(HPT_ENOMEM, "cache allocation failed");
+    S->cache_bytes = bytes;
+    S->cache_desc = *cd;
+    // grid: bounds inflated by 1e-3 of the largest extent
+    double ext = std::max({S->hi[0] - S->lo[0], S->hi[1] - S->lo[1], S->hi[2] - S->lo[2]});
+    double pad = 1e-3 * ext;
+    SceneDev &h = S->host;
+    for (int a = 0; a < 3; ++a) {
+      h.cache_lo_d[a] = S->lo[a] - pad;
+      h.cache_hi_d[a] = S->hi[a] + pad;
+      h.cache_lo[a] = (float)h.cache_lo_d[a];
+      double w = h.cache_hi_d[a] - h.cache_lo_d[a];
+      h.cache_scale[a] = (float)(w > 0 ? cd->res / w : 0.0);
+    }
+    h.cache = nullptr;  // not used while it is being built
+    h.cache_res = cd->res; h.cache_bins = cd->bins;
+    if (hipMemcpy(S->dev, &h, sizeof(SceneDev), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(HPT_EDEVICE, "scene update failed");
+    auto J = std::make_unique<Job>();
+    J->id = id = C->next_id++;
+    J->scene = S;
+    J->cache_build = true;
+    JobDev &jd = J->host;
+    std::memset(&jd, 0, sizeof(jd));
+    jd.max_bounces = cd->max_bounces;
+    jd.seed = cd->seed;
+    jd.scene = S->dev;
+    jd.cache_out = S->cache;
+    jd.cache_res = cd->res; jd.cache_bins = cd->bins; jd.cache_spb = cd->spb;
+    jd.spp = 1;
+    jd.T = 1;
+    split_cache_units(J.get());
+    J->bytes = sizeof(JobDev);
+    J->t_submit = Clock::now();
+    S->users++;
+    C->queue.push_back(J.get());
+    C->jobs[id] = std::move(J);
+  }
+  C->cv.notify_all();
+  std::unique_lock<std::mutex> lk(C->mu);
+  Job *J = find_job(C, id);
+  C->cv.wait(lk, [&] { return J->state != JS_QUEUED && J->state != JS_RUNNING; });
+  hpt_status st = J->status;
+  std::string err = J->err;
+  Scene *S = find_scene(C, scene);
+  free_job_buffers(C, J);
+  C->jobs.erase(id);
+  if (st != HPT_OK) return fail(st, err);
+  if (S) {
+    S->host.cache = S->cache;
+    if (hipMemcpy(S->dev, &S->host, sizeof(SceneDev), hipMemcpyHostToDevice) != hipSuccess)
+      return fail(HPT_EDEVICE, "scene update failed");
+  }
+  return HPT_OK;
+}
+
+hpt_status hpt_cache_export(hpt_ctx *C, uint64_t scene, uint16_t *host, size_t n) {
+  if (!C || !host) return fail(HPT_EINVAL, "null argument");
+  std::lock_guard<std::mutex> g(C->mu);
+  Scene *S = find_scene(C, scene);
+  if (!S) return fail(HPT_ENOTFOUND, "unknown scene");
+  if (!S->host.cache) return fail(HPT_EINVAL, "scene has no radiance cache");
+  if (n * sizeof(uint16_t) != S->cache_bytes) return fail(HPT_EINVAL, "size mismatch");
+  if (hipMemcpy(host, S->cache, S->cache_bytes, hipMemcpyDeviceToHost) != hipSuccess)
+    return fail(HPT_EDEVICE, "copy failed");
+  return HPT_OK;
+}
+
+hpt_status hpt_trace_submit(hpt_ctx *C, uint64_t scene, const hpt_job_desc *d, void *d_field, uint64_t *out) {
+  if (!C || !d || !out) return fail(HPT_EINVAL, "null argument");
+  if (d->width == 0 || d->height == 0 || d->width > 32768 || d->height > 32768)
+    return fail(HPT_EINVAL, "bad SLM size");
+  if (!(d->pitch > 0) || !std::isfinite(d->pitch)) return fail(HPT_EINVAL, "bad pitch");
+  if (d->n_ch < 1 || d->n_ch > 3) return fail(HPT_EINVAL, "n_ch must be 1..3");
+  if (d->T < 1 || d->T > (uint32_t)kMaxT) return fail(HPT_EINVAL, "T must be 1..64");
+  if (d->spp < 1) return fail(HPT_EINVAL, "spp must be >= 1");
+  if (d->max_bounces < 1 || d->max_bounces > 31) return fail(HPT_EINVAL, "max_bounces must be 1..31");
+  if (d->phase_mode > HPT_PHASE_FP32) return fail(HPT_EINVAL, "bad phase mode");
+  for (uint32_t c = 0; c < d->n_ch; ++c) {
+    if (!(d->lambda[c] > 0) || !std::isfinite(d->lambda[c])) return fail(HPT_EINVAL, "bad wavelength");
+    if (!(d->lambda[c] / (2 * d->pitch) < 1.0)) return fail(HPT_EINVAL, "lambda/(2 pitch) must be < 1");
+    if (d->comp[c] > 2) return fail(HPT_EINVAL, "colour component must be 0..2");
+  }
+  if (d->grf_w < d->width || d->grf_h < d->height || d->grf_w > 4096 || d->grf_h > 4096)
+    return fail(HPT_EINVAL, "random-field grid must cover the SLM and be <= 4096");
+  uint32_t x0 = d->crop[0], y0 = d->crop[1], cw = d->crop[2], ch = d->crop[3];
+  if (cw == 0 || ch == 0) { x0 = 0; y0 = 0; cw = d->width; ch = d->height; }
+  if ((uint64_t)x0 + cw > d->width || (uint64_t)y0 + ch > d->height) return fail(HPT_EINVAL, "crop outside SLM");
+  uint32_t sb = d->spp_begin, se = d->spp_end;
+  if (sb == 0 && se == 0) se = d->spp;
+  if (!(sb < se) || se > d->spp) return fail(HPT_EINVAL, "empty or invalid sample range");
+  for (int k = 0; k < 12; ++k)
+    if (!std::isfinite(d->holo_from_world[k])) return fail(HPT_EINVAL, "non-finite transform");
+  double Ti[12];
+  if (!affine_inverse(d->holo_from_world, Ti)) return fail(HPT_EINVAL, "singular transform");
+  uint64_t n_paths = (uint64_t)d->n_ch * cw * ch * (se - sb);
+  if ((d->debug & 3u) && n_paths > (1ull << 22)) return fail(HPT_EINVAL, "per-path debug output limited to 2^22 paths");
+  std::unique_lock<std::mutex> lk(C->mu);
+  Scene *S = find_scene(C, scene);
+  if (!S) return fail(HPT_ENOTFOUND, "unknown scene");
+  if (d->use_cache && !S->host.cache) return fail(HPT_EINVAL, "use_cache needs hpt_cache_build first");
+  auto J = std::make_unique<Job>();
+  J->desc = *d;
+  J->scene = S;
+  JobDev &jd = J->host;
+  std::memset(&jd, 0, sizeof(jd));
+  jd.width = d->width; jd.height = d->height; jd.pitch = d->pitch;
+  jd.crop_x0 = x0; jd.crop_y0 = y0; jd.crop_w = cw; jd.crop_h = ch;
+  jd.n_ch = d->n_ch;
+  for (uint32_t c = 0; c < d->n_ch; ++c) {
+    jd.comp[c] = d->comp[c];
+    jd.lambda[c] = d->lambda[c];
+    jd.inv_lambda[c] = 1.0 / d->lambda[c];
+    jd.s_cone[c] = d->lambda[c] / (2.0 * d->pitch);
+    jd.lambda_f[c] = (float)jd.lambda[c];
+    jd.inv_lambda_f[c] = (float)jd.inv_lambda[c];
+    jd.s_cone_f[c] = (float)jd.s_cone[c];
+  }
+  jd.spp = d->spp; jd.max_bounces = d->max_bounces; jd.T = d->T; jd.phase_mode = d->phase_mode;
+  jd.random_phase = d->random_phase ? 1 : 0;
+  jd.use_cache = d->use_cache ? 1 : 0;
+  jd.cache_depth = d->cache_depth;
+  jd.debug = d->debug;
+  jd.seed = d->seed;
+  std::memcpy(jd.Tm, d->holo_from_world, sizeof(jd.Tm));
+  std::memcpy(jd.Ti, Ti, sizeof(jd.Ti));
+  static const double I[12] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0};
+  jd.identity_T = std::memcmp(I, d->holo_from_world, sizeof(I)) == 0 ? 1 : 0;
+  jd.grf_w = d->grf_w; jd.grf_h = d->grf_h;
+  jd.spp_lo = sb; jd.n_s = se - sb;
+  jd.scene = S->dev;
+  J->field_elems = (size_t)d->n_ch * d->T * cw * ch;
+  J->own_field = d_field == nullptr;
+  J->field = (float2 *)d_field;
+  if (d->debug & 1u) J->n_rec = n_paths;
+  if (d->debug & 2u) J->n_contrib = n_paths * d->T;
+  if (d->debug & 4u) J->n_sig = (size_t)d->n_ch * cw * ch;
+  J->bytes = (J->own_field ? J->field_elems * sizeof(float2) : 0) + J->n_rec * sizeof(hpt_path_record) +
+             J->n_contrib * sizeof(float2) + J->n_sig * 8 + sizeof(JobDev);
+  J->grf_bytes = grf_table_bytes(d->grf_w, d->grf_h, d->T) + grf_temp_bytes(d->grf_w, d->grf_h, d->T);
+  // the fixed part (batch buffers, scenes, caches) never shrinks; refuse what can never fit
+  uint64_t fixed = 0;
+  for (void *p : C->batch_bufs) (void)p;
+  fixed = (uint64_t)C->capacity * kBytesPerPath;
+  for (auto &kv : C->scenes) fixed += kv.second->bytes + kv.second->cache_bytes;
+  if (fixed + J->bytes + J->grf_bytes > C->budget) return fail(HPT_EBUDGET, "job can never fit the budget");
+  split_units(J.get());
+  J->id = C->next_id++;
+  J->t_submit = Clock::now();
+  S->users++;
+  *out = J->id;
+  C->queue.push_back(J.get());
+  C->jobs[J->id] = std::move(J);
+  lk.unlock();
+  C->cv.notify_all();
+  return HPT_OK;
+}
+
+hpt_status hpt_job_wait(hpt_ctx *C, uint64_t id, int64_t timeout_ms) {
+  if (!C) return fail(HPT_EINVAL, "null context");
+  std::unique_lock<std::mutex> lk(C->mu);
+  Job *J = find_job(C, id);
+  if (!J) return fail(HPT_ENOTFOUND, "unknown job");
+  auto done = [&] { return J->state == JS_DONE || J->state == JS_FAILED || J->state == JS_CANCELED; };
+  if (timeout_ms < 0) C->cv.wait(lk, done);
+  else if (!C->cv.wait_for(lk, std::chrono::milliseconds(timeout_ms), done))
+    return fail(HPT_ETIMEOUT, "job not finished");
+  if (J->status != HPT_OK) return fail(J->status, J->err);
+  return HPT_OK;
+}
+
+hpt_status hpt_job_stats_get(hpt_ctx *C, uint64_t id, hpt_job_stats *out) {
+  if (!C || !out) return fail(HPT_EINVAL, "null argument");
+  std::lock_guard<std::mutex> g(C->mu);
+  Job *J = find_job(C, id);
+  if (!J) return fail(HPT_ENOTFOUND, "unknown job");
+  *out = J->stats;
+  return HPT_OK;
+}
+
+static hpt_status copy_out(hpt_ctx *C, uint64_t id, int what, void *host, size_t n) {
+  if (!C || !host) return fail(HPT_EINVAL, "null argument");
+  std::lock_guard<std::mutex> g(C->mu);
+  Job *J = find_job(C, id);
+  if (!J) return fail(HPT_ENOTFOUND, "unknown job");
+  if (J->state != JS_DONE) return fail(J->state == JS_QUEUED || J->state == JS_RUNNING ? HPT_EBUSY : J->status,
+                                       "job has not finished successfully");
+  const void *src;
+  size_t bytes;
+  if (what == 0) { src = J->field; bytes = J->field_elems * sizeof(float2); if (n * 4 != bytes) return fail(HPT_EINVAL, "size mismatch"); }
+  else if (what == 1) { src = J->rec; bytes = J->n_rec * sizeof(hpt_path_record); if (n * sizeof(hpt_path_record) != bytes) return fail(HPT_EINVAL, "size mismatch"); }
+  else if (what == 2) { src = J->contrib; bytes = J->n_contrib * sizeof(float2); if (n * 4 != bytes) return fail(HPT_EINVAL, "size mismatch"); }
+  else { src = J->sigsum; bytes = J->n_sig * 8; if (n * 8 != bytes) return fail(HPT_EINVAL, "size mismatch"); }
+  if (!src) return fail(HPT_EINVAL, "the job has no such output (debug flags)");
+  (void)hipSetDevice(C->device);
+  if (hipMemcpy(host, src, bytes, hipMemcpyDeviceToHost) != hipSuccess) return fail(HPT_EDEVICE, "copy failed");
+  return HPT_OK;
+}
+
+hpt_status hpt_field_read(hpt_ctx *C, uint64_t id, float *host, size_t n) { return copy_out(C, id, 0, host, n); }
+hpt_status hpt_paths_read(hpt_ctx *C, uint64_t id, hpt_path_record *host, size_t n) {
+  return copy_out(C, id, 1, host, n);
+}
+hpt_status hpt_contrib_read(hpt_ctx *C, uint64_t id, float *host, size_t n) { return copy_out(C, id, 2, host, n); }
+hpt_status hpt_sigsum_read(hpt_ctx *C, uint64_t id, uint64_t *host, size_t n) {
+  return copy_out(C, id, 3, host, n);
+}
+
+hpt_status hpt_field_device_ptr(hpt_ctx *C, uint64_t id, void **out) {
+  if (!C || !out) return fail(HPT_EINVAL, "null argument");
+  std::lock_guard<std::mutex> g(C->mu);
+  Job *J = find_job(C, id);
+  if (!J) return fail(HPT_ENOTFOUND, "unknown job");
+  if (!J->field) return fail(HPT_EBUSY, "field not allocated yet");
+  *out = J->field;
+  return HPT_OK;
+}
+
+hpt_status hpt_job_cancel(hpt_ctx *C, uint64_t id) {
+  if (!C) return fail(HPT_EINVAL, "null context");
+  {
+    std::lock_guard<std::mutex> g(C->mu);
+    Job *J = find_job(C, id);
+    if (!J) return fail(HPT_ENOTFOUND, "unknown job");
+    J->cancel = true;
+  }
+  C->cv.notify_all();
+  return HPT_OK;
+}
+
+hpt_status hpt_job_release(hpt_ctx *C, uint64_t id) {
+  if (!C) return fail(HPT_EINVAL, "null context");
+  std::lock_guard<std::mutex> g(C->mu);
+  Job *J = find_job(C, id);
+  if (!J) return fail(HPT_ENOTFOUND, "unknown job");
+  if (J->state == JS_QUEUED || J->state == JS_RUNNING) return fail(HPT_EBUSY, "job still active");
+  (void)hipSetDevice(C->device);
+  free_job_buffers(C, J);
+  C->jobs.erase(id);
+  return HPT_OK;
+}
+
+hpt_status hpt_grf_read(hpt_ctx *C, uint32_t gw, uint32_t gh, uint32_t T, uint64_t seed, float *host, size_t n) {
+  if (!C || !host) return fail(HPT_EINVAL, "null argument");
+  if (gw < 1 || gh < 1 || gw > 4096 || gh > 4096 || T < 1 || T > (uint32_t)kMaxT)
+    return fail(HPT_EINVAL, "bad table size");
+  if (n != 2ull * gw * gh * T) return fail(HPT_EINVAL, "size mismatch");
+  std::lock_guard<std::mutex> g(C->mu);
+  (void)hipSetDevice(C->device);
+  Grf *G = nullptr;
+  hpt_status s = build_grf(C, gw, gh, T, seed, C->aux, &G);
+  if (s != HPT_OK) return s;
+  if (hipMemcpy(host, G->d, G->bytes, hipMemcpyDeviceToHost) != hipSuccess) return fail(HPT_EDEVICE, "copy failed");
+  return HPT_OK;
+}
+
+}  // extern "C"
