@@ -1,0 +1,232 @@
+"""Benchmark: path-samples/s and ms per 1920x1080 RGB T=24 hologram.
+
+Workload: a ~1M-triangle seeded procedural scene (displaced grids, 36
+displaced icosphere instances with Lambert/GGX/mirror/dielectric materials, a
+tilted mirror plane, a quad light) at depth 1-50 mm; SLM 1920x1080 at 8 um;
+RGB 638/520/450 nm; 256 samples per pixel; up to 6 interactions; T=24
+random-phase frames (Path Reuse); split-precision phase; ambient radiance
+cache 64^3 cells x 8x8 binary16 bins. One step = one full hologram (3 x 24
+fields) from device-resident scene, cache and random-phase tables into a
+torch-allocated device field.
+
+Prints one JSON line. Also reports, from the same run: the roofline of the
+traversal kernel (algorithmic FLOPs from a counting pass / event-measured
+duration), the FP64 oracle timed on host cores on a bounded crop, and the
+phase error of the GPU against the oracle on that crop.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+PEAK_FP32 = 157.3e12   # MI355X FP32 vector, FLOP/s
+PEAK_HBM = 8.0e12      # bytes/s
+# algorithmic FP32 FLOPs per traversal step (see the design notes): one BVH2
+# node = two ray/box slab tests; one primitive = one watertight triangle test
+FLOP_NODE = 48
+FLOP_PRIM = 46
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def workload(cfg):
+    import scenes
+    from scenes import jobs
+    if cfg == 2:
+        return scenes.scene_large(2), jobs.job_for_config(2), dict(res=64, bins=8, spb=4, max_bounces=6, seed=7)
+    if cfg == 1:
+        return scenes.scene_mid(1), jobs.job_for_config(1), None
+    return scenes.scene_tiny(0), jobs.job_for_config(0), None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-count", action="store_true")
+    ap.add_argument("--phase-mode", type=int, default=None)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs the hot path on a single MI355X "
+              "(multi-GPU sharding is a design note only); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if args.calib_copy:
+        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30}))
+        return
+    import paper_2606_14173_amd as hpt
+
+    sc, job, cdesc = workload(args.config)
+    if args.phase_mode is not None:
+        job["phase_mode"] = args.phase_mode
+    W, H = job["width"], job["height"]
+    n_ch, T, spp = len(job["lambdas"]), job["T"], job["spp"]
+    paths_per_step = n_ch * W * H * spp
+
+    ctx = hpt.Context(0)
+    t0 = time.time()
+    sid = ctx.upload_scene(sc)
+    info = ctx.scene_info(sid)
+    log("scene: %d prims, %d nodes, depth %d, BVH %.0f ms, upload total %.2f s"
+        % (info["n_prims"], info["n_nodes"], info["max_depth"], info["build_ms"], time.time() - t0))
+    if cdesc:
+        t0 = time.time()
+        ctx.build_cache(sid, **cdesc)
+        log("radiance cache %d^3 x %dx%d, %d paths/bin: %.2f s"
+            % (cdesc["res"], cdesc["bins"], cdesc["bins"], cdesc["spb"], time.time() - t0))
+    field = torch.empty((n_ch, T, H, W), dtype=torch.complex64, device="cuda:0")
+
+    def step():
+        jid = ctx.submit(sid, job, field=field)
+        ctx.wait(jid)
+        st = ctx.stats(jid)
+        ctx.release_job(jid)
+        return st
+
+    for i in range(args.warmup):
+        t0 = time.time()
+        step()
+        log("warmup %d: %.1f ms" % (i, 1e3 * (time.time() - t0)))
+    torch.cuda.synchronize()
+    ctx.profile(1)
+    ctx.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rays = 0
+    for i in range(args.steps):
+        st = step()
+        rays += st["rays"]
+        log("step %d: %.1f ms" % (i, st["run_ms"]))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kt = ctx.kernel_times()
+    ctx.profile(0)
+    ms_per_step = 1e3 * dt / args.steps
+    value = paths_per_step * args.steps / dt
+    assert torch.isfinite(torch.view_as_real(field)).all().item()
+    log("kernels: " + ", ".join("%s %.1f ms/%d" % (k, v["total_ms"], v["launches"])
+                                for k, v in kt.items() if isinstance(v, dict)))
+
+    # traversal work per ray from a counting pass (untimed, same workload)
+    roof = None
+    tr = kt["trace"]
+    if not args.no_count and tr["launches"]:
+        ctx.profile(2)
+        ctx.profile_reset()
+        step()
+        kc = ctx.kernel_times()
+        ctx.profile(0)
+        rays_c = max(kc["trace"]["items"], 1)
+        nv = kc["node_visits"] / rays_c
+        nt = kc["prim_tests"] / rays_c
+        flop_ray = FLOP_NODE * nv + FLOP_PRIM * nt
+        avg_ms = tr["total_ms"] / tr["launches"]
+        flop_launch = flop_ray * tr["items"] / tr["launches"]
+        achieved = flop_launch / (avg_ms * 1e-3) / 1e12
+        roof = {"kernel": "k_trace", "bound": "alu", "achieved": round(achieved, 3),
+                "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                "frac": round(achieved / (PEAK_FP32 / 1e12), 4), "traffic": None,
+                "avg_launch_ms": round(avg_ms, 4), "rays_per_launch": round(tr["items"] / tr["launches"]),
+                "node_visits_per_ray": round(nv, 2), "prim_tests_per_ray": round(nt, 2),
+                "flop_per_ray": round(flop_ray, 1),
+                "share_of_step": round(tr["total_ms"] / (1e3 * dt), 3)}
+        log("trace roofline: %s" % roof)
+
+    # CPU baseline: the FP64 oracle on a centred crop, timed on this host
+    cpu = None
+    acc = None
+    if not args.no_cpu_baseline:
+        import oracle
+        cw = 160 if args.config == 2 else 64
+        crop = ((W - cw) // 2, (H - cw) // 2, cw, cw)
+        cj = dict(job, crop=crop)
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+        threads = max(1, min(threads, 16, os.cpu_count()))
+        t0 = time.time()
+        grf = oracle.grf_table(job["grf_w"], job["grf_h"], T, job["grf_seed"])
+        os_ = oracle.OracleScene(sc)
+        ocache = oracle.OracleCache(os_, **cdesc) if cdesc else None
+        log("oracle set-up %.1f s" % (time.time() - t0))
+        if ocache is not None:  # fill the on-demand cache entries the crop uses (untimed)
+            t0 = time.time()
+            oracle.trace(os_, cj, grf=grf, cache=ocache, threads=threads)
+            log("oracle cache entries filled in %.1f s" % (time.time() - t0))
+        t0 = time.perf_counter()
+        oracle.trace(os_, cj, grf=grf, cache=ocache, threads=threads)
+        tcpu = time.perf_counter() - t0
+        n_cpu = n_ch * cw * cw * spp
+        cpu = {"value": round(n_cpu / tcpu, 1), "unit": "path-samples/s", "cores": threads,
+               "kind": "oracle",
+               "sample": "centred %dx%d crop of the same job (%d path-samples, all %d frames), "
+                         "%.1f s" % (cw, cw, n_cpu, T, tcpu)}
+        log("cpu baseline: %s" % cpu)
+        # accuracy of the GPU against the oracle on a 64x64 crop (per-path records)
+        aw = 64
+        acrop = ((W - aw) // 2, (H - aw) // 2, aw, aw)
+        aj = dict(job, crop=acrop)
+        Uo, reco, _ = oracle.trace(os_, aj, grf=grf, cache=ocache, records=True, threads=threads)
+        del grf
+        Ug, recg = ctx.trace(sid, aj, records=True)
+        match = recg["sig"] == reco["sig"]
+        img = match & (reco["amp"] != 0)
+        dphi = np.abs(np.angle(np.exp(2j * np.pi * (recg["rev"][img] - reco["rev"][img]))))
+        rms = float(np.sqrt(np.mean(np.abs(Uo) ** 2)))
+        acc = {"crop": list(acrop), "path_match": round(float(match.mean()), 6),
+               "phase_err_rad_p50": float(np.percentile(dphi, 50)) if dphi.size else 0.0,
+               "phase_err_rad_p99": float(np.percentile(dphi, 99)) if dphi.size else 0.0,
+               "phase_err_rad_max": float(dphi.max()) if dphi.size else 0.0,
+               "field_err_over_rms_max": float(np.abs(Ug - Uo).max() / rms) if rms > 0 else 0.0}
+        log("accuracy: %s" % acc)
+
+    names = {2: "1920x1080 RGB T=24 hologram, ~1M-triangle procedural scene, 256 spp, 6 bounces, "
+                "split phase, radiance cache 64^3x8x8",
+             1: "512x512 RGB T=8, ~58k triangles, 64 spp, 4 bounces, split phase",
+             0: "64x64 mono T=1, 3 spheres + quad light, 16 spp, 2 bounces, FP64 phase"}
+    out = {
+        "metric": "path-samples/s and ms per 1080p T=24 hologram at <=1e-3 rad phase error",
+        "value": round(value, 1),
+        "unit": "path-samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if job["phase_mode"] != 0 else "f64-phase",
+        "data": "synthetic",
+        "config": {"workload": names[args.config], "width": W, "height": H, "channels": n_ch,
+                   "spp": spp, "T": T, "max_bounces": job["max_bounces"],
+                   "phase_mode": ["fp64", "split", "fp32"][job["phase_mode"]],
+                   "triangles": int(len(sc["tri"])), "path_samples_per_step": paths_per_step,
+                   "rays_per_step": int(rays / max(args.steps, 1))},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "accuracy": acc,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()
