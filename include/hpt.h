@@ -202,6 +202,22 @@ typedef struct {
 } hpt_ctx_stats;
 hpt_status hpt_ctx_stats_get(hpt_ctx *ctx, hpt_ctx_stats *out);
 
+/* ---------------------------------------------------------------- profiling
+ * Level 1: HIP events around every kernel launch on the context stream,
+ * summed per kernel kind. Level 2: also counts BVH node visits and primitive
+ * tests in the traversal kernel (slower; for work accounting only). */
+enum { HPT_K_RAYGEN = 0, HPT_K_TRACE = 1, HPT_K_SHADE = 2, HPT_K_ACCUMULATE = 3,
+       HPT_K_CACHE_REDUCE = 4, HPT_K_KINDS = 5 };
+typedef struct {
+  uint64_t launches;  /* kernel launches timed */
+  uint64_t items;     /* rays (trace, shade), paths (raygen), pixel-units (accumulate) */
+  double total_ms;    /* sum of event-measured launch durations */
+} hpt_kernel_time;
+hpt_status hpt_profile_set(hpt_ctx *ctx, uint32_t level);
+/* out: HPT_K_KINDS entries; node_visits / prim_tests: level-2 counters (nullable). */
+hpt_status hpt_profile_get(hpt_ctx *ctx, hpt_kernel_time *out, uint64_t *node_visits, uint64_t *prim_tests);
+hpt_status hpt_profile_reset(hpt_ctx *ctx);
+
 #ifdef __cplusplus
 }
 #endif

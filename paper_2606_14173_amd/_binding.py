@@ -68,6 +68,12 @@ class CtxStats(C.Structure):
                 ("jobs_running", C.c_uint64)]
 
 
+class KernelTime(C.Structure):
+    _fields_ = [("launches", C.c_uint64), ("items", C.c_uint64), ("total_ms", C.c_double)]
+
+
+KERNEL_KINDS = ("raygen", "trace", "shade", "accumulate", "cache_reduce")
+
 PATH_RECORD = np.dtype([("sig", np.uint64), ("kind", np.int32), ("bP", np.int32),
                         ("first_gid", np.int32), ("n_hits", np.int32),
                         ("ell", np.float64), ("r", np.float64), ("A", np.float64),
@@ -98,6 +104,9 @@ SIGNATURES = {
     "hpt_job_release": (C.c_int, [_vp, _u64]),
     "hpt_grf_read": (C.c_int, [_vp, _u32, _u32, _u32, _u64, _vp, _sz]),
     "hpt_ctx_stats_get": (C.c_int, [_vp, C.POINTER(CtxStats)]),
+    "hpt_profile_set": (C.c_int, [_vp, _u32]),
+    "hpt_profile_get": (C.c_int, [_vp, C.POINTER(KernelTime), C.POINTER(_u64), C.POINTER(_u64)]),
+    "hpt_profile_reset": (C.c_int, [_vp]),
 }
 
 _LIB = None
@@ -286,6 +295,23 @@ class Context:
     def grf(self, gw, gh, T, seed):
         out = np.zeros((gh, gw, T), dtype=np.complex64)
         _check(self.lib.hpt_grf_read(self.h, gw, gh, T, seed, out.ctypes.data, out.size * 2))
+        return out
+
+    # profiling
+    def profile(self, level):
+        _check(self.lib.hpt_profile_set(self.h, level))
+
+    def profile_reset(self):
+        _check(self.lib.hpt_profile_reset(self.h))
+
+    def kernel_times(self):
+        arr = (KernelTime * len(KERNEL_KINDS))()
+        nv, nt = C.c_uint64(), C.c_uint64()
+        _check(self.lib.hpt_profile_get(self.h, arr, C.byref(nv), C.byref(nt)))
+        out = {k: dict(launches=arr[i].launches, items=arr[i].items, total_ms=arr[i].total_ms)
+               for i, k in enumerate(KERNEL_KINDS)}
+        out["node_visits"] = nv.value
+        out["prim_tests"] = nt.value
         return out
 
     def trace(self, sid, job, records=False, contrib=False, sigsum=False):

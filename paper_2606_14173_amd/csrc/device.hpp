@@ -65,6 +65,16 @@ __device__ __forceinline__ D3 to_d(F3 a) { return {a.x, a.y, a.z}; }
 // ------------------------------------------------------------------ traversal
 struct Hit { float t; int32_t gid; };
 
+// Read-only scene data addressed as global memory (address space 1), so the
+// compiler issues global loads (counted by vmcnt only) rather than flat loads.
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef const v4f __attribute__((address_space(1))) *GF4;
+__device__ __forceinline__ GF4 as_global(const float4 *p) { return (GF4)(const void *)p; }
+__device__ __forceinline__ float4 ld4(GF4 p) {
+  v4f v = *p;
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
 // Watertight ray/triangle test (Woop, Benthin, Wald, JCGT 2013) in FP32 with
 // per-ray shear constants; returns t in (tmin, tbest] or leaves best alone.
 struct RayPre {
@@ -158,56 +168,106 @@ __device__ __forceinline__ void box2(const RayPre &r, float4 a, float4 b, float4
   t0 = n0; t1 = n1;
 }
 
-// Closest hit in (tmin, inf), ties to the lower global id, skipping the
-// triangle `exclude`. Private stack of kStackMax entries.
-__device__ __forceinline__ Hit closest_hit(const SceneDev &S, F3 o, F3 d, float tmin, int32_t exclude) {
-  Hit best{INFINITY, -1};
-  if (S.n_nodes == 0) return best;
-  RayPre r = ray_pre(o, d);
-  int32_t stack[kStackMax];
-  int sp = 0;
-  int32_t node = 0;
-  const float4 *N = S.nodes;
-  const float4 *P = S.prims;
+__device__ __forceinline__ void leaf_test(const RayPre &r, GF4 P, int32_t node, float tmin,
+                                          int32_t exclude, Hit &best) {
+  uint32_t v = (uint32_t)(~node);
+  uint32_t first = v >> 3, cnt = (v & 7u) + 1u;
+  for (uint32_t k = 0; k < cnt; ++k) {
+    GF4 p = P + 3 * (size_t)(first + k);
+    float4 p0 = ld4(p), p1 = ld4(p + 1);
+    int32_t gid = __float_as_int(p0.w);
+    if (gid == exclude) continue;
+    float t;
+    bool h;
+    if (__float_as_int(p1.w) == 1) {
+      h = sph_hit(r, f3(p0.x, p0.y, p0.z), p1.x, tmin, best.t, t);
+    } else {
+      float4 p2 = ld4(p + 2);
+      h = tri_hit(r, f3(p0.x, p0.y, p0.z), f3(p1.x, p1.y, p1.z), f3(p2.x, p2.y, p2.z), tmin, best.t, t);
+    }
+    if (h && (t < best.t || gid < best.gid)) { best.t = t; best.gid = gid; }
+  }
+}
+
+// Traversal state of one lane: closest hit in (tmin, inf), ties to the
+// lower global id, skipping the triangle `exclude`. The stack lives in LDS,
+// one column per lane (consecutive entries `stride` ints apart, so lanes
+// never share a bank).
+struct Trav {
+  RayPre r;
+  float tmin;
+  int32_t exclude;
+  int32_t node;   // next node: >= 0 inner, < 0 leaf, kDone: finished
+  int sp;
+  Hit best;
+};
+constexpr int32_t kDone = 0x7FFFFFFF;
+
+__device__ __forceinline__ void trav_init(Trav &T, F3 o, F3 d, float tmin, int32_t exclude, bool empty) {
+  T.r = ray_pre(o, d);
+  T.tmin = tmin;
+  T.exclude = exclude;
+  T.node = empty ? kDone : 0;
+  T.sp = 0;
+  T.best.t = INFINITY;
+  T.best.gid = -1;
+}
+
+// Advance this lane by one round: descend inner nodes, postponing the first
+// leaf reached and continuing with the next stack entry, until every active
+// lane of the wave holds a leaf or has nothing left to descend; then test
+// the postponed leaf (Aila and Laine's speculative "while-while", which keeps
+// lanes descending instead of idling while others look for a leaf). Leaves
+// may be tested out of front-to-back order; the closest-hit and tie rules
+// make the result independent of the order. COUNT adds node visits and
+// primitive tests to nv / nt.
+template <bool COUNT>
+__device__ __forceinline__ void trav_step(Trav &T, GF4 N, GF4 P, int32_t *stack, uint32_t stride, uint32_t &nv,
+                                          uint32_t &nt) {
+  int32_t node = T.node;
+  int sp = T.sp;
+  bool has_leaf = false;
+  int32_t leaf = 0;
   for (;;) {
-    if (node >= 0) {
-      float4 a = N[4 * node], b = N[4 * node + 1], c = N[4 * node + 2];
-      int4 lk = *reinterpret_cast<const int4 *>(&N[4 * node + 3]);
+    if (node >= 0 && node != kDone) {
+      if (COUNT) ++nv;
+      float4 a = ld4(N + 4 * node), b = ld4(N + 4 * node + 1), c = ld4(N + 4 * node + 2),
+             l4 = ld4(N + 4 * node + 3);
+      int32_t c0 = __float_as_int(l4.x), c1 = __float_as_int(l4.y);
       float t0, t1;
       bool h0, h1;
-      box2(r, a, b, c, tmin, best.t, t0, t1, h0, h1);
+      box2(T.r, a, b, c, T.tmin, T.best.t, t0, t1, h0, h1);
       if (h0 && h1) {
-        int32_t nearc = t0 <= t1 ? lk.x : lk.y, farc = t0 <= t1 ? lk.y : lk.x;
-        stack[sp++] = farc;
-        node = nearc;
-        continue;
-      }
-      if (h0) { node = lk.x; continue; }
-      if (h1) { node = lk.y; continue; }
-    } else {
-      uint32_t v = (uint32_t)(~node);
-      uint32_t first = v >> 3, cnt = (v & 7u) + 1u;
-      for (uint32_t k = 0; k < cnt; ++k) {
-        const float4 *p = P + 3 * (size_t)(first + k);
-        float4 p0 = p[0], p1 = p[1];
-        int32_t gid = __float_as_int(p0.w);
-        if (gid == exclude) continue;
-        float t;
-        bool h;
-        if (__float_as_int(p1.w) == 1) {
-          h = sph_hit(r, f3(p0.x, p0.y, p0.z), p1.x, tmin, best.t, t);
-        } else {
-          float4 p2 = p[2];
-          h = tri_hit(r, f3(p0.x, p0.y, p0.z), f3(p1.x, p1.y, p1.z), f3(p2.x, p2.y, p2.z), tmin,
-                      best.t, t);
-        }
-        if (h && (t < best.t || gid < best.gid)) { best.t = t; best.gid = gid; }
+        bool first0 = t0 <= t1;
+        stack[sp * stride] = first0 ? c1 : c0;
+        ++sp;
+        node = first0 ? c0 : c1;
+      } else if (h0) {
+        node = c0;
+      } else if (h1) {
+        node = c1;
+      } else {
+        node = sp > 0 ? stack[--sp * stride] : kDone;
       }
     }
-    if (sp == 0) break;
-    node = stack[--sp];
+    if (node < 0 && !has_leaf) {  // postpone the leaf, keep descending
+      has_leaf = true;
+      leaf = node;
+      node = sp > 0 ? stack[--sp * stride] : kDone;
+    }
+    bool ready = has_leaf || node == kDone || node < 0;
+    if (__all(ready)) break;
   }
-  return best;
+  if (has_leaf) {
+    if (COUNT) nt += ((uint32_t)(~leaf) & 7u) + 1u;
+    leaf_test(T.r, P, leaf, T.tmin, T.exclude, T.best);
+  } else if (node < 0) {
+    if (COUNT) nt += ((uint32_t)(~node) & 7u) + 1u;
+    leaf_test(T.r, P, node, T.tmin, T.exclude, T.best);
+    node = sp > 0 ? stack[--sp * stride] : kDone;
+  }
+  T.node = node;
+  T.sp = sp;
 }
 
 // ------------------------------------------------------------------ FP64 refinement

@@ -9,11 +9,19 @@ namespace hpt {
 
 constexpr int kMaxT = 64;
 constexpr int kStackMax = 64;        // BVH depth bound enforced by the builder
+constexpr int kRaysPerWave = 512;    // rays a traversal wave owns (lanes refill from them)
 constexpr float kTmin = 1e-7f;       // self-intersection guard (metres)
 constexpr double kTminD = 1e-7;
 
 enum Stage : uint32_t { STAGE_PREFIX = 0, STAGE_TAIL = 1 };
 enum UnitKind : uint32_t { UNIT_HOLO = 0, UNIT_CACHE = 1 };
+
+// Lanes per pixel in the accumulation: the next power of two >= T.
+__host__ __device__ inline uint32_t frame_group(uint32_t T) {
+  uint32_t g = 1;
+  while (g < T) g <<= 1;
+  return g;
+}
 
 // Path events hashed into the signature (same codes as the FP64 reference).
 enum : uint32_t { EV_MIRROR = 1, EV_DIEL_REFL = 2, EV_DIEL_REFR = 3, EV_LAMBERT = 4, EV_GGX = 5,
@@ -82,6 +90,7 @@ struct UnitDev {
   uint32_t p_lo, p_n, s_lo, s_n;
   uint32_t slot_base, acc_base;
   const JobDev *job;
+  const SceneDev *scene;
 };
 
 // Path state, records and queues of one batch (structure of arrays).
@@ -104,6 +113,8 @@ struct BatchDev {
   float *q_t[2];
   int32_t *q_gid[2];
   uint32_t *counters;        // [0], [1]: queue lengths; [2]: rays traced
+  unsigned long long *work;  // [0] node visits, [1] primitive tests (counting traversal)
+  const SceneDev *scene_uniform;  // the one scene of every unit, or null for mixed batches
 };
 
 }  // namespace hpt

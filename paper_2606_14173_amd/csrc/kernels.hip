@@ -169,20 +169,84 @@ __global__ void __launch_bounds__(kBlock) k_raygen(BatchDev B) {
 }
 
 // ------------------------------------------------------------------ trace
+// FP32 closest hit for every ray of queue q. Each wave owns kRaysPerWave
+// consecutive queue entries; a lane that finishes its ray takes the next one
+// of the wave's range, so lanes do not idle while the wave's longest ray
+// finishes. DEPTH: LDS stack entries per lane (>= the deepest inner-node
+// path of the batch's BVHs).
+template <bool COUNT, int DEPTH>
 __global__ void __launch_bounds__(kBlock) k_trace(BatchDev B, int q) {
-  uint32_t n = B.counters[q];
+  __shared__ int32_t stack[DEPTH * kBlock];
+#ifdef HPT_STAGE_RESULTS
+  __shared__ float2 res[kBlock / 64][kRaysPerWave];
+#endif
+  const uint32_t n = B.counters[q];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     B.counters[q ^ 1] = 0;
     B.counters[2] += n;
   }
-  uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t i = xcd_block() * blockDim.x + threadIdx.x; i < n; i += stride) {
-    uint32_t slot = B.q_slot[q][i];
-    const SceneDev &S = *B.units[B.s_unit[slot]].job->scene;
-    float4 r0 = B.q_ray[q][2 * i], r1 = B.q_ray[q][2 * i + 1];
-    Hit h = closest_hit(S, f3(r0.x, r0.y, r0.z), f3(r1.x, r1.y, r1.z), r0.w, __float_as_int(r1.w));
-    B.q_t[q][i] = h.t;
-    B.q_gid[q][i] = h.gid;
+  const uint32_t wave = (xcd_block() * blockDim.x + threadIdx.x) / 64u;
+  const uint32_t begin = wave * (uint32_t)kRaysPerWave;
+  uint32_t next = begin;
+  if (next >= n) return;
+  const uint32_t end = min(n, next + (uint32_t)kRaysPerWave);
+  const uint32_t lane = __lane_id();
+  int32_t *st = stack + threadIdx.x;
+  uint32_t nv = 0, nt = 0;
+  int64_t i = -1;  // queue entry of this lane's ray, -1: none
+  Trav T;
+  const SceneDev *S = B.scene_uniform;
+  GF4 N = as_global(S ? S->nodes : nullptr), P = as_global(S ? S->prims : nullptr);
+  uint32_t nn = S ? S->n_nodes : 0;
+  for (;;) {
+    // refill idle lanes from the wave's range, in lane order
+    unsigned long long need = __ballot(i < 0 && next < end);
+    if (need) {
+      if (i < 0) {
+        uint32_t k = next + (uint32_t)__popcll(need & ((1ull << lane) - 1ull));
+        if (k < end) {
+          i = k;
+          uint32_t slot = B.q_slot[q][k];
+          if (!B.scene_uniform) {
+            S = B.units[B.s_unit[slot]].scene;
+            N = as_global(S->nodes); P = as_global(S->prims); nn = S->n_nodes;
+          }
+          float4 r0 = B.q_ray[q][2 * k], r1 = B.q_ray[q][2 * k + 1];
+          trav_init(T, f3(r0.x, r0.y, r0.z), f3(r1.x, r1.y, r1.z), r0.w, __float_as_int(r1.w), nn == 0);
+        }
+      }
+      next += (uint32_t)__popcll(need);
+    }
+    if (!__any(i >= 0)) break;
+    if (i >= 0) {
+      if (T.node != kDone) trav_step<COUNT>(T, N, P, st, kBlock, nv, nt);
+      if (T.node == kDone) {
+#ifdef HPT_STAGE_RESULTS
+        res[threadIdx.x / 64u][i - begin] = make_float2(T.best.t, __int_as_float(T.best.gid));
+#else
+        B.q_t[q][i] = T.best.t;
+        B.q_gid[q][i] = T.best.gid;
+#endif
+        i = -1;
+      }
+    }
+  }
+#ifdef HPT_STAGE_RESULTS
+  for (uint32_t k = begin + lane; k < end; k += 64) {
+    float2 v = res[threadIdx.x / 64u][k - begin];
+    B.q_t[q][k] = v.x;
+    B.q_gid[q][k] = __float_as_int(v.y);
+  }
+#endif
+  if (COUNT) {
+    for (int off = 32; off > 0; off >>= 1) {
+      nv += __shfl_xor(nv, off);
+      nt += __shfl_xor(nt, off);
+    }
+    if (lane == 0 && (nv | nt)) {
+      atomicAdd(&B.work[0], (unsigned long long)nv);
+      atomicAdd(&B.work[1], (unsigned long long)nt);
+    }
   }
 }
 
@@ -477,12 +541,13 @@ __global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
 }
 
 // ------------------------------------------------------------------ accumulate
-// s8-s9 and Path Reuse: each thread owns one pixel of a unit, walks the
-// unit's samples in order and adds A W exp(i(k r + phi_t(Q))) / spp to the
-// frames, TB at a time, then adds its partial sums to the field. Only the
-// random-field phase depends on the frame; amplitude, weight and k r are
-// computed once per path and frame block.
-template <int TB, bool F64>
+// s8-s9 and Path Reuse. A group of G = frame_group(T) consecutive lanes owns
+// one pixel of a unit; lane t of the group owns frame t. The group walks the
+// unit's samples in order; for each path it forms A W exp(i k r) / spp once
+// (the same value in every lane) and lane t multiplies it by the unit phasor
+// of frame t at Q, so the T frames of a texel are read by consecutive lanes
+// from consecutive addresses. Partial sums are added to the field at the end.
+template <bool F64>
 __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
   uint32_t idx = xcd_block() * blockDim.x + threadIdx.x;
   if (idx >= B.n_acc) return;
@@ -491,31 +556,25 @@ __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
   if (U.kind != UNIT_HOLO) return;
   const JobDev &J = *U.job;
   if (F64 != (J.phase_mode == HPT_PHASE_FP64)) return;
-  uint32_t p_local = idx - U.acc_base;
+  const uint32_t T = J.T, G = frame_group(T);
+  uint32_t local = idx - U.acc_base;
+  uint32_t p_local = local / G, t = local - p_local * G;
+  if (t >= T) return;
   uint32_t p = U.p_lo + p_local;
   uint32_t cx = p % J.crop_w, cy = p / J.crop_w;
   using R = typename std::conditional<F64, double, float>::type;
-  const uint32_t T = J.T, gw = J.grf_w, gh = J.grf_h;
-  const float2 *G = J.grf;
+  const uint32_t gw = J.grf_w, gh = J.grf_h;
+  const float2 *G2 = J.grf + t;
   const size_t plane = (size_t)J.crop_h * J.crop_w;
-  float2 *F = J.field + (size_t)U.ch * T * plane + (size_t)cy * J.crop_w + cx;
+  R ar = 0, ai = 0;
   unsigned long long sigsum = 0;
-  for (uint32_t t0 = 0; t0 < T; t0 += TB) {
-    const uint32_t nt = T - t0 < (uint32_t)TB ? T - t0 : (uint32_t)TB;
-    R ar[TB], ai[TB];
-#pragma unroll
-    for (int t = 0; t < TB; ++t) { ar[t] = 0; ai[t] = 0; }
-    for (uint32_t s = 0; s < U.s_n; ++s) {
-      uint32_t slot = U.slot_base + s * U.p_n + p_local;
-      if ((J.debug & 4u) && t0 == 0) sigsum += B.s_sig[slot];
-      float amp = B.r_amp[slot];
-      if (amp == 0.f) {
-        if (J.debug & 2u) {
-          size_t base = rec_index(J, U, p_local, s) * T + t0;
-          for (uint32_t t = 0; t < nt; ++t) J.contrib[base + t] = make_float2(0.f, 0.f);
-        }
-        continue;
-      }
+  const bool dbg_c = (J.debug & 2u) != 0, dbg_s = (J.debug & 4u) != 0 && t == 0;
+  for (uint32_t s = 0; s < U.s_n; ++s) {
+    uint32_t slot = U.slot_base + s * U.p_n + p_local;
+    if (dbg_s) sigsum += B.s_sig[slot];
+    float amp = B.r_amp[slot];
+    R cr = 0, ci = 0;
+    if (amp != 0.f) {
       R br, bi;
       if (F64) {
         double x = B.r_r64[slot] * J.inv_lambda[U.ch];
@@ -533,45 +592,27 @@ __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
         uint32_t i0 = tex & 0xFFFFu, j0 = tex >> 16;
         uint32_t i1 = i0 + 1 == gw ? 0 : i0 + 1, j1 = j0 + 1 == gh ? 0 : j0 + 1;
         float fx = B.r_fx[slot], fy = B.r_fy[slot];
+        float2 a = G2[((size_t)j0 * gw + i0) * T], bq = G2[((size_t)j0 * gw + i1) * T];
+        float2 c = G2[((size_t)j1 * gw + i0) * T], d = G2[((size_t)j1 * gw + i1) * T];
         float w00 = (1.f - fx) * (1.f - fy), w10 = fx * (1.f - fy), w01 = (1.f - fx) * fy, w11 = fx * fy;
-        const float2 *g00 = G + ((size_t)j0 * gw + i0) * T + t0, *g10 = G + ((size_t)j0 * gw + i1) * T + t0;
-        const float2 *g01 = G + ((size_t)j1 * gw + i0) * T + t0, *g11 = G + ((size_t)j1 * gw + i1) * T + t0;
-#pragma unroll
-        for (int t = 0; t < TB; ++t) {
-          if ((uint32_t)t < nt) {
-            float2 a = g00[t], bq = g10[t], c = g01[t], d = g11[t];
-            float zr = w00 * a.x + w10 * bq.x + w01 * c.x + w11 * d.x;
-            float zi = w00 * a.y + w10 * bq.y + w01 * c.y + w11 * d.y;
-            float m2 = zr * zr + zi * zi;
-            float inv = m2 > 0.f ? rsqrtf(m2) : 0.f;
-            R pr = m2 > 0.f ? (R)(zr * inv) : (R)1, pi = (R)(zi * inv);
-            R cr = br * pr - bi * pi, ci = br * pi + bi * pr;
-            ar[t] += cr; ai[t] += ci;
-            if (J.debug & 2u)
-              J.contrib[rec_index(J, U, p_local, s) * T + t0 + t] = make_float2((float)cr, (float)ci);
-          }
-        }
+        float zr = w00 * a.x + w10 * bq.x + w01 * c.x + w11 * d.x;
+        float zi = w00 * a.y + w10 * bq.y + w01 * c.y + w11 * d.y;
+        float m2 = zr * zr + zi * zi;
+        float inv = m2 > 0.f ? rsqrtf(m2) : 0.f;
+        R pr = m2 > 0.f ? (R)(zr * inv) : (R)1, pi = (R)(zi * inv);
+        cr = br * pr - bi * pi; ci = br * pi + bi * pr;
       } else {
-#pragma unroll
-        for (int t = 0; t < TB; ++t) {
-          if ((uint32_t)t < nt) {
-            ar[t] += br; ai[t] += bi;
-            if (J.debug & 2u)
-              J.contrib[rec_index(J, U, p_local, s) * T + t0 + t] = make_float2((float)br, (float)bi);
-          }
-        }
+        cr = br; ci = bi;
       }
+      ar += cr; ai += ci;
     }
-#pragma unroll
-    for (int t = 0; t < TB; ++t) {
-      if ((uint32_t)t < nt) {
-        float2 v = F[(t0 + t) * plane];
-        v.x += (float)ar[t]; v.y += (float)ai[t];
-        F[(t0 + t) * plane] = v;
-      }
-    }
+    if (dbg_c) J.contrib[rec_index(J, U, p_local, s) * T + t] = make_float2((float)cr, (float)ci);
   }
-  if (J.debug & 4u) J.sigsum[(size_t)U.ch * plane + (size_t)cy * J.crop_w + cx] += sigsum;
+  float2 *F = J.field + ((size_t)U.ch * T + t) * plane + (size_t)cy * J.crop_w + cx;
+  float2 v = *F;
+  v.x += (float)ar; v.y += (float)ai;
+  *F = v;
+  if (dbg_s) J.sigsum[(size_t)U.ch * plane + (size_t)cy * J.crop_w + cx] += sigsum;
 }
 
 // Mean radiance of each cache entry over its paths, rounded to binary16.
@@ -685,26 +726,34 @@ hipError_t launch_raygen(const BatchDev &B, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_bounce(const BatchDev &B, int q, hipStream_t st) {
-  uint32_t g = round8(grid_for(B.n_paths));
-  hipLaunchKernelGGL(k_trace, dim3(g), dim3(kBlock), 0, st, B, q);
+template <int D>
+static void trace_launch(const BatchDev &B, int q, bool count, hipStream_t st) {
+  // one wave per kRaysPerWave rays of the largest possible queue
+  uint64_t waves = ((uint64_t)B.n_paths + kRaysPerWave - 1) / kRaysPerWave;
+  uint32_t g = round8((uint32_t)((waves * 64 + kBlock - 1) / kBlock));
+  if (count) hipLaunchKernelGGL((k_trace<true, D>), dim3(g), dim3(kBlock), 0, st, B, q);
+  else hipLaunchKernelGGL((k_trace<false, D>), dim3(g), dim3(kBlock), 0, st, B, q);
+}
+
+hipError_t launch_trace(const BatchDev &B, int q, bool count, uint32_t depth, hipStream_t st) {
+  // depth = levels including the leaf level; the stack holds one entry per inner level
+  if (depth <= 17) trace_launch<16>(B, q, count, st);
+  else if (depth <= 25) trace_launch<24>(B, q, count, st);
+  else if (depth <= 33) trace_launch<32>(B, q, count, st);
+  else trace_launch<kStackMax>(B, q, count, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_shade(const BatchDev &B, int q, hipStream_t st) {
   hipLaunchKernelGGL(k_shade, dim3(grid_for(B.n_paths)), dim3(kBlock), 0, st, B, q);
   return hipGetLastError();
 }
 
-// tb: frames per pass (1, 8 or 24); one launch per precision present in the batch.
-hipError_t launch_accumulate(const BatchDev &B, uint32_t tb, bool has_f64, bool has_f32, hipStream_t st) {
+// One launch per precision present in the batch.
+hipError_t launch_accumulate(const BatchDev &B, bool has_f64, bool has_f32, hipStream_t st) {
   uint32_t g = round8(grid_for(B.n_acc));
-  if (has_f32) {
-    if (tb >= 24) hipLaunchKernelGGL((k_accumulate<24, false>), dim3(g), dim3(kBlock), 0, st, B);
-    else if (tb >= 8) hipLaunchKernelGGL((k_accumulate<8, false>), dim3(g), dim3(kBlock), 0, st, B);
-    else hipLaunchKernelGGL((k_accumulate<1, false>), dim3(g), dim3(kBlock), 0, st, B);
-  }
-  if (has_f64) {
-    if (tb >= 24) hipLaunchKernelGGL((k_accumulate<24, true>), dim3(g), dim3(kBlock), 0, st, B);
-    else if (tb >= 8) hipLaunchKernelGGL((k_accumulate<8, true>), dim3(g), dim3(kBlock), 0, st, B);
-    else hipLaunchKernelGGL((k_accumulate<1, true>), dim3(g), dim3(kBlock), 0, st, B);
-  }
+  if (has_f32) hipLaunchKernelGGL(k_accumulate<false>, dim3(g), dim3(kBlock), 0, st, B);
+  if (has_f64) hipLaunchKernelGGL(k_accumulate<true>, dim3(g), dim3(kBlock), 0, st, B);
   return hipGetLastError();
 }
 

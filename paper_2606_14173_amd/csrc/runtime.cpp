@@ -146,6 +146,12 @@ struct hpt_ctx {
   BatchDev batch{};
   UnitDev *d_units = nullptr, *h_units = nullptr;
   uint64_t batches = 0, jobs_done = 0;
+  // profiling (guarded by mu; events used by the scheduler thread only)
+  uint32_t profile = 0;
+  static constexpr int kEvents = 160;
+  hipEvent_t pev[kEvents] = {};
+  hpt_kernel_time ktime[HPT_K_KINDS] = {};
+  uint64_t node_visits = 0, prim_tests = 0;
 
   hipError_t alloc(void **p, size_t bytes) {
     hipError_t e = hipMalloc(p, bytes ? bytes : 16);
@@ -355,49 +361,83 @@ std::vector<Picked> pick_batch(hpt_ctx *C) {
 }
 
 // Run one batch on the context stream (lock not held).
-hpt_status run_batch(hpt_ctx *C, const std::vector<Picked> &P, double &gpu_ms, uint64_t &rays) {
-  uint32_t slot = 0, acc = 0, max_b = 0, max_T = 1;
+hpt_status run_batch(hpt_ctx *C, const std::vector<Picked> &P, uint32_t profile, double &gpu_ms,
+                     uint64_t &rays, hpt_kernel_time *kt, uint64_t *work) {
+  uint32_t slot = 0, acc = 0, max_b = 0, max_depth = 0;
   bool has_f64 = false, has_f32 = false, has_holo = false, has_cache = false;
   for (size_t k = 0; k < P.size(); ++k) {
     const Unit &u = P[k].job->units[P[k].unit];
     UnitDev &d = C->h_units[k];
     d.kind = u.kind; d.ch = u.ch; d.p_lo = u.p_lo; d.p_n = u.p_n; d.s_lo = u.s_lo; d.s_n = u.s_n;
-    d.slot_base = slot; d.acc_base = acc; d.job = P[k].job->dev;
-    slot += u.p_n * u.s_n;
-    acc += u.p_n;
+    d.slot_base = slot; d.acc_base = acc; d.job = P[k].job->dev; d.scene = P[k].job->scene->dev;
+    max_depth = std::max(max_depth, P[k].job->scene->info.max_depth);
     const JobDev &J = P[k].job->host;
+    slot += u.p_n * u.s_n;
+    acc += u.kind == UNIT_HOLO ? u.p_n * frame_group(J.T) : u.p_n;
     max_b = std::max(max_b, J.max_bounces);
     if (u.kind == UNIT_HOLO) {
       has_holo = true;
-      max_T = std::max(max_T, J.T);
       if (J.phase_mode == HPT_PHASE_FP64) has_f64 = true; else has_f32 = true;
     } else {
       has_cache = true;
     }
   }
   BatchDev B = C->batch;
+  B.scene_uniform = P.empty() ? nullptr : P[0].job->scene->dev;
+  for (auto &p : P)
+    if (p.job->scene->dev != B.scene_uniform) B.scene_uniform = nullptr;
   B.units = C->d_units;
   B.n_units = (uint32_t)P.size();
   B.n_paths = slot;
   B.n_acc = acc;
-  hipError_t e = hipMemcpyAsync(C->d_units, C->h_units, P.size() * sizeof(UnitDev), hipMemcpyHostToDevice,
-                                C->stream);
+  // event pairs around each launch when profiling
+  int ne = 0;
+  int seg_kind[hpt_ctx::kEvents / 2];
+  hipError_t e = hipSuccess;
+  auto timed = [&](int kind, auto &&launch) {
+    if (e != hipSuccess) return;
+    if (profile && ne + 2 <= hpt_ctx::kEvents) {
+      e = hipEventRecord(C->pev[ne], C->stream);
+      if (e == hipSuccess) e = launch();
+      if (e == hipSuccess) e = hipEventRecord(C->pev[ne + 1], C->stream);
+      seg_kind[ne / 2] = kind;
+      ne += 2;
+    } else {
+      e = launch();
+    }
+  };
+  e = hipMemcpyAsync(C->d_units, C->h_units, P.size() * sizeof(UnitDev), hipMemcpyHostToDevice, C->stream);
   if (e == hipSuccess) e = hipMemsetAsync(B.counters, 0, 4 * sizeof(uint32_t), C->stream);
+  if (e == hipSuccess && profile >= 2) e = hipMemsetAsync(B.work, 0, 2 * sizeof(unsigned long long), C->stream);
   if (e == hipSuccess) e = hipEventRecord(C->ev0, C->stream);
-  if (e == hipSuccess) e = launch_raygen(B, C->stream);
-  for (uint32_t it = 0; e == hipSuccess && it <= max_b; ++it) e = launch_bounce(B, (int)(it & 1u), C->stream);
-  if (e == hipSuccess && has_holo) {
-    uint32_t tb = max_T >= 24 ? 24 : (max_T >= 8 ? 8 : 1);
-    e = launch_accumulate(B, tb, has_f64, has_f32, C->stream);
+  timed(HPT_K_RAYGEN, [&] { return launch_raygen(B, C->stream); });
+  for (uint32_t it = 0; it <= max_b; ++it) {
+    int q = (int)(it & 1u);
+    timed(HPT_K_TRACE, [&] { return launch_trace(B, q, profile >= 2, max_depth, C->stream); });
+    timed(HPT_K_SHADE, [&] { return launch_shade(B, q, C->stream); });
   }
-  if (e == hipSuccess && has_cache) e = launch_cache_reduce(B, C->stream);
+  if (has_holo) timed(HPT_K_ACCUMULATE, [&] { return launch_accumulate(B, has_f64, has_f32, C->stream); });
+  if (has_cache) timed(HPT_K_CACHE_REDUCE, [&] { return launch_cache_reduce(B, C->stream); });
   if (e == hipSuccess) e = hipEventRecord(C->ev1, C->stream);
   if (e == hipSuccess) e = hipEventSynchronize(C->ev1);
   uint32_t cnt[4] = {0, 0, 0, 0};
   if (e == hipSuccess) e = hipMemcpy(cnt, B.counters, sizeof(cnt), hipMemcpyDeviceToHost);
+  if (e == hipSuccess && profile >= 2) e = hipMemcpy(work, B.work, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost);
   float ms = 0.f;
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, C->ev0, C->ev1);
+  for (int k = 0; e == hipSuccess && k < ne; k += 2) {
+    float m = 0.f;
+    e = hipEventElapsedTime(&m, C->pev[k], C->pev[k + 1]);
+    hpt_kernel_time &t = kt[seg_kind[k / 2]];
+    t.launches++;
+    t.total_ms += m;
+  }
   if (e != hipSuccess) return fail(HPT_EDEVICE, std::string("batch failed: ") + hipGetErrorString(e));
+  kt[HPT_K_RAYGEN].items += profile ? slot : 0;
+  kt[HPT_K_TRACE].items += profile ? cnt[2] : 0;
+  kt[HPT_K_SHADE].items += profile ? cnt[2] : 0;
+  kt[HPT_K_ACCUMULATE].items += (profile && has_holo) ? slot : 0;
+  kt[HPT_K_CACHE_REDUCE].items += (profile && has_cache) ? slot : 0;
   gpu_ms = ms;
   rays = cnt[2];
   return HPT_OK;
@@ -448,13 +488,22 @@ void scheduler(hpt_ctx *C) {
     if (P.empty()) continue;
     for (auto &p : P)
       if (!p.job->started) { p.job->started = true; p.job->t_start = Clock::now(); }
+    uint32_t profile = C->profile;
     lk.unlock();
     double gpu_ms = 0.0;
-    uint64_t rays = 0;
-    hpt_status s = run_batch(C, P, gpu_ms, rays);
+    uint64_t rays = 0, work[2] = {0, 0};
+    hpt_kernel_time kt[HPT_K_KINDS] = {};
+    hpt_status s = run_batch(C, P, profile, gpu_ms, rays, kt, work);
     std::string err = s == HPT_OK ? std::string() : g_err;
     lk.lock();
     C->batches++;
+    for (int k = 0; k < HPT_K_KINDS; ++k) {
+      C->ktime[k].launches += kt[k].launches;
+      C->ktime[k].items += kt[k].items;
+      C->ktime[k].total_ms += kt[k].total_ms;
+    }
+    C->node_visits += work[0];
+    C->prim_tests += work[1];
     uint64_t total = 0;
     for (auto &p : P) total += (uint64_t)p.job->units[p.unit].p_n * p.job->units[p.unit].s_n;
     for (auto &p : P) {
@@ -508,6 +557,7 @@ hpt_status alloc_batch(hpt_ctx *C) {
     ok &= A((void **)&B.q_slot[q], 4ull * N) && A((void **)&B.q_ray[q], 32ull * N) &&
           A((void **)&B.q_t[q], 4ull * N) && A((void **)&B.q_gid[q], 4ull * N);
   ok &= A((void **)&B.counters, 64);
+  ok &= A((void **)&B.work, 64);
   ok &= A((void **)&C->d_units, kMaxUnitsPerBatch * sizeof(UnitDev));
   if (!ok) return fail(HPT_ENOMEM, "batch buffer allocation failed");
   if (hipHostMalloc((void **)&C->h_units, kMaxUnitsPerBatch * sizeof(UnitDev), hipHostMallocDefault) !=
@@ -562,6 +612,8 @@ hpt_status hpt_create(int device, uint64_t budget, hpt_ctx **out) {
       hipStreamCreateWithFlags(&C->aux, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreate(&C->ev0) != hipSuccess || hipEventCreate(&C->ev1) != hipSuccess)
     return fail(HPT_EDEVICE, "stream/event creation failed");
+  for (int k = 0; k < hpt_ctx::kEvents; ++k)
+    if (hipEventCreate(&C->pev[k]) != hipSuccess) return fail(HPT_EDEVICE, "event creation failed");
   hpt_status s = alloc_batch(C.get());
   if (s != HPT_OK) {
     for (void *p : C->batch_bufs) (void)hipFree(p);
@@ -595,6 +647,8 @@ void hpt_destroy(hpt_ctx *C) {
   if (C->h_units) (void)hipHostFree(C->h_units);
   (void)hipEventDestroy(C->ev0);
   (void)hipEventDestroy(C->ev1);
+  for (int k = 0; k < hpt_ctx::kEvents; ++k)
+    if (C->pev[k]) (void)hipEventDestroy(C->pev[k]);
   (void)hipStreamDestroy(C->stream);
   (void)hipStreamDestroy(C->aux);
   delete C;
@@ -1013,6 +1067,30 @@ hpt_status hpt_job_release(hpt_ctx *C, uint64_t id) {
   (void)hipSetDevice(C->device);
   free_job_buffers(C, J);
   C->jobs.erase(id);
+  return HPT_OK;
+}
+
+hpt_status hpt_profile_set(hpt_ctx *C, uint32_t level) {
+  if (!C || level > 2) return fail(HPT_EINVAL, "bad argument");
+  std::lock_guard<std::mutex> g(C->mu);
+  C->profile = level;
+  return HPT_OK;
+}
+
+hpt_status hpt_profile_get(hpt_ctx *C, hpt_kernel_time *out, uint64_t *node_visits, uint64_t *prim_tests) {
+  if (!C || !out) return fail(HPT_EINVAL, "null argument");
+  std::lock_guard<std::mutex> g(C->mu);
+  for (int k = 0; k < HPT_K_KINDS; ++k) out[k] = C->ktime[k];
+  if (node_visits) *node_visits = C->node_visits;
+  if (prim_tests) *prim_tests = C->prim_tests;
+  return HPT_OK;
+}
+
+hpt_status hpt_profile_reset(hpt_ctx *C) {
+  if (!C) return fail(HPT_EINVAL, "null context");
+  std::lock_guard<std::mutex> g(C->mu);
+  for (int k = 0; k < HPT_K_KINDS; ++k) C->ktime[k] = hpt_kernel_time{};
+  C->node_visits = C->prim_tests = 0;
   return HPT_OK;
 }
 
