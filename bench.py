@@ -30,8 +30,8 @@ PEAK_FP32 = 157.3e12   # MI355X FP32 vector, FLOP/s
 PEAK_HBM = 8.0e12      # bytes/s
 # algorithmic FP32 FLOPs per traversal step (see the design notes): one BVH2
 # node = two ray/box slab tests; one primitive = one watertight triangle test
-FLOP_NODE = 48
-FLOP_PRIM = 46
+FLOP_NODE = 55
+FLOP_PRIM = 47
 
 
 def log(*a):
