@@ -159,6 +159,7 @@ typedef struct {
   uint64_t sig;              /* FNV-1a over the path's events */
   int32_t kind, bP, first_gid, n_hits;
   double ell, r, A, W, amp, qx, qy, rev;
+  int32_t cache_cell, cache_bin;  /* radiance-cache entry used, -1: none */
 } hpt_path_record;
 
 /* Queue a job. d_field: device buffer of n_ch*T*crop_h*crop_w complex64

@@ -16,7 +16,8 @@ REC_DTYPE = np.dtype([("sig", np.uint64), ("kind", np.int32), ("bP", np.int32),
                       ("first_gid", np.int32), ("n_hits", np.int32),
                       ("ell", np.float64), ("r", np.float64), ("A", np.float64),
                       ("W", np.float64), ("amp", np.float64), ("qx", np.float64),
-                      ("qy", np.float64), ("rev", np.float64)])
+                      ("qy", np.float64), ("rev", np.float64), ("cache_cell", np.int32),
+                      ("cache_bin", np.int32)])
 assert REC_DTYPE.itemsize == C.sizeof(_lib.ORecord)
 
 
@@ -76,6 +77,16 @@ class OracleCache:
 
     def entry(self, comp, cell, b, rounded=True):
         return _lib.lib().oracle_cache_entry(self.h, comp, cell, b, int(rounded))
+
+    def entries(self, comp, cell, b, threads=0):
+        """binary16-rounded entries for arrays of (comp, cell, bin)."""
+        comp = _c(comp, np.int32)
+        cell = _c(cell, np.int32)
+        b = _c(b, np.int32)
+        out = np.zeros(len(comp))
+        _lib.lib().oracle_cache_entries(self.h, len(comp), comp.ctypes.data, cell.ctypes.data,
+                                        b.ctypes.data, out.ctypes.data, int(threads))
+        return out
 
     def bounds(self):
         out = np.zeros(6)

@@ -33,7 +33,7 @@ class ORecord(C.Structure):
                 ("first_gid", C.c_int32), ("n_hits", C.c_int32),
                 ("ell", C.c_double), ("r", C.c_double), ("A", C.c_double), ("W", C.c_double),
                 ("amp", C.c_double), ("qx", C.c_double), ("qy", C.c_double),
-                ("rev", C.c_double)]
+                ("rev", C.c_double), ("cache_cell", C.c_int32), ("cache_bin", C.c_int32)]
 
 
 def lib():
@@ -53,6 +53,7 @@ def lib():
         L.oracle_cache_entry.restype = dbl
         L.oracle_cache_entry.argtypes = [vp, i32, i32, i32, i32]
         L.oracle_cache_bounds.argtypes = [vp, vp]
+        L.oracle_cache_entries.argtypes = [vp, C.c_int64, vp, vp, vp, vp, i32]
         L.oracle_grf_phases.argtypes = [i32, i32, i32, i32, u64, vp, vp]
         L.oracle_philox.argtypes = [vp, vp, vp]
         L.oracle_closest_hit.argtypes = [vp, vp, vp, dbl, i32, i32, vp, vp]

@@ -488,7 +488,8 @@ double cache_lookup(Cache &C, int comp, int cell, int bin);
 // cached radiance instead of tracing (cache on). bP: index of the image point.
 double radiance_tail(const TraceCtx &X, V3 x, V3 d_in, int gid, int b, int bP, int comp,
                      uint64_t seed, uint32_t key_a, uint32_t key_b, uint32_t stream_word,
-                     uint64_t &sig, int &kind, Cache *cache_rw, int *n_hits) {
+                     uint64_t &sig, int &kind, Cache *cache_rw, int *n_hits, int *cell_out = nullptr,
+                     int *bin_out = nullptr) {
   const Scene &S = *X.S;
   double L = 0.0, beta = 1.0;
   double eta = 1.0;
@@ -515,6 +516,8 @@ double radiance_tail(const TraceCtx &X, V3 x, V3 d_in, int gid, int b, int bP, i
     if (s.ev == EV_DIEL_REFR) eta = s.eta_t;
     if (X.cache && !s.delta && (b - bP + 1) >= X.cache_depth) {
       int cell = cell_of(*X.cache, x), bin = oct_bin(s.d, X.cache->P.bins);
+      if (cell_out) *cell_out = cell;
+      if (bin_out) *bin_out = bin;
       sig_add(sig, 0x40000000u | (uint32_t)cell);
       sig_add(sig, 0x50000000u | (uint32_t)bin);
       L += beta * cache_lookup(*cache_rw, comp, cell, bin);
@@ -609,6 +612,7 @@ struct ORecord {           // one per (channel, pixel, sample) path
   uint64_t sig;
   int32_t kind, bP, first_gid, n_hits;
   double ell, r, A, W, amp, qx, qy, rev;
+  int32_t cache_cell, cache_bin;   // radiance-cache entry used (-1: none)
 };
 
 void *oracle_scene_create(const OScene *d) {
@@ -669,6 +673,15 @@ void oracle_cache_destroy(void *c) { delete (Cache *)c; }
 double oracle_cache_entry(void *c, int32_t comp, int32_t cell, int32_t bin, int32_t rounded) {
   Cache *C = (Cache *)c;
   return rounded ? cache_lookup(*C, comp, cell, bin) : cache_entry_fp64(*C, comp, cell, bin);
+}
+
+// Many entries at once (binary16-rounded values), in parallel.
+void oracle_cache_entries(void *c, int64_t n, const int32_t *comp, const int32_t *cell,
+                          const int32_t *bin, double *out, int32_t n_threads) {
+  Cache *C = (Cache *)c;
+  int nt = n_threads > 0 ? n_threads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nt)
+  for (int64_t i = 0; i < n; ++i) out[i] = cache_lookup(*C, comp[i], cell[i], bin[i]);
 }
 
 void oracle_cache_bounds(void *c, double *lo_hi) {
@@ -838,6 +851,8 @@ int32_t oracle_trace(void *scene, void *cache, const OJob *J, double *field, ORe
         uint32_t smp = (uint32_t)(sb + si);
         ORecord R{};
         R.first_gid = -1;
+        R.cache_cell = -1;
+        R.cache_bin = -1;
         uint64_t sig = FNV_OFFSET;
         // s1: direction cosines uniform on the disc alpha^2 + beta^2 <= s^2
         Uniforms U0 = path_uniforms(J->seed, pixel, smp, 0, (uint32_t)comp);
@@ -890,7 +905,8 @@ int32_t oracle_trace(void *scene, void *cache, const OJob *J, double *field, ORe
           // s5: incoherent amplitude from the image point
           int tk = 0, nh = 0;
           double Lhat = radiance_tail(X, o, dir, gid, b, b, comp, J->seed, pixel, smp,
-                                      ((uint32_t)comp << 16) | STREAM_PATH, sig, tk, C, &nh);
+                                      ((uint32_t)comp << 16) | STREAM_PATH, sig, tk, C, &nh,
+                                      &R.cache_cell, &R.cache_bin);
           kind = tk;
           double A = std::sqrt(beta_pre * Lhat);
           double amp = A * W / J->spp;

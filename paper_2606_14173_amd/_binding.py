@@ -78,7 +78,8 @@ PATH_RECORD = np.dtype([("sig", np.uint64), ("kind", np.int32), ("bP", np.int32)
                         ("first_gid", np.int32), ("n_hits", np.int32),
                         ("ell", np.float64), ("r", np.float64), ("A", np.float64),
                         ("W", np.float64), ("amp", np.float64), ("qx", np.float64),
-                        ("qy", np.float64), ("rev", np.float64)])
+                        ("qy", np.float64), ("rev", np.float64), ("cache_cell", np.int32),
+                        ("cache_bin", np.int32)])
 
 # Every entry point declared in include/hpt.h, with its argument types.
 _vp, _u32, _u64, _i64, _sz = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int64, C.c_size_t

@@ -261,6 +261,7 @@ __device__ __forceinline__ void write_rec_tail(const JobDev &J, const UnitDev &U
   hpt_path_record *R = J.rec + rec_index(J, U, p_local, s_local);
   R->sig = sig; R->kind = kind; R->n_hits = (int32_t)b; R->A = A; R->amp = amp;
   R->first_gid = B.s_first[slot];
+  if (kind != K_CACHE) { R->cache_cell = -1; R->cache_bin = -1; }
 }
 
 // End of a hologram path or a cache path.
@@ -400,6 +401,13 @@ __device__ __forceinline__ void tail_interaction(const BatchDev &B, const UnitDe
     uint32_t bin = oct_bin(lb.d, S.cache_bins);
     sig_add(sig, 0x40000000u | cell);
     sig_add(sig, 0x50000000u | bin);
+    if (J.debug & 1u) {
+      uint32_t l = slot - U.slot_base;
+      uint32_t s_local = l / U.p_n, p_local = l - s_local * U.p_n;
+      hpt_path_record *R = J.rec + rec_index(J, U, p_local, s_local);
+      R->cache_cell = (int32_t)cell;
+      R->cache_bin = (int32_t)bin;
+    }
     size_t ce = (size_t)comp * res * res * res * nb + (size_t)cell * nb + bin;
     L += beta * __half2float(__ushort_as_half(S.cache[ce]));
     finish(B, U, J, slot, K_CACHE, b, L, sig, true);

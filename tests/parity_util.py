@@ -18,10 +18,31 @@ def gpu_run(ctx, sid, job):
     return U, rec, ct
 
 
-def compare(Ug, recg, ctg, Uo, reco, cto, tol=1e-4, min_match=0.999):
+def cache_agree(recg, reco, comps, gpu_cache, ocache):
+    """For paths that ended in the radiance cache, whether the GPU's entry and
+    the oracle's entry for that (component, cell, bin) are the same binary16
+    value. comps: colour component per channel."""
+    ok = np.ones(recg.shape, dtype=bool)
+    used = reco["cache_cell"] >= 0
+    if not used.any():
+        return ok
+    ch = np.broadcast_to(np.arange(recg.shape[0]).reshape(-1, 1, 1, 1), recg.shape)[used]
+    comp = np.asarray(comps)[ch]
+    cell = reco["cache_cell"][used]
+    b = reco["cache_bin"][used]
+    g = np.ascontiguousarray(gpu_cache[comp, cell, b]).view(np.float16).astype(np.float64)
+    o = ocache.entries(comp, cell, b)
+    ok[used] = g == o
+    return ok
+
+
+def compare(Ug, recg, ctg, Uo, reco, cto, tol=1e-4, min_match=0.999, extra_match=None):
     """Path signatures must agree on >= min_match of the paths; on matched
-    paths the per-pixel complex field error must be <= tol * RMS(field)."""
+    paths the per-pixel complex field error must be <= tol * RMS(field).
+    extra_match: further per-path agreement (e.g. identical cache entries)."""
     match = recg["sig"] == reco["sig"]
+    if extra_match is not None:
+        match = match & extra_match
     frac = float(match.mean())
     # remove unmatched paths' contributions from both fields: [ch,h,w,s,T] -> [ch,T,h,w]
     um = ~match
