@@ -59,6 +59,12 @@ def main():
     ap.add_argument("--phase-mode", type=int, default=None)
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
+    ap.add_argument("--precision-sweep", action="store_true",
+                    help="phase-precision study: depth 1/10/50 mm, 450 nm, FP64 / split / FP32 phase")
+    ap.add_argument("--serving", action="store_true",
+                    help="continuous batching: Poisson arrivals over four resident scenes")
+    ap.add_argument("--requests", type=int, default=96)
+    ap.add_argument("--load", type=float, default=0.8)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the hot path on a single MI355X "
@@ -75,6 +81,10 @@ def main():
         print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30}))
         return
     import paper_2606_14173_amd as hpt
+    if args.precision_sweep:
+        return precision_sweep(hpt)
+    if args.serving:
+        return serving(hpt, args.requests, args.load)
 
     sc, job, cdesc = workload(args.config)
     if args.phase_mode is not None:
@@ -229,6 +239,170 @@ def main():
         "accuracy": acc,
     }
     print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def precision_sweep(hpt):
+    """Config-2 scene with its depth mapped onto [0.8 D, 1.2 D], D = 1, 10,
+    50 mm; 450 nm, 256 spp, T = 24, radiance cache. Per variant: per-path
+    phase error and field error against the FP64 oracle on the centred
+    128x128 crop, and path-samples/s on the full 1920x1080 frame."""
+    import oracle
+    import scenes
+    from scenes import jobs
+    cdesc = dict(res=64, bins=8, spb=4, max_bounces=6, seed=7)
+    base = scenes.scene_large(2)
+    gw, gh = jobs.grf_size(1920, 1080, 8e-6, 450e-9, 60e-3)
+    ctx = hpt.Context(0)
+    grf = oracle.grf_table(gw, gh, 24, 4)
+    rows = []
+    for D in (1e-3, 10e-3, 50e-3):
+        sc = scenes.scene_depth_rescaled(base, D)
+        sid = ctx.upload_scene(sc)
+        ctx.build_cache(sid, **cdesc)
+        job = jobs.job_for_config(2, lambdas=[450e-9], comps=[2], grf_w=gw, grf_h=gh, grf_seed=4)
+        crop = dict(job, crop=(896, 476, 128, 128))
+        os_ = oracle.OracleScene(sc)
+        oc = oracle.OracleCache(os_, **cdesc)
+        threads = max(1, min(16, os.cpu_count()))
+        t0 = time.time()
+        Uo, reco, _ = oracle.trace(os_, crop, grf=grf, cache=oc, records=True, threads=threads)
+        log("D=%g mm: oracle crop %.1f s" % (D * 1e3, time.time() - t0))
+        rms = float(np.sqrt(np.mean(np.abs(Uo) ** 2)))
+        for mode, name in ((0, "fp64"), (1, "split"), (2, "fp32")):
+            Ug, recg = ctx.trace(sid, dict(crop, phase_mode=mode), records=True)
+            match = recg["sig"] == reco["sig"]
+            img = match & (reco["amp"] != 0)
+            dphi = np.abs(np.angle(np.exp(2j * np.pi * (recg["rev"][img] - reco["rev"][img]))))
+            pix = match.all(axis=-1)
+            dU = np.abs(Ug - Uo).max(axis=1)
+            full = dict(job, phase_mode=mode)
+            jid = ctx.submit(sid, full)
+            ctx.wait(jid)
+            jid2 = ctx.submit(sid, full)   # second run: tables resident
+            t0 = time.perf_counter()
+            ctx.wait(jid2)
+            st = ctx.stats(jid2)
+            ctx.release_job(jid)
+            ctx.release_job(jid2)
+            n = 1920 * 1080 * 256
+            row = {"depth_mm": D * 1e3, "phase": name, "path_match": round(float(match.mean()), 6),
+                   "phase_err_rad_p50": float(np.median(dphi)), "phase_err_rad_p99": float(np.percentile(dphi, 99)),
+                   "phase_err_rad_max": float(dphi.max()),
+                   "field_err_over_rms_matched_pixels": float(dU[pix].max() / rms),
+                   "pixels_all_paths_match": round(float(pix.mean()), 5),
+                   "path_samples_per_s_full_frame": round(n / (st["run_ms"] * 1e-3), 1),
+                   "ms_full_frame": round(st["run_ms"], 2)}
+            log(json.dumps(row))
+            rows.append(row)
+        ctx.release_scene(sid)
+    print(json.dumps({"precision_sweep": rows}))
+    ctx.close()
+
+
+def serving(hpt, n_req, load):
+    """Requests over four resident scenes (tiny, mid, large with cache, a
+    second mid); resolution from {256^2, 512^2, 1024^2, 1920x1080}, spp from
+    {16, 64, 256}, T from {1, 8, 24}, 520 nm. First every request alone, one
+    after another; then a Poisson stream at `load` times the alone capacity,
+    submitted as requests arrive while earlier ones run. Reports p50/p99
+    latency, aggregate path-samples/s of both, and whether each request's
+    field is bitwise the same alone and in the mix."""
+    import threading
+    import torch
+    import scenes
+    from scenes import jobs
+    ctx = hpt.Context(0)
+    sids = [ctx.upload_scene(scenes.scene_tiny(0)), ctx.upload_scene(scenes.scene_mid(1)),
+            ctx.upload_scene(scenes.scene_large(2)), ctx.upload_scene(scenes.scene_mid(3))]
+    ctx.build_cache(sids[2], res=64, bins=8, spb=4, max_bounces=6, seed=7)
+    bounces = [2, 4, 6, 4]
+    res = [(256, 256), (512, 512), (1024, 1024), (1920, 1080)]
+    rng = np.random.default_rng(0)
+    reqs = []
+    for i in range(n_req):
+        k = int(rng.integers(4))
+        w, h = res[int(rng.integers(4))]
+        spp = [16, 64, 256][int(rng.integers(3))]
+        T = [1, 8, 24][int(rng.integers(3))]
+        gw, gh = jobs.grf_size(w, h, 8e-6, 520e-9, 52e-3)
+        j = dict(jobs.JOB_DEFAULTS)
+        j.update(width=w, height=h, lambdas=[520e-9], comps=[1], spp=spp, max_bounces=bounces[k], T=T,
+                 seed=i, grf_seed=1000 + (i % 4), grf_w=gw, grf_h=gh, phase_mode=1,
+                 use_cache=1 if k == 2 else 0)
+        reqs.append((sids[k], j, w * h * spp))
+
+    def checksum(f):
+        b = torch.view_as_real(f).contiguous().view(torch.int32).to(torch.int64).view(-1)
+        wgt = torch.arange(b.numel(), device=b.device, dtype=torch.int64) % 1000003 + 1
+        return int((b * wgt).sum().item())
+
+    def run_one(sid, j):
+        w, h = (j["crop"][2], j["crop"][3]) if j["crop"][2] else (j["width"], j["height"])
+        f = torch.empty((1, j["T"], h, w), dtype=torch.complex64, device="cuda:0")
+        jid = ctx.submit(sid, j, field=f)
+        ctx.wait(jid)
+        ctx.release_job(jid)
+        return checksum(f)
+
+    warmed = set()               # build every random-field table once, untimed
+    for sid, j, _ in reqs:
+        key = (j["grf_w"], j["grf_h"], j["T"], j["grf_seed"])
+        if key not in warmed:
+            warmed.add(key)
+            run_one(sid, dict(j, crop=(0, 0, 1, 1), spp=1))
+    # alone: one request at a time
+    alone_lat, alone_sum = [], []
+    t0 = time.perf_counter()
+    for sid, j, _ in reqs:
+        t1 = time.perf_counter()
+        alone_sum.append(run_one(sid, j))
+        alone_lat.append(time.perf_counter() - t1)
+    t_alone = time.perf_counter() - t0
+    total_paths = sum(r[2] for r in reqs)
+    rate = load * n_req / t_alone   # requests per second
+    gaps = rng.exponential(1.0 / rate, n_req)
+    arrivals = np.cumsum(gaps)
+    log("alone: %d requests, %.2f s, %.3g path-samples/s; mix at %.2f req/s"
+        % (n_req, t_alone, total_paths / t_alone, rate))
+    fields, jids = [None] * n_req, [None] * n_req
+    done_t = [0.0] * n_req
+    lock = threading.Lock()
+
+    def waiter(i):
+        ctx.wait(jids[i])
+        with lock:
+            done_t[i] = time.perf_counter()
+
+    threads = []
+    base = time.perf_counter()
+    for i, (sid, j, _) in enumerate(reqs):
+        now = time.perf_counter() - base
+        if arrivals[i] > now:
+            time.sleep(arrivals[i] - now)
+        f = torch.empty((1, j["T"], j["height"], j["width"]), dtype=torch.complex64, device="cuda:0")
+        fields[i] = f
+        jids[i] = ctx.submit(sid, j, field=f)
+        th = threading.Thread(target=waiter, args=(i,))
+        th.start()
+        threads.append(th)
+    for th in threads:
+        th.join()
+    t_mix = max(done_t) - base
+    lat = [done_t[i] - base - arrivals[i] for i in range(n_req)]
+    same = 0
+    for i in range(n_req):
+        ctx.release_job(jids[i])
+        same += int(checksum(fields[i]) == alone_sum[i])
+        fields[i] = None
+    out = {"serving": {
+        "requests": n_req, "load": load, "arrival_rate_per_s": round(rate, 3),
+        "alone": {"p50_s": float(np.percentile(alone_lat, 50)), "p99_s": float(np.percentile(alone_lat, 99)),
+                  "path_samples_per_s": round(total_paths / t_alone, 1), "wall_s": round(t_alone, 3)},
+        "mix": {"p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+                "path_samples_per_s": round(total_paths / t_mix, 1), "wall_s": round(t_mix, 3)},
+        "bitwise_same_alone_and_mix": f"{same}/{n_req}"}}
+    print(json.dumps(out))
     ctx.close()
 
 

@@ -303,6 +303,26 @@ def scene_translate(sc, t):
     return out
 
 
+def scene_depth_rescaled(sc, D):
+    """Copy of a scene whose z range is mapped linearly onto [0.8 D, 1.2 D]
+    (lateral coordinates unchanged): the depth sweep of the precision study."""
+    out = {k: np.array(v, copy=True) for k, v in sc.items()}
+    tri = sc["tri"].astype(np.float64)
+    zs = [tri[..., 2].ravel()]
+    if len(sc["sph"]):
+        zs.append(sc["sph"][:, 2].astype(np.float64))
+    z = np.concatenate(zs)
+    z0, z1 = z.min(), z.max()
+    f = lambda v: D * (0.8 + 0.4 * (v - z0) / (z1 - z0))
+    tri[..., 2] = f(tri[..., 2])
+    out["tri"] = tri.astype(np.float32)
+    if len(sc["sph"]):
+        s2 = sc["sph"].astype(np.float64)
+        s2[:, 2] = f(s2[:, 2])
+        out["sph"] = s2.astype(np.float32)
+    return out
+
+
 def make_scene(name, seed=None):
     if name in ("tiny", "config0"):
         return scene_tiny(0 if seed is None else seed)

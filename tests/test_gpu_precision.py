@@ -1,0 +1,62 @@
+"""Precision of the phase chain on the ~1M-triangle scene (GPU vs the FP64
+oracle): depth rescaled to 1, 10 and 50 mm, 450 nm, T = 24, radiance cache
+on. FP64 and split phase must keep the per-path phase error <= 1e-3 rad and
+the field error on pixels whose paths all match <= 1e-4 RMS; plain FP32 is
+reported (its error grows with depth, about one FP32 ulp of k*l)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import scenes
+from scenes import jobs
+from parity_util import cache_agree
+
+pytestmark = pytest.mark.gpu
+
+CDESC = dict(res=32, bins=8, spb=2, max_bounces=6, seed=7)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2606_14173_amd as hpt
+    c = hpt.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("D", [1e-3, 10e-3, 50e-3])
+def test_precision_sweep(ctx, D):
+    base = scenes.scene_large(2)
+    sc = scenes.scene_depth_rescaled(base, D)
+    sid = ctx.upload_scene(sc)
+    ctx.build_cache(sid, **CDESC)
+    gcache = ctx.export_cache(sid, CDESC["res"], CDESC["bins"])
+    gw, gh = jobs.grf_size(1920, 1080, 8e-6, 450e-9, 1.2 * D)
+    job = jobs.job_for_config(2, lambdas=[450e-9], comps=[2], spp=32, crop=(944, 524, 32, 32),
+                              grf_w=gw, grf_h=gh, grf_seed=4)
+    os_ = oracle.OracleScene(sc)
+    oc = oracle.OracleCache(os_, **CDESC)
+    grf = oracle.grf_table(gw, gh, job["T"], job["grf_seed"])
+    Uo, reco, _ = oracle.trace(os_, job, grf=grf, cache=oc, records=True)
+    rms = float(np.sqrt(np.mean(np.abs(Uo) ** 2)))
+    out = {}
+    for mode, name in ((jobs.PHASE_FP64, "fp64"), (jobs.PHASE_SPLIT, "split"), (jobs.PHASE_FP32, "fp32")):
+        Ug, recg = ctx.trace(sid, dict(job, phase_mode=mode), records=True)
+        # identical hit/lobe sequence and identical radiance-cache entry
+        match = (recg["sig"] == reco["sig"]) & cache_agree(recg, reco, job["comps"], gcache, oc)
+        img = match & (reco["amp"] != 0)
+        dphi = np.abs(np.angle(np.exp(2j * np.pi * (recg["rev"][img] - reco["rev"][img]))))
+        pix = match.all(axis=-1)
+        err = float(np.abs(Ug - Uo).max(axis=1)[pix].max() / rms)
+        out[name] = (float(match.mean()), float(np.median(dphi)), float(np.percentile(dphi, 99)),
+                     float(dphi.max()), err)
+        print("D=%2.0f mm %-5s match %.5f phase p50/p99/max %.1e/%.1e/%.1e field err/rms %.1e"
+              % (D * 1e3, name, *out[name]))
+        sys.stdout.flush()
+    ctx.release_scene(sid)
+    for name in ("fp64", "split"):
+        m, p50, p99, pmax, err = out[name]
+        assert m >= 0.999 and pmax <= 1e-3 and err <= 1e-4
+    assert out["fp32"][0] >= 0.999

@@ -1,0 +1,146 @@
+"""Continuous batching on the GPU: requests that run together give the same
+fields as when each runs alone; admission by HBM budget; cancellation;
+resumable sample chunks."""
+import sys
+import threading
+
+import numpy as np
+import pytest
+
+import scenes
+from scenes import jobs
+
+pytestmark = pytest.mark.gpu
+
+
+def _job(w, h, spp, T, seed, bounces, use_cache=0, mode=jobs.PHASE_SPLIT):
+    gw, gh = jobs.grf_size(w, h, 8e-6, 520e-9, 52e-3)
+    j = dict(jobs.JOB_DEFAULTS)
+    j.update(width=w, height=h, lambdas=[520e-9], comps=[1], spp=spp, max_bounces=bounces, T=T,
+             seed=seed, grf_seed=7, grf_w=gw, grf_h=gh, phase_mode=mode, use_cache=use_cache)
+    return j
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import paper_2606_14173_amd as hpt
+    ctx = hpt.Context(0)
+    sids = [ctx.upload_scene(scenes.scene_tiny(0)), ctx.upload_scene(scenes.scene_mid(1)),
+            ctx.upload_scene(scenes.scene_large(2))]
+    ctx.build_cache(sids[2], res=32, bins=8, spb=2, max_bounces=6, seed=7)
+    yield ctx, sids
+    ctx.close()
+
+
+def _requests(sids):
+    return [(sids[0], _job(256, 256, 16, 1, 1, 2)),
+            (sids[1], _job(512, 512, 16, 8, 2, 4)),
+            (sids[2], _job(640, 360, 8, 24, 3, 6, use_cache=1)),
+            (sids[1], _job(300, 200, 32, 8, 4, 4, mode=jobs.PHASE_FP64)),
+            (sids[0], _job(128, 96, 64, 24, 5, 2, mode=jobs.PHASE_FP32)),
+            (sids[2], _job(200, 150, 16, 8, 6, 6, use_cache=1))]
+
+
+def test_mix_equals_alone(setup):
+    ctx, sids = setup
+    reqs = _requests(sids)
+    alone = [ctx.trace(sid, j) for sid, j in reqs]
+    jids = [ctx.submit(sid, j) for sid, j in reqs]          # all queued at once
+    out = []
+    for jid, (sid, j) in zip(jids, reqs):
+        ctx.wait(jid)
+        out.append(ctx.read_field(jid, j))
+        st = ctx.stats(jid)
+        assert st["paths"] == j["width"] * j["height"] * j["spp"]
+        ctx.release_job(jid)
+    for a, b in zip(alone, out):
+        assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    cs = ctx.ctx_stats()
+    print("batches run:", cs["batches"])
+
+
+def test_arrivals_while_running(setup):
+    """Requests submitted from another thread while earlier ones are running
+    are admitted at batch boundaries; results unchanged."""
+    ctx, sids = setup
+    reqs = _requests(sids)
+    alone = [ctx.trace(sid, j) for sid, j in reqs]
+    jids = [None] * len(reqs)
+
+    def producer():
+        import time
+        for i, (sid, j) in enumerate(reqs):
+            jids[i] = ctx.submit(sid, j)
+            time.sleep(0.01)
+
+    th = threading.Thread(target=producer)
+    th.start()
+    th.join()
+    for i, (sid, j) in enumerate(reqs):
+        ctx.wait(jids[i])
+        assert np.array_equal(ctx.read_field(jids[i], j).view(np.uint32), alone[i].view(np.uint32))
+        ctx.release_job(jids[i])
+
+
+def test_admission_by_budget():
+    """A context with a small HBM budget runs jobs whose outputs together do
+    not fit one after another, and refuses a job that can never fit."""
+    import paper_2606_14173_amd as hpt
+    budget = 1 << 30
+    with hpt.Context(0, budget) as ctx:
+        cs = ctx.ctx_stats()
+        assert cs["budget_bytes"] == budget and cs["batch_capacity_paths"] >= 1 << 16
+        sid = ctx.upload_scene(scenes.scene_tiny(0))
+        j = _job(1024, 1024, 1, 8, 9, 2)                    # 64 MiB field + table
+        free = budget - ctx.ctx_stats()["used_bytes"]
+        n = int(free // (64 << 20)) + 2                      # more than fit at once
+        jids = [ctx.submit(sid, dict(j, seed=k)) for k in range(n)]
+        for jid in jids:
+            ctx.wait(jid)
+            ctx.release_job(jid)
+        with pytest.raises(hpt.HptError) as e:
+            ctx.submit(sid, _job(3072, 3072, 1, 64, 1, 2))   # 4.5 GiB field
+        assert e.value.name == "HPT_EBUDGET"
+        assert ctx.ctx_stats()["jobs_done"] >= n
+
+
+def test_cancel_keeps_context_usable(setup):
+    import paper_2606_14173_amd as hpt
+    ctx, sids = setup
+    big = _job(1920, 1080, 256, 24, 11, 6, use_cache=1)
+    jid = ctx.submit(sids[2], big)
+    ctx.cancel(jid)
+    with pytest.raises(hpt.HptError) as e:
+        ctx.wait(jid)
+    assert e.value.name == "HPT_ECANCELED"
+    ctx.release_job(jid)
+    small = _job(64, 64, 4, 1, 1, 2)
+    U = ctx.trace(sids[0], small)
+    assert np.isfinite(U).all() and np.abs(U).max() > 0
+
+
+def test_resumable_chunks(setup):
+    """A job split into sample chunks sums to the one-shot field."""
+    ctx, sids = setup
+    j = _job(96, 80, 48, 8, 3, 4)
+    full = ctx.trace(sids[1], j).astype(np.complex128)
+    parts = sum(ctx.trace(sids[1], dict(j, spp_begin=a, spp_end=b)).astype(np.complex128)
+                for a, b in ((0, 13), (13, 30), (30, 48)))
+    err = np.abs(parts - full).max() / np.abs(full).max()
+    print("chunk sum vs one-shot: %.2e" % err)
+    sys.stdout.flush()
+    assert err < 1e-5
+
+
+def test_wait_timeout_and_unknown(setup):
+    import paper_2606_14173_amd as hpt
+    ctx, sids = setup
+    with pytest.raises(hpt.HptError) as e:
+        ctx.wait(987654321, 10)
+    assert e.value.name == "HPT_ENOTFOUND"
+    jid = ctx.submit(sids[2], _job(1920, 1080, 64, 8, 12, 6, use_cache=1))
+    with pytest.raises(hpt.HptError) as e:
+        ctx.wait(jid, 0)
+    assert e.value.name in ("HPT_ETIMEOUT",)
+    ctx.wait(jid)
+    ctx.release_job(jid)
