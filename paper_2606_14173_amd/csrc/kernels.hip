@@ -51,10 +51,54 @@ __device__ __forceinline__ F3 normal32(const SceneDev &S, int32_t gid, F3 x) {
                          f3(v[6] - v[0], v[7] - v[1], v[8] - v[2])));
 }
 
+// Pixel order of a crop: 8x8 tiles, tiles row-major, pixels row-major inside
+// a tile (narrower / shorter tiles at the right and bottom edges). Units own
+// ranges of this order, so the rays of a unit's first wave groups come from
+// one small tile.
+__device__ __forceinline__ void crop_xy(const JobDev &J, uint32_t p, uint32_t &cx, uint32_t &cy) {
+  uint32_t w = J.crop_w, h = J.crop_h;
+  uint32_t band = p / (8u * w);                 // 8-row band
+  uint32_t rows = min(8u, h - 8u * band);
+  uint32_t o = p - band * 8u * w;
+  uint32_t full = (w / 8u) * 8u * rows;         // pixels in the band's full-width tiles
+  uint32_t tx, ix, iy;
+  if (o < full) {
+    tx = o / (8u * rows);
+    uint32_t in = o - tx * 8u * rows;
+    iy = in / 8u; ix = in - iy * 8u;
+    cx = tx * 8u + ix;
+  } else {
+    uint32_t wp = w - (w / 8u) * 8u;              // width of the last, partial tile
+    uint32_t in = o - full;
+    iy = in / wp; ix = in - iy * wp;
+    cx = (w / 8u) * 8u + ix;
+  }
+  cy = band * 8u + iy;
+}
+
+// Slots of a unit are pixel-major: slot = slot_base + p_local * s_n + s_local.
+__device__ __forceinline__ void slot_decode(const UnitDev &U, uint32_t slot, uint32_t &p_local,
+                                            uint32_t &s_local) {
+  uint32_t l = slot - U.slot_base;
+  p_local = l / U.s_n;
+  s_local = l - p_local * U.s_n;
+}
+
 __device__ __forceinline__ size_t rec_index(const JobDev &J, const UnitDev &U, uint32_t p_local,
                                             uint32_t s_local) {
-  uint32_t p = U.p_lo + p_local;
-  return ((size_t)U.ch * J.crop_w * J.crop_h + p) * J.n_s + (U.s_lo + s_local - J.spp_lo);
+  uint32_t cx, cy;
+  crop_xy(J, U.p_lo + p_local, cx, cy);
+  return ((size_t)U.ch * J.crop_h * J.crop_w + (size_t)cy * J.crop_w + cx) * J.n_s +
+         (U.s_lo + s_local - J.spp_lo);
+}
+
+// Morton index of a point of [-1,1]^2 on an 8x8 grid (ray-sorting key).
+__device__ __forceinline__ uint32_t morton8(float u, float v) {
+  int a = min(max((int)floorf((u + 1.f) * 4.f), 0), 7);
+  int b = min(max((int)floorf((v + 1.f) * 4.f), 0), 7);
+  uint32_t k = 0;
+  for (int i = 0; i < 3; ++i) k |= (((uint32_t)a >> i) & 1u) << (2 * i) | (((uint32_t)b >> i) & 1u) << (2 * i + 1);
+  return k;
 }
 
 __device__ __forceinline__ void push_ray(const BatchDev &B, int q, uint32_t pos, uint32_t slot, F3 o,
@@ -65,107 +109,134 @@ __device__ __forceinline__ void push_ray(const BatchDev &B, int q, uint32_t pos,
 }
 
 // ------------------------------------------------------------------ raygen
-__global__ void __launch_bounds__(kBlock) k_raygen(BatchDev B) {
-  uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+// One thread per slot. A block of kRaygenBlock consecutive slots (one 8x8
+// pixel tile x 16 samples for a 16-sample unit) counting-sorts its rays by
+// direction (8x8 Morton bins over the cone, or over the octahedral square
+// for cache paths) before writing the first queue, so that each wave traces
+// rays of similar origin and direction. The queue order changes nothing but
+// the traversal's coherence: every path keeps its slot.
+constexpr int kRaygenBlock = 1024;
+
+__global__ void __launch_bounds__(kRaygenBlock) k_raygen(BatchDev B) {
+  __shared__ uint32_t hist[64], base[64];
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t g0 = blockIdx.x * blockDim.x;
   if (i == 0) { B.counters[0] = B.n_paths; B.counters[1] = 0; }
-  if (i >= B.n_paths) return;
-  uint32_t u = find_unit(B.units, B.n_units, i, false);
-  const UnitDev U = B.units[u];
-  const JobDev &J = *U.job;
-  uint32_t l = i - U.slot_base;
-  uint32_t s_local = l / U.p_n, p_local = l - s_local * U.p_n;
-  B.s_unit[i] = u;
-  B.s_L[i] = 0.f;
-  B.s_beta[i] = 1.f;
-  B.s_bpre[i] = 1.f;
-  B.s_first[i] = -1;
-  B.s_sig[i] = kSigInit;
-  B.r_amp[i] = 0.f;
-  if (U.kind == UNIT_HOLO) {
-    uint32_t comp = J.comp[U.ch];
-    uint32_t p = U.p_lo + p_local;
-    uint32_t px = J.crop_x0 + p % J.crop_w, py = J.crop_y0 + p / J.crop_w;
-    uint32_t gpix = py * J.width + px, smp = U.s_lo + s_local;
-    B.s_ka[i] = gpix;
-    B.s_kb[i] = smp;
-    U4 w = philox(gpix, smp, 0u, comp << 16, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
-    D3 xp = {((double)px + 0.5 - 0.5 * (double)J.width) * J.pitch,
-             ((double)py + 0.5 - 0.5 * (double)J.height) * J.pitch, 0.0};
-    D3 O, d;
-    double al, be;
-    if (J.phase_mode != HPT_PHASE_FP32) {
-      // s1: direction cosines uniform on the disc of radius lambda/(2d)
-      double rad = J.s_cone[U.ch] * sqrt(ud(w.x));
-      double sn, cs;
-      sincospi(2.0 * ud(w.y), &sn, &cs);
-      al = rad * cs; be = rad * sn;
-      D3 v = {al, be, sqrt(1.0 - al * al - be * be)};
-      if (J.identity_T) {
-        O = xp;
-        d = normalize(v);
-      } else {  // s2: into world space through the inverse of T (Eq. 3)
-        const double *M = J.Ti;
-        O = {M[0] * xp.x + M[1] * xp.y + M[2] * xp.z + M[3], M[4] * xp.x + M[5] * xp.y + M[6] * xp.z + M[7],
-             M[8] * xp.x + M[9] * xp.y + M[10] * xp.z + M[11]};
-        d = normalize(D3{M[0] * v.x + M[1] * v.y + M[2] * v.z, M[4] * v.x + M[5] * v.y + M[6] * v.z,
-                         M[8] * v.x + M[9] * v.y + M[10] * v.z});
-      }
-    } else {
-      float rad = J.s_cone_f[U.ch] * sqrtf(uf(w.x));
-      float sn, cs;
-      sincospif(2.0f * uf(w.y), &sn, &cs);
-      float alf = rad * cs, bef = rad * sn;
-      F3 v = f3(alf, bef, sqrtf(1.0f - alf * alf - bef * bef));
-      al = alf; be = bef;
-      F3 O32, d32;
-      if (J.identity_T) {
-        O32 = to_f(xp);
-        d32 = normalize(v);
+  if (threadIdx.x < 64) hist[threadIdx.x] = 0;
+  __syncthreads();
+  const bool valid = i < B.n_paths;
+  F3 ro = f3(0.f, 0.f, 0.f), rd = f3(0.f, 0.f, 1.f);
+  uint32_t key = 0;
+  if (valid) {
+    uint32_t u = find_unit(B.units, B.n_units, i, false);
+    const UnitDev U = B.units[u];
+    const JobDev &J = *U.job;
+    uint32_t p_local, s_local;
+    slot_decode(U, i, p_local, s_local);
+    B.s_unit[i] = u;
+    B.s_L[i] = 0.f;
+    B.s_beta[i] = 1.f;
+    B.s_bpre[i] = 1.f;
+    B.s_first[i] = -1;
+    B.s_sig[i] = kSigInit;
+    B.r_amp[i] = 0.f;
+    if (U.kind == UNIT_HOLO) {
+      uint32_t comp = J.comp[U.ch];
+      uint32_t cx, cy;
+      crop_xy(J, U.p_lo + p_local, cx, cy);
+      uint32_t px = J.crop_x0 + cx, py = J.crop_y0 + cy;
+      uint32_t gpix = py * J.width + px, smp = U.s_lo + s_local;
+      B.s_ka[i] = gpix;
+      B.s_kb[i] = smp;
+      U4 w = philox(gpix, smp, 0u, comp << 16, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
+      D3 xp = {((double)px + 0.5 - 0.5 * (double)J.width) * J.pitch,
+               ((double)py + 0.5 - 0.5 * (double)J.height) * J.pitch, 0.0};
+      D3 O, d;
+      double al, be;
+      if (J.phase_mode != HPT_PHASE_FP32) {
+        // s1: direction cosines uniform on the disc of radius lambda/(2d)
+        double rad = J.s_cone[U.ch] * sqrt(ud(w.x));
+        double sn, cs;
+        sincospi(2.0 * ud(w.y), &sn, &cs);
+        al = rad * cs; be = rad * sn;
+        D3 v = {al, be, sqrt(1.0 - al * al - be * be)};
+        if (J.identity_T) {
+          O = xp;
+          d = normalize(v);
+        } else {  // s2: into world space through the inverse of T (Eq. 3)
+          const double *M = J.Ti;
+          O = {M[0] * xp.x + M[1] * xp.y + M[2] * xp.z + M[3], M[4] * xp.x + M[5] * xp.y + M[6] * xp.z + M[7],
+               M[8] * xp.x + M[9] * xp.y + M[10] * xp.z + M[11]};
+          d = normalize(D3{M[0] * v.x + M[1] * v.y + M[2] * v.z, M[4] * v.x + M[5] * v.y + M[6] * v.z,
+                           M[8] * v.x + M[9] * v.y + M[10] * v.z});
+        }
       } else {
-        float M[12];
-        for (int k = 0; k < 12; ++k) M[k] = (float)J.Ti[k];
-        F3 x = to_f(xp);
-        O32 = f3(M[0] * x.x + M[1] * x.y + M[2] * x.z + M[3], M[4] * x.x + M[5] * x.y + M[6] * x.z + M[7],
-                 M[8] * x.x + M[9] * x.y + M[10] * x.z + M[11]);
-        d32 = normalize(f3(M[0] * v.x + M[1] * v.y + M[2] * v.z, M[4] * v.x + M[5] * v.y + M[6] * v.z,
-                           M[8] * v.x + M[9] * v.y + M[10] * v.z));
+        float rad = J.s_cone_f[U.ch] * sqrtf(uf(w.x));
+        float sn, cs;
+        sincospif(2.0f * uf(w.y), &sn, &cs);
+        float alf = rad * cs, bef = rad * sn;
+        F3 v = f3(alf, bef, sqrtf(1.0f - alf * alf - bef * bef));
+        al = alf; be = bef;
+        F3 O32, d32;
+        if (J.identity_T) {
+          O32 = to_f(xp);
+          d32 = normalize(v);
+        } else {
+          float M[12];
+          for (int k = 0; k < 12; ++k) M[k] = (float)J.Ti[k];
+          F3 x = to_f(xp);
+          O32 = f3(M[0] * x.x + M[1] * x.y + M[2] * x.z + M[3], M[4] * x.x + M[5] * x.y + M[6] * x.z + M[7],
+                   M[8] * x.x + M[9] * x.y + M[10] * x.z + M[11]);
+          d32 = normalize(f3(M[0] * v.x + M[1] * v.y + M[2] * v.z, M[4] * v.x + M[5] * v.y + M[6] * v.z,
+                             M[8] * v.x + M[9] * v.y + M[10] * v.z));
+        }
+        O = to_d(O32); d = to_d(d32);
       }
-      O = to_d(O32); d = to_d(d32);
+      B.s_al[i] = al; B.s_be[i] = be;
+      B.s_ox[i] = O.x; B.s_oy[i] = O.y; B.s_oz[i] = O.z;
+      B.s_dx[i] = d.x; B.s_dy[i] = d.y; B.s_dz[i] = d.z;
+      B.s_ell[i] = 0.0;
+      B.s_W[i] = 1.0f;  // refractive index of the current medium while in the prefix
+      B.s_meta[i] = STAGE_PREFIX;
+      ro = to_f(O); rd = to_f(d);
+      key = morton8((float)(al / J.s_cone[U.ch]), (float)(be / J.s_cone[U.ch]));
+    } else {
+      // radiance-cache path: a point uniform in the cell, a direction uniform
+      // in the bin's octahedral square
+      const SceneDev &S = *J.scene;
+      uint32_t comp = U.ch;
+      uint32_t e = U.p_lo + p_local, j = U.s_lo + s_local;
+      uint32_t nb = J.cache_bins * J.cache_bins;
+      uint32_t cell = e / nb, bin = e - cell * nb;
+      uint32_t res = J.cache_res;
+      uint32_t ix = cell % res, iy = (cell / res) % res, iz = cell / (res * res);
+      uint32_t bu = bin % J.cache_bins, bv = bin / J.cache_bins;
+      uint32_t ka = cell, kb = (bin << 16) | j;
+      uint32_t sw = (comp << 16) | 2u;
+      U4 w0 = philox(ka, kb, 0u, sw, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
+      U4 w1 = philox(ka, kb, 1u, sw, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
+      D3 lo = {S.cache_lo_d[0], S.cache_lo_d[1], S.cache_lo_d[2]};
+      D3 ext = {S.cache_hi_d[0] - lo.x, S.cache_hi_d[1] - lo.y, S.cache_hi_d[2] - lo.z};
+      D3 x = {lo.x + (ix + ud(w0.x)) / res * ext.x, lo.y + (iy + ud(w0.y)) / res * ext.y,
+              lo.z + (iz + ud(w0.z)) / res * ext.z};
+      double pu = -1.0 + 2.0 * (bu + ud(w0.w)) / J.cache_bins;
+      double pv = -1.0 + 2.0 * (bv + ud(w1.x)) / J.cache_bins;
+      D3 d = oct_decode64(pu, pv);
+      B.s_ka[i] = ka;
+      B.s_kb[i] = kb;
+      B.s_meta[i] = STAGE_TAIL;  // b = 0, bP = 0
+      ro = to_f(x); rd = to_f(d);
+      key = morton8((float)pu, (float)pv);
     }
-    B.s_al[i] = al; B.s_be[i] = be;
-    B.s_ox[i] = O.x; B.s_oy[i] = O.y; B.s_oz[i] = O.z;
-    B.s_dx[i] = d.x; B.s_dy[i] = d.y; B.s_dz[i] = d.z;
-    B.s_ell[i] = 0.0;
-    B.s_W[i] = 1.0f;  // refractive index of the current medium while in the prefix
-    B.s_meta[i] = STAGE_PREFIX;
-    push_ray(B, 0, i, i, to_f(O), to_f(d), -1);
-  } else {
-    // radiance-cache path: a point uniform in the cell, a direction uniform
-    // in the bin's octahedral square
-    const SceneDev &S = *J.scene;
-    uint32_t comp = U.ch;
-    uint32_t e = U.p_lo + p_local, j = U.s_lo + s_local;
-    uint32_t nb = J.cache_bins * J.cache_bins;
-    uint32_t cell = e / nb, bin = e - cell * nb;
-    uint32_t res = J.cache_res;
-    uint32_t ix = cell % res, iy = (cell / res) % res, iz = cell / (res * res);
-    uint32_t bu = bin % J.cache_bins, bv = bin / J.cache_bins;
-    uint32_t ka = cell, kb = (bin << 16) | j;
-    uint32_t sw = (comp << 16) | 2u;
-    U4 w0 = philox(ka, kb, 0u, sw, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
-    U4 w1 = philox(ka, kb, 1u, sw, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
-    D3 lo = {S.cache_lo_d[0], S.cache_lo_d[1], S.cache_lo_d[2]};
-    D3 ext = {S.cache_hi_d[0] - lo.x, S.cache_hi_d[1] - lo.y, S.cache_hi_d[2] - lo.z};
-    D3 x = {lo.x + (ix + ud(w0.x)) / res * ext.x, lo.y + (iy + ud(w0.y)) / res * ext.y,
-            lo.z + (iz + ud(w0.z)) / res * ext.z};
-    double pu = -1.0 + 2.0 * (bu + ud(w0.w)) / J.cache_bins;
-    double pv = -1.0 + 2.0 * (bv + ud(w1.x)) / J.cache_bins;
-    D3 d = oct_decode64(pu, pv);
-    B.s_ka[i] = ka;
-    B.s_kb[i] = kb;
-    B.s_meta[i] = STAGE_TAIL;  // b = 0, bP = 0
-    push_ray(B, 0, i, i, to_f(x), to_f(d), -1);
   }
+  uint32_t rank = valid ? atomicAdd(&hist[key], 1u) : 0u;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (int k = 0; k < 64; ++k) { base[k] = acc; acc += hist[k]; }
+  }
+  __syncthreads();
+  if (valid) push_ray(B, 0, g0 + base[key] + rank, i, ro, rd, -1);
 }
 
 // ------------------------------------------------------------------ trace
@@ -256,8 +327,8 @@ struct Emit { bool on; F3 o, d; int32_t excl; };
 __device__ __forceinline__ void write_rec_tail(const JobDev &J, const UnitDev &U, const BatchDev &B,
                                                uint32_t slot, int32_t kind, uint32_t b, float A,
                                                float amp, unsigned long long sig) {
-  uint32_t l = slot - U.slot_base;
-  uint32_t s_local = l / U.p_n, p_local = l - s_local * U.p_n;
+  uint32_t p_local, s_local;
+  slot_decode(U, slot, p_local, s_local);
   hpt_path_record *R = J.rec + rec_index(J, U, p_local, s_local);
   R->sig = sig; R->kind = kind; R->n_hits = (int32_t)b; R->A = A; R->amp = amp;
   R->first_gid = B.s_first[slot];
@@ -362,8 +433,8 @@ __device__ __forceinline__ void image_point(const BatchDev &B, const UnitDev &U,
   B.r_rev[slot] = (float)rev;
   B.s_W[slot] = W;
   if (J.debug & 1u) {
-    uint32_t l = slot - U.slot_base;
-    uint32_t s_local = l / U.p_n, p_local = l - s_local * U.p_n;
+    uint32_t p_local, s_local;
+    slot_decode(U, slot, p_local, s_local);
     hpt_path_record *R = J.rec + rec_index(J, U, p_local, s_local);
     R->bP = (int32_t)bP; R->ell = ell; R->r = r; R->W = W; R->qx = qx; R->qy = qy; R->rev = rev;
   }
@@ -402,8 +473,8 @@ __device__ __forceinline__ void tail_interaction(const BatchDev &B, const UnitDe
     sig_add(sig, 0x40000000u | cell);
     sig_add(sig, 0x50000000u | bin);
     if (J.debug & 1u) {
-      uint32_t l = slot - U.slot_base;
-      uint32_t s_local = l / U.p_n, p_local = l - s_local * U.p_n;
+      uint32_t p_local, s_local;
+      slot_decode(U, slot, p_local, s_local);
       hpt_path_record *R = J.rec + rec_index(J, U, p_local, s_local);
       R->cache_cell = (int32_t)cell;
       R->cache_bin = (int32_t)bin;
@@ -568,8 +639,8 @@ __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
   uint32_t local = idx - U.acc_base;
   uint32_t p_local = local / G, t = local - p_local * G;
   if (t >= T) return;
-  uint32_t p = U.p_lo + p_local;
-  uint32_t cx = p % J.crop_w, cy = p / J.crop_w;
+  uint32_t cx, cy;
+  crop_xy(J, U.p_lo + p_local, cx, cy);
   using R = typename std::conditional<F64, double, float>::type;
   const uint32_t gw = J.grf_w, gh = J.grf_h;
   const float2 *G2 = J.grf + t;
@@ -578,7 +649,7 @@ __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
   unsigned long long sigsum = 0;
   const bool dbg_c = (J.debug & 2u) != 0, dbg_s = (J.debug & 4u) != 0 && t == 0;
   for (uint32_t s = 0; s < U.s_n; ++s) {
-    uint32_t slot = U.slot_base + s * U.p_n + p_local;
+    uint32_t slot = U.slot_base + p_local * U.s_n + s;
     if (dbg_s) sigsum += B.s_sig[slot];
     float amp = B.r_amp[slot];
     R cr = 0, ci = 0;
@@ -633,7 +704,7 @@ __global__ void __launch_bounds__(kBlock) k_cache_reduce(BatchDev B) {
   const JobDev &J = *U.job;
   uint32_t e_local = idx - U.acc_base;
   float sum = 0.f;
-  for (uint32_t s = 0; s < U.s_n; ++s) sum += B.r_amp[U.slot_base + s * U.p_n + e_local];
+  for (uint32_t s = 0; s < U.s_n; ++s) sum += B.r_amp[U.slot_base + e_local * U.s_n + s];
   float mean = sum / (float)J.cache_spb;
   size_t n_entries = (size_t)J.cache_res * J.cache_res * J.cache_res * J.cache_bins * J.cache_bins;
   J.cache_out[(size_t)U.ch * n_entries + U.p_lo + e_local] = __half_as_ushort(__float2half_rn(mean));
@@ -730,7 +801,8 @@ static inline uint32_t grid_for(uint64_t n) { return (uint32_t)((n + kBlock - 1)
 static inline uint32_t round8(uint32_t g) { return (g + 7u) & ~7u; }
 
 hipError_t launch_raygen(const BatchDev &B, hipStream_t st) {
-  hipLaunchKernelGGL(k_raygen, dim3(grid_for(B.n_paths)), dim3(kBlock), 0, st, B);
+  uint32_t g = (uint32_t)(((uint64_t)B.n_paths + kRaygenBlock - 1) / kRaygenBlock);
+  hipLaunchKernelGGL(k_raygen, dim3(g), dim3(kRaygenBlock), 0, st, B);
   return hipGetLastError();
 }
 
