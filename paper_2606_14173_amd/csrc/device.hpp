@@ -213,6 +213,29 @@ __device__ __forceinline__ void trav_init(Trav &T, F3 o, F3 d, float tmin, int32
   T.best.gid = -1;
 }
 
+// Traversal stack of one lane: the first kStackLds entries in LDS (lanes
+// interleaved with stride `stride`), deeper ones in global memory (`spill`,
+// one column per thread, entries `sstride` apart). Entries past the LDS
+// part are rare: they need a path with that many pending far children.
+struct Stack {
+  int32_t *lds;
+  uint32_t stride;
+  int32_t *spill;
+  uint32_t sstride;
+};
+
+__device__ __forceinline__ void push(const Stack &S, int &sp, int32_t v) {
+  if (sp < kStackLds) S.lds[sp * S.stride] = v;
+  else S.spill[(size_t)(sp - kStackLds) * S.sstride] = v;
+  ++sp;
+}
+
+__device__ __forceinline__ int32_t pop(const Stack &S, int &sp) {
+  if (sp == 0) return kDone;
+  --sp;
+  return sp < kStackLds ? S.lds[sp * S.stride] : S.spill[(size_t)(sp - kStackLds) * S.sstride];
+}
+
 // Advance this lane by one round: descend inner nodes, postponing the first
 // leaf reached and continuing with the next stack entry, until every active
 // lane of the wave holds a leaf or has nothing left to descend; then test
@@ -222,8 +245,7 @@ __device__ __forceinline__ void trav_init(Trav &T, F3 o, F3 d, float tmin, int32
 // make the result independent of the order. COUNT adds node visits and
 // primitive tests to nv / nt.
 template <bool COUNT>
-__device__ __forceinline__ void trav_step(Trav &T, GF4 N, GF4 P, int32_t *stack, uint32_t stride, uint32_t &nv,
-                                          uint32_t &nt) {
+__device__ __forceinline__ void trav_step(Trav &T, GF4 N, GF4 P, const Stack &St, uint32_t &nv, uint32_t &nt) {
   int32_t node = T.node;
   int sp = T.sp;
   bool has_leaf = false;
@@ -239,21 +261,20 @@ __device__ __forceinline__ void trav_step(Trav &T, GF4 N, GF4 P, int32_t *stack,
       box2(T.r, a, b, c, T.tmin, T.best.t, t0, t1, h0, h1);
       if (h0 && h1) {
         bool first0 = t0 <= t1;
-        stack[sp * stride] = first0 ? c1 : c0;
-        ++sp;
+        push(St, sp, first0 ? c1 : c0);
         node = first0 ? c0 : c1;
       } else if (h0) {
         node = c0;
       } else if (h1) {
         node = c1;
       } else {
-        node = sp > 0 ? stack[--sp * stride] : kDone;
+        node = pop(St, sp);
       }
     }
     if (node < 0 && !has_leaf) {  // postpone the leaf, keep descending
       has_leaf = true;
       leaf = node;
-      node = sp > 0 ? stack[--sp * stride] : kDone;
+      node = pop(St, sp);
     }
     bool ready = has_leaf || node == kDone || node < 0;
     if (__all(ready)) break;
@@ -264,7 +285,7 @@ __device__ __forceinline__ void trav_step(Trav &T, GF4 N, GF4 P, int32_t *stack,
   } else if (node < 0) {
     if (COUNT) nt += ((uint32_t)(~node) & 7u) + 1u;
     leaf_test(T.r, P, node, T.tmin, T.exclude, T.best);
-    node = sp > 0 ? stack[--sp * stride] : kDone;
+    node = pop(St, sp);
   }
   T.node = node;
   T.sp = sp;

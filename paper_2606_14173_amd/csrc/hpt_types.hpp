@@ -9,7 +9,16 @@ namespace hpt {
 
 constexpr int kMaxT = 64;
 constexpr int kStackMax = 64;        // BVH depth bound enforced by the builder
-constexpr int kRaysPerWave = 512;    // rays a traversal wave owns (lanes refill from them)
+#ifndef HPT_STACK_LDS
+#define HPT_STACK_LDS 16
+#endif
+constexpr int kStackLds = HPT_STACK_LDS;           // traversal stack entries per lane in LDS
+constexpr int kStackSpill = kStackMax - kStackLds;  // further entries per lane in global memory
+#ifndef HPT_TRACE_CHUNK
+#define HPT_TRACE_CHUNK 64
+#endif
+constexpr int kTraceChunk = HPT_TRACE_CHUNK;  // queue entries a traversal wave claims at a time
+constexpr uint32_t kTraceGridMax = 2048;      // traversal workgroups per launch (8 per CU)
 constexpr float kTmin = 1e-7f;       // self-intersection guard (metres)
 constexpr double kTminD = 1e-7;
 
@@ -112,8 +121,10 @@ struct BatchDev {
   float4 *q_ray[2];          // 2 per entry: (o, tmin), (d, exclude id bits)
   float *q_t[2];
   int32_t *q_gid[2];
-  uint32_t *counters;        // [0], [1]: queue lengths; [2]: rays traced
+  uint32_t *counters;        // [0], [1]: queue lengths; [2]: rays traced; [4], [5]: traversal claims
   unsigned long long *work;  // [0] node visits, [1] primitive tests (counting traversal)
+  int32_t *stack_spill;      // [kStackSpill][spill_threads] traversal stack beyond the LDS part
+  uint32_t spill_threads;    // threads the spill has a column for
   const SceneDev *scene_uniform;  // the one scene of every unit, or null for mixed batches
 };
 

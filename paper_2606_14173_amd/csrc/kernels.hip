@@ -240,37 +240,47 @@ __global__ void __launch_bounds__(kRaygenBlock) k_raygen(BatchDev B) {
 }
 
 // ------------------------------------------------------------------ trace
-// FP32 closest hit for every ray of queue q. Each wave owns kRaysPerWave
-// consecutive queue entries; a lane that finishes its ray takes the next one
-// of the wave's range, so lanes do not idle while the wave's longest ray
-// finishes. DEPTH: LDS stack entries per lane (>= the deepest inner-node
-// path of the batch's BVHs).
-template <bool COUNT, int DEPTH>
+// FP32 closest hit for every ray of queue q. Waves claim kTraceChunk
+// consecutive queue entries at a time from the queue's claim counter
+// (counters[4 + q], zeroed by the shading pass of the previous use of the
+// queue), and a lane that finishes its ray takes the next entry of the
+// wave's chunk, so lanes do not idle while the wave's longest ray finishes
+// and the launch ends when the queue is drained, however short the queue.
+// The traversal stack is kStackLds entries per lane in LDS, then the lane's
+// column of the global spill.
+template <bool COUNT>
 __global__ void __launch_bounds__(kBlock) k_trace(BatchDev B, int q) {
-  __shared__ int32_t stack[DEPTH * kBlock];
-#ifdef HPT_STAGE_RESULTS
-  __shared__ float2 res[kBlock / 64][kRaysPerWave];
-#endif
+  __shared__ int32_t stack[kStackLds * kBlock];
   const uint32_t n = B.counters[q];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     B.counters[q ^ 1] = 0;
     B.counters[2] += n;
   }
-  const uint32_t wave = (xcd_block() * blockDim.x + threadIdx.x) / 64u;
-  const uint32_t begin = wave * (uint32_t)kRaysPerWave;
-  uint32_t next = begin;
-  if (next >= n) return;
-  const uint32_t end = min(n, next + (uint32_t)kRaysPerWave);
+  uint32_t *claim = B.counters + 4 + q;
   const uint32_t lane = __lane_id();
-  int32_t *st = stack + threadIdx.x;
+  const Stack St{stack + threadIdx.x, kBlock, B.stack_spill + xcd_block() * blockDim.x + threadIdx.x,
+                 B.spill_threads};
   uint32_t nv = 0, nt = 0;
-  int64_t i = -1;  // queue entry of this lane's ray, -1: none
+  uint32_t next = 0, end = 0;  // unassigned entries of the wave's chunk
+  bool more = true;            // the queue may hold unclaimed entries
+  int64_t i = -1;              // queue entry of this lane's ray, -1: none
   Trav T;
   const SceneDev *S = B.scene_uniform;
   GF4 N = as_global(S ? S->nodes : nullptr), P = as_global(S ? S->prims : nullptr);
   uint32_t nn = S ? S->n_nodes : 0;
   for (;;) {
-    // refill idle lanes from the wave's range, in lane order
+    if (more && next >= end && __any(i < 0)) {  // claim the next chunk
+      uint32_t c = 0;
+      if (lane == 0) c = atomicAdd(claim, (uint32_t)kTraceChunk);
+      c = __shfl(c, 0);
+      if (c >= n) {
+        more = false;
+      } else {
+        next = c;
+        end = min(n, c + (uint32_t)kTraceChunk);
+      }
+    }
+    // refill idle lanes from the chunk, in lane order
     unsigned long long need = __ballot(i < 0 && next < end);
     if (need) {
       if (i < 0) {
@@ -286,29 +296,21 @@ __global__ void __launch_bounds__(kBlock) k_trace(BatchDev B, int q) {
           trav_init(T, f3(r0.x, r0.y, r0.z), f3(r1.x, r1.y, r1.z), r0.w, __float_as_int(r1.w), nn == 0);
         }
       }
-      next += (uint32_t)__popcll(need);
+      next = min(end, next + (uint32_t)__popcll(need));
     }
-    if (!__any(i >= 0)) break;
+    if (!__any(i >= 0)) {
+      if (!more) break;
+      continue;
+    }
     if (i >= 0) {
-      if (T.node != kDone) trav_step<COUNT>(T, N, P, st, kBlock, nv, nt);
+      if (T.node != kDone) trav_step<COUNT>(T, N, P, St, nv, nt);
       if (T.node == kDone) {
-#ifdef HPT_STAGE_RESULTS
-        res[threadIdx.x / 64u][i - begin] = make_float2(T.best.t, __int_as_float(T.best.gid));
-#else
         B.q_t[q][i] = T.best.t;
         B.q_gid[q][i] = T.best.gid;
-#endif
         i = -1;
       }
     }
   }
-#ifdef HPT_STAGE_RESULTS
-  for (uint32_t k = begin + lane; k < end; k += 64) {
-    float2 v = res[threadIdx.x / 64u][k - begin];
-    B.q_t[q][k] = v.x;
-    B.q_gid[q][k] = __float_as_int(v.y);
-  }
-#endif
   if (COUNT) {
     for (int off = 32; off > 0; off >>= 1) {
       nv += __shfl_xor(nv, off);
@@ -599,6 +601,7 @@ __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, 
 __global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
   uint32_t n = B.counters[q];
   int qo = q ^ 1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) B.counters[4 + q] = 0;  // traversal claims of queue q
   uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
     uint32_t i = base + threadIdx.x;
@@ -806,21 +809,21 @@ hipError_t launch_raygen(const BatchDev &B, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <int D>
-static void trace_launch(const BatchDev &B, int q, bool count, hipStream_t st) {
-  // one wave per kRaysPerWave rays of the largest possible queue
-  uint64_t waves = ((uint64_t)B.n_paths + kRaysPerWave - 1) / kRaysPerWave;
+uint32_t trace_grid(uint32_t n_paths) {
+  // enough waves to fill every CU; waves beyond the resident ones find the
+  // queue drained and exit
+  uint64_t waves = ((uint64_t)n_paths + kTraceChunk - 1) / kTraceChunk;
   uint32_t g = round8((uint32_t)((waves * 64 + kBlock - 1) / kBlock));
-  if (count) hipLaunchKernelGGL((k_trace<true, D>), dim3(g), dim3(kBlock), 0, st, B, q);
-  else hipLaunchKernelGGL((k_trace<false, D>), dim3(g), dim3(kBlock), 0, st, B, q);
+  return g < kTraceGridMax ? g : kTraceGridMax;
 }
 
-hipError_t launch_trace(const BatchDev &B, int q, bool count, uint32_t depth, hipStream_t st) {
-  // depth = levels including the leaf level; the stack holds one entry per inner level
-  if (depth <= 17) trace_launch<16>(B, q, count, st);
-  else if (depth <= 25) trace_launch<24>(B, q, count, st);
-  else if (depth <= 33) trace_launch<32>(B, q, count, st);
-  else trace_launch<kStackMax>(B, q, count, st);
+uint32_t trace_block() { return kBlock; }
+
+hipError_t launch_trace(const BatchDev &B, int q, bool count, hipStream_t st) {
+  uint32_t g = trace_grid(B.n_paths);
+  if ((uint64_t)g * kBlock > B.spill_threads) return hipErrorInvalidValue;
+  if (count) hipLaunchKernelGGL(k_trace<true>, dim3(g), dim3(kBlock), 0, st, B, q);
+  else hipLaunchKernelGGL(k_trace<false>, dim3(g), dim3(kBlock), 0, st, B, q);
   return hipGetLastError();
 }
 

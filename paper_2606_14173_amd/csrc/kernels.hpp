@@ -9,8 +9,12 @@ namespace hpt {
 hipError_t launch_raygen(const BatchDev &B, hipStream_t st);
 // One interaction for every ray in queue q: closest hit (trace), then
 // shading that compacts continuing rays into queue q^1 (shade).
-// depth: the deepest BVH among the batch's scenes (sizes the LDS stack).
-hipError_t launch_trace(const BatchDev &B, int q, bool count, uint32_t depth, hipStream_t st);
+// Fails (hipErrorInvalidValue) if the batch's stack spill is too small.
+hipError_t launch_trace(const BatchDev &B, int q, bool count, hipStream_t st);
+// Workgroups and threads per workgroup of a traversal launch for a batch of
+// n_paths (they size the stack spill).
+uint32_t trace_grid(uint32_t n_paths);
+uint32_t trace_block();
 hipError_t launch_shade(const BatchDev &B, int q, hipStream_t st);
 hipError_t launch_accumulate(const BatchDev &B, bool has_f64, bool has_f32, hipStream_t st);
 hipError_t launch_cache_reduce(const BatchDev &B, hipStream_t st);

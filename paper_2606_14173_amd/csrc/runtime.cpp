@@ -47,6 +47,7 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
 }
 
 constexpr uint32_t kMaxUnitsPerBatch = 4096;
+// path state, results and two queues
 constexpr size_t kBytesPerPath = 4 * 4 + 9 * 8 + 4 * 4 + 8 + 4 + 4 * 4 + 8 + 4 + 2 * (4 + 32 + 4 + 4);
 
 struct Scene {
@@ -143,6 +144,7 @@ struct hpt_ctx {
   std::vector<std::unique_ptr<Grf>> grfs;
   // batch buffers
   std::vector<void *> batch_bufs;
+  uint64_t batch_bytes = 0;   // device bytes of batch_bufs
   BatchDev batch{};
   UnitDev *d_units = nullptr, *h_units = nullptr;
   uint64_t batches = 0, jobs_done = 0;
@@ -363,14 +365,13 @@ std::vector<Picked> pick_batch(hpt_ctx *C) {
 // Run one batch on the context stream (lock not held).
 hpt_status run_batch(hpt_ctx *C, const std::vector<Picked> &P, uint32_t profile, double &gpu_ms,
                      uint64_t &rays, hpt_kernel_time *kt, uint64_t *work) {
-  uint32_t slot = 0, acc = 0, max_b = 0, max_depth = 0;
+  uint32_t slot = 0, acc = 0, max_b = 0;
   bool has_f64 = false, has_f32 = false, has_holo = false, has_cache = false;
   for (size_t k = 0; k < P.size(); ++k) {
     const Unit &u = P[k].job->units[P[k].unit];
     UnitDev &d = C->h_units[k];
     d.kind = u.kind; d.ch = u.ch; d.p_lo = u.p_lo; d.p_n = u.p_n; d.s_lo = u.s_lo; d.s_n = u.s_n;
     d.slot_base = slot; d.acc_base = acc; d.job = P[k].job->dev; d.scene = P[k].job->scene->dev;
-    max_depth = std::max(max_depth, P[k].job->scene->info.max_depth);
     const JobDev &J = P[k].job->host;
     slot += u.p_n * u.s_n;
     acc += u.kind == UNIT_HOLO ? u.p_n * frame_group(J.T) : u.p_n;
@@ -407,13 +408,13 @@ hpt_status run_batch(hpt_ctx *C, const std::vector<Picked> &P, uint32_t profile,
     }
   };
   e = hipMemcpyAsync(C->d_units, C->h_units, P.size() * sizeof(UnitDev), hipMemcpyHostToDevice, C->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(B.counters, 0, 4 * sizeof(uint32_t), C->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(B.counters, 0, 8 * sizeof(uint32_t), C->stream);
   if (e == hipSuccess && profile >= 2) e = hipMemsetAsync(B.work, 0, 2 * sizeof(unsigned long long), C->stream);
   if (e == hipSuccess) e = hipEventRecord(C->ev0, C->stream);
   timed(HPT_K_RAYGEN, [&] { return launch_raygen(B, C->stream); });
   for (uint32_t it = 0; it <= max_b; ++it) {
     int q = (int)(it & 1u);
-    timed(HPT_K_TRACE, [&] { return launch_trace(B, q, profile >= 2, max_depth, C->stream); });
+    timed(HPT_K_TRACE, [&] { return launch_trace(B, q, profile >= 2, C->stream); });
     timed(HPT_K_SHADE, [&] { return launch_shade(B, q, C->stream); });
   }
   if (has_holo) timed(HPT_K_ACCUMULATE, [&] { return launch_accumulate(B, has_f64, has_f32, C->stream); });
@@ -541,6 +542,7 @@ hpt_status alloc_batch(hpt_ctx *C) {
   auto A = [&](void **p, size_t bytes) {
     if (C->alloc(p, bytes) != hipSuccess) return false;
     C->batch_bufs.push_back(*p);
+    C->batch_bytes += bytes;
     return true;
   };
   bool ok = true;
@@ -558,6 +560,8 @@ hpt_status alloc_batch(hpt_ctx *C) {
           A((void **)&B.q_t[q], 4ull * N) && A((void **)&B.q_gid[q], 4ull * N);
   ok &= A((void **)&B.counters, 64);
   ok &= A((void **)&B.work, 64);
+  B.spill_threads = trace_grid(N) * trace_block();
+  ok &= A((void **)&B.stack_spill, (size_t)kStackSpill * B.spill_threads * sizeof(int32_t));
   ok &= A((void **)&C->d_units, kMaxUnitsPerBatch * sizeof(UnitDev));
   if (!ok) return fail(HPT_ENOMEM, "batch buffer allocation failed");
   if (hipHostMalloc((void **)&C->h_units, kMaxUnitsPerBatch * sizeof(UnitDev), hipHostMallocDefault) !=
@@ -602,11 +606,14 @@ hpt_status hpt_create(int device, uint64_t budget, hpt_ctx **out) {
   size_t free_b = 0, total_b = 0;
   (void)hipMemGetInfo(&free_b, &total_b);
   C->budget = budget ? budget : (uint64_t)(0.9 * (double)free_b);
-  // path capacity: at most 2^24, at most a quarter of the budget
-  uint64_t cap = std::min<uint64_t>(1ull << 24, C->budget / 4 / kBytesPerPath);
-  uint32_t c = 1u << 16;
-  while ((uint64_t)c * 2 <= cap) c *= 2;
-  if ((uint64_t)c * kBytesPerPath > C->budget) return fail(HPT_EBUDGET, "budget too small for path state");
+  // path capacity: a power of two, at most 2^24, batch buffers (path state
+  // and traversal stack spill) at most a quarter of the budget
+  auto batch_bytes = [](uint32_t n) {
+    return (uint64_t)n * kBytesPerPath + (uint64_t)kStackSpill * 4 * trace_grid(n) * trace_block();
+  };
+  uint32_t c = 1u << 24;
+  while (c > (1u << 16) && batch_bytes(c) > C->budget / 4) c /= 2;
+  if (batch_bytes(c) > C->budget) return fail(HPT_EBUDGET, "budget too small for path state");
   C->capacity = c;
   if (hipStreamCreateWithFlags(&C->stream, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&C->aux, hipStreamNonBlocking) != hipSuccess ||
@@ -969,9 +976,7 @@ hpt_status hpt_trace_submit(hpt_ctx *C, uint64_t scene, const hpt_job_desc *d, v
              J->n_contrib * sizeof(float2) + J->n_sig * 8 + sizeof(JobDev);
   J->grf_bytes = grf_table_bytes(d->grf_w, d->grf_h, d->T) + grf_temp_bytes(d->grf_w, d->grf_h, d->T);
   // the fixed part (batch buffers, scenes, caches) never shrinks; refuse what can never fit
-  uint64_t fixed = 0;
-  for (void *p : C->batch_bufs) (void)p;
-  fixed = (uint64_t)C->capacity * kBytesPerPath;
+  uint64_t fixed = C->batch_bytes;
   for (auto &kv : C->scenes) fixed += kv.second->bytes + kv.second->cache_bytes;
   if (fixed + J->bytes + J->grf_bytes > C->budget) return fail(HPT_EBUDGET, "job can never fit the budget");
   split_units(J.get());
