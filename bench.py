@@ -15,6 +15,7 @@ duration), the FP64 oracle timed on host cores on a bounded crop, and the
 phase error of the GPU against the oracle on that crop.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -32,6 +33,36 @@ PEAK_HBM = 8.0e12      # bytes/s
 # node = two ray/box slab tests; one primitive = one watertight triangle test
 FLOP_NODE = 55
 FLOP_PRIM = 47
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, kept with
+# a hash of the sources they were taken on (library and workload generator)
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "k_trace_hologram_1080p_rgb_T24_hbm_traffic.md")
+
+
+def source_hash():
+    h = hashlib.sha256()
+    dirs = [os.path.join(ROOT, "paper_2606_14173_amd", "csrc"), os.path.join(ROOT, "scenes")]
+    for d in dirs:
+        for f in sorted(os.listdir(d)):
+            if f.endswith((".hip", ".hpp", ".cpp", ".h", ".py")):
+                with open(os.path.join(d, f), "rb") as fh:
+                    h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel):
+    """Counter-measured HBM bytes per launch of `kernel` (read + written), or
+    None when the sources changed after the counters were taken."""
+    try:
+        lines = open(TRAFFIC_PROFILE).read().splitlines()
+    except OSError:
+        return None
+    for ln in lines:
+        if not ln.startswith("traffic-record:"):
+            continue
+        kv = dict(x.split("=", 1) for x in ln.split()[1:])
+        if kv.get("kernel") == kernel and kv.get("sources") == source_hash():
+            return int(kv["read_bytes"]) + int(kv["write_bytes"])
+    return None
 
 
 def log(*a):
@@ -172,7 +203,7 @@ def main():
         achieved = flop_launch / (avg_ms * 1e-3) / 1e12
         roof = {"kernel": "k_trace", "bound": "alu", "achieved": round(achieved, 3),
                 "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                "frac": round(achieved / (PEAK_FP32 / 1e12), 4), "traffic": None,
+                "frac": round(achieved / (PEAK_FP32 / 1e12), 4), "traffic": recorded_traffic("k_trace"),
                 "avg_launch_ms": round(avg_ms, 4), "rays_per_launch": round(tr["items"] / tr["launches"]),
                 "node_visits_per_ray": round(nv, 2), "prim_tests_per_ray": round(nt, 2),
                 "flop_per_ray": round(flop_ray, 1),

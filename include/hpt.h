@@ -206,6 +206,30 @@ typedef struct {
 } hpt_ctx_stats;
 hpt_status hpt_ctx_stats_get(hpt_ctx *ctx, hpt_ctx_stats *out);
 
+/* ---------------------------------------------------------------- propagation
+ * Angular-spectrum propagation (second stage of the two-stage scheme, Sec.
+ * 4.4; angular spectrum as the field's Fourier transform, Sec. 3): carries
+ * fields recorded on one plane (e.g. a wave recording plane near the scene)
+ * a distance `distance` further from the scene (metres; negative: back
+ * towards it). Each field is zero-padded on each axis to the next power of two
+ * >= twice its size (field in the top-left corner), Fourier transformed,
+ * multiplied by H(f) = exp(+i 2 pi distance sqrt(1/lambda^2 - |f|^2)) (0 for
+ * evanescent frequencies; with HPT_ASM_BAND_LIMIT also 0 where
+ * |f_x| > 1 / (lambda sqrt((2 distance / (P_x pitch))^2 + 1)), likewise y, the
+ * band limit of Matsushima and Shimobaba 2009), transformed back, and cropped
+ * to its window. FP32 transforms; the transfer function's phase in FP64.
+ *   d_in, d_out: device, complex64 [n_fields][height][width] (interleaved
+ *     re, im), row-major; may be the same buffer. Caller-owned.
+ *   width, height: 1..4096; pitch, lambda > 0 (metres); distance finite.
+ * Synchronous (returns when d_out is written). Scratch (two [height][P_x]
+ * complex64 buffers per field of a chunk of fields, at most 1 GiB) is taken
+ * from the context's budget for the call. EINVAL on bad arguments, EBUDGET if
+ * one field's scratch does not fit, EDEVICE on a HIP error. */
+#define HPT_ASM_BAND_LIMIT 1u
+hpt_status hpt_asm_propagate(hpt_ctx *ctx, const void *d_in, void *d_out, uint32_t n_fields,
+                             uint32_t width, uint32_t height, double pitch, double lambda,
+                             double distance, uint32_t flags);
+
 /* ---------------------------------------------------------------- profiling
  * Level 1: HIP events around every kernel launch on the context stream,
  * summed per kernel kind. Level 2: also counts BVH node visits and primitive

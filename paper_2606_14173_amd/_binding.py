@@ -108,7 +108,10 @@ SIGNATURES = {
     "hpt_profile_set": (C.c_int, [_vp, _u32]),
     "hpt_profile_get": (C.c_int, [_vp, C.POINTER(KernelTime), C.POINTER(_u64), C.POINTER(_u64)]),
     "hpt_profile_reset": (C.c_int, [_vp]),
+    "hpt_asm_propagate": (C.c_int, [_vp, _vp, _vp, _u32, _u32, _u32, C.c_double, C.c_double, C.c_double,
+                                    _u32]),
 }
+ASM_BAND_LIMIT = 1
 
 _LIB = None
 
@@ -120,6 +123,11 @@ def load():
         if not os.path.exists(LIB_PATH):
             raise ImportError("libhpt.so is not built (run __graft_entry__.build()); "
                               "the wave path tracer has no CPU fallback")
+        # One HIP runtime per process: torch's libraries name the runtime
+        # without its version suffix, so if libhpt.so loaded the system copy
+        # first, torch would load a second copy that finds no device. Loading
+        # torch first makes libhpt.so bind to the copy already in the process.
+        import torch  # noqa: F401
         lib = C.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(lib, name)
@@ -297,6 +305,14 @@ class Context:
         out = np.zeros((gh, gw, T), dtype=np.complex64)
         _check(self.lib.hpt_grf_read(self.h, gw, gh, T, seed, out.ctypes.data, out.size * 2))
         return out
+
+    def asm_propagate(self, src, dst, n_fields, width, height, pitch, lam, distance, band_limit=True):
+        """Angular-spectrum propagation of n_fields complex64 [height][width]
+        fields; src, dst: device pointers (int) or torch tensors."""
+        ps = src if isinstance(src, int) else src.data_ptr()
+        pd = dst if isinstance(dst, int) else dst.data_ptr()
+        _check(self.lib.hpt_asm_propagate(self.h, ps, pd, n_fields, width, height, float(pitch), float(lam),
+                                          float(distance), ASM_BAND_LIMIT if band_limit else 0))
 
     # profiling
     def profile(self, level):

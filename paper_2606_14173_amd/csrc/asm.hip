@@ -1,0 +1,271 @@
+// Angular-spectrum propagation of recorded fields on gfx950: the second
+// stage of the two-stage scheme (Sec. 4.4), which carries the field traced
+// onto a wave recording plane to the hologram plane; the angular spectrum is
+// the field's Fourier transform (Sec. 3).
+//
+// Per field [h][w] (complex64), zero-padded to [Py][Px] (powers of two,
+// >= 2h, >= 2w), with the field in the top-left corner:
+//   k_fft_rows     FFT of the h non-zero rows, length Px       [h][w]  -> A [h][Px]
+//   k_transpose    A -> B [Px][h]
+//   k_fft_columns  per column: zero-pad to Py, FFT, multiply by the transfer
+//                  function, inverse FFT, keep rows [0, h)     B -> B
+//   k_transpose    B -> A [h][Px]
+//   k_ifft_rows    inverse FFT of each row, keep [0, w), scale 1/(Px Py)
+// Transfer function H = exp(+i 2 pi z sqrt(1/lambda^2 - f^2)) on propagating
+// frequencies (phase reduced in FP64), optionally band-limited
+// (Matsushima and Shimobaba, 2009), 0 on evanescent ones.
+//
+// Line FFTs run in LDS, one workgroup per line: radix-4 Stockham stages
+// (Govindaraju et al., SC 2008 formulation), a final radix-2 stage when
+// log2(n) is odd; each stage reads its operands into registers, synchronises,
+// and writes the results back in place. Twiddles exp(-+2 pi i k / L) come from
+// sincospif of the exact rational k / L.
+#include <hip/hip_runtime.h>
+
+#include "asm.hpp"
+
+namespace hpt {
+namespace {
+
+constexpr int kFftThreads = 256;
+constexpr int kFftMax = 8192;   // longest line (LDS: 64 KB of complex64)
+
+struct C2 { float x, y; };
+__device__ __forceinline__ C2 c2(float x, float y) { return {x, y}; }
+__device__ __forceinline__ C2 add(C2 a, C2 b) { return {a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ C2 sub(C2 a, C2 b) { return {a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ C2 mul(C2 a, C2 b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+// multiply by -i (forward) or +i (inverse)
+__device__ __forceinline__ C2 rot(C2 a, bool inv) { return inv ? c2(-a.y, a.x) : c2(a.y, -a.x); }
+
+// exp(s 2 pi i num / den) with s = -1 forward, +1 inverse
+__device__ __forceinline__ C2 twiddle(uint32_t num, uint32_t den, bool inv) {
+  float sn, cs;
+  sincospif(2.0f * (float)num / (float)den, &sn, &cs);
+  return c2(cs, inv ? sn : -sn);
+}
+
+// In-place FFT of the n = 2^lg values in LDS buffer x (all threads of the
+// block take part; returns synchronised). Each thread handles butterflies
+// j = tid + u * kFftThreads; the per-thread operands stay in registers
+// (static indices), written back after the whole stage has been read.
+// U4: butterflies per thread and radix-4 stage (n <= 4 * U4 * kFftThreads).
+template <int U4>
+__device__ void lds_fft(C2 *x, uint32_t n, uint32_t lg, bool inv) {
+  constexpr int U2 = 2 * U4;
+  const uint32_t tid = threadIdx.x;
+  uint32_t Ns = 1;
+  const uint32_t q = n / 4;
+  for (uint32_t s = 0; s < lg / 2; ++s) {
+    C2 v[U4][4];
+#pragma unroll
+    for (int u = 0; u < U4; ++u) {
+      const uint32_t j = tid + (uint32_t)u * kFftThreads;
+      if (j < q) {
+        const uint32_t k = j % Ns;
+        C2 a0 = x[j], a1 = x[j + q], a2 = x[j + 2 * q], a3 = x[j + 3 * q];
+        if (Ns > 1) {
+          a1 = mul(a1, twiddle(k, 4 * Ns, inv));
+          a2 = mul(a2, twiddle(2 * k, 4 * Ns, inv));
+          a3 = mul(a3, twiddle(3 * k, 4 * Ns, inv));
+        }
+        C2 b0 = add(a0, a2), b1 = sub(a0, a2), b2 = add(a1, a3), b3 = rot(sub(a1, a3), inv);
+        v[u][0] = add(b0, b2);
+        v[u][1] = add(b1, b3);
+        v[u][2] = sub(b0, b2);
+        v[u][3] = sub(b1, b3);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U4; ++u) {
+      const uint32_t j = tid + (uint32_t)u * kFftThreads;
+      if (j < q) {
+        const uint32_t d = (j / Ns) * Ns * 4 + j % Ns;
+        x[d] = v[u][0];
+        x[d + Ns] = v[u][1];
+        x[d + 2 * Ns] = v[u][2];
+        x[d + 3 * Ns] = v[u][3];
+      }
+    }
+    __syncthreads();
+    Ns *= 4;
+  }
+  if (lg & 1u) {  // final radix-2 stage
+    const uint32_t hn = n / 2;
+    C2 v[U2][2];
+#pragma unroll
+    for (int u = 0; u < U2; ++u) {
+      const uint32_t j = tid + (uint32_t)u * kFftThreads;
+      if (j < hn) {
+        C2 a0 = x[j], a1 = x[j + hn];
+        if (Ns > 1) a1 = mul(a1, twiddle(j % Ns, 2 * Ns, inv));
+        v[u][0] = add(a0, a1);
+        v[u][1] = sub(a0, a1);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U2; ++u) {
+      const uint32_t j = tid + (uint32_t)u * kFftThreads;
+      if (j < hn) {
+        const uint32_t d = (j / Ns) * Ns * 2 + j % Ns;
+        x[d] = v[u][0];
+        x[d + Ns] = v[u][1];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Forward FFT of row (f, y) of in [nf][h][w], zero-padded to Px -> A [nf][h][Px].
+template <int U4>
+__global__ void __launch_bounds__(kFftThreads) k_fft_rows(const float2 *in, float2 *A, uint32_t w, uint32_t h,
+                                                          uint32_t px, uint32_t lgx) {
+  extern __shared__ C2 lds[];
+  const size_t row = blockIdx.x;  // f * h + y
+  const float2 *src = in + row * w;
+  for (uint32_t i = threadIdx.x; i < px; i += kFftThreads) {
+    float2 v = i < w ? src[i] : make_float2(0.f, 0.f);
+    lds[i] = c2(v.x, v.y);
+  }
+  __syncthreads();
+  lds_fft<U4>(lds, px, lgx, false);
+  float2 *dst = A + row * px;
+  for (uint32_t i = threadIdx.x; i < px; i += kFftThreads) dst[i] = make_float2(lds[i].x, lds[i].y);
+}
+
+// Transpose of each of nf matrices [rows][cols] -> [cols][rows], 32 x 32 tiles.
+__global__ void __launch_bounds__(256) k_transpose(const float2 *in, float2 *out, uint32_t rows, uint32_t cols) {
+  __shared__ float2 tile[32][33];
+  const uint32_t f = blockIdx.z;
+  const uint32_t c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+  const float2 *src = in + (size_t)f * rows * cols;
+  float2 *dst = out + (size_t)f * rows * cols;
+  const uint32_t tx = threadIdx.x & 31u, ty = threadIdx.x >> 5;  // 32 x 8
+  for (uint32_t k = ty; k < 32; k += 8) {
+    uint32_t r = r0 + k, c = c0 + tx;
+    if (r < rows && c < cols) tile[k][tx] = src[(size_t)r * cols + c];
+  }
+  __syncthreads();
+  for (uint32_t k = ty; k < 32; k += 8) {
+    uint32_t c = c0 + k, r = r0 + tx;
+    if (r < rows && c < cols) dst[(size_t)c * rows + r] = tile[tx][k];
+  }
+}
+
+// Column kx of every field: B [nf][Px][h] holds the row spectra transposed.
+// Zero-pad the column to Py, FFT, multiply by H(f_x, f_y), inverse FFT, and
+// keep rows [0, h).
+template <int U4>
+__global__ void __launch_bounds__(kFftThreads) k_fft_columns(float2 *B, uint32_t h, uint32_t px, uint32_t py,
+                                                             uint32_t lgy, AsmParams P) {
+  extern __shared__ C2 lds[];
+  const size_t line = blockIdx.x;  // f * Px + kx
+  const uint32_t kx = (uint32_t)(line % px);
+  float2 *col = B + line * h;
+  for (uint32_t i = threadIdx.x; i < py; i += kFftThreads) {
+    float2 v = i < h ? col[i] : make_float2(0.f, 0.f);
+    lds[i] = c2(v.x, v.y);
+  }
+  __syncthreads();
+  lds_fft<U4>(lds, py, lgy, false);
+  // transfer function: FFT frequency order k / (P d) for k < P/2, (k - P) / (P d) otherwise
+  const double fx = (kx < px / 2 ? (double)kx : (double)kx - (double)px) * P.dfx;
+  const bool ok_x = !P.band_limit || fabs(fx) <= P.lim_x;
+  for (uint32_t i = threadIdx.x; i < py; i += kFftThreads) {
+    const double fy = (i < py / 2 ? (double)i : (double)i - (double)py) * P.dfy;
+    const double f2 = fx * fx + fy * fy;
+    C2 hv = c2(0.f, 0.f);
+    if (ok_x && (!P.band_limit || fabs(fy) <= P.lim_y) && f2 < P.inv_lam2) {
+      // z sqrt(1/lambda^2 - f^2) = z/lambda - z f^2 / (1/lambda + sqrt(1/lambda^2 - f^2)),
+      // the first term reduced modulo 1 on the host
+      const double rev = P.z_rev_frac - P.z * f2 / (P.inv_lam + sqrt(P.inv_lam2 - f2));
+      const double fr = rev - floor(rev);
+      double sn, cs;
+      sincospi(2.0 * fr, &sn, &cs);
+      hv = c2((float)cs, (float)sn);
+    }
+    lds[i] = mul(lds[i], hv);
+  }
+  __syncthreads();
+  lds_fft<U4>(lds, py, lgy, true);
+  for (uint32_t i = threadIdx.x; i < h; i += kFftThreads) col[i] = make_float2(lds[i].x, lds[i].y);
+}
+
+// Inverse FFT of row (f, y) of A [nf][h][Px]; keep [0, w), scale -> out [nf][h][w].
+template <int U4>
+__global__ void __launch_bounds__(kFftThreads) k_ifft_rows(const float2 *A, float2 *out, uint32_t w, uint32_t h,
+                                                           uint32_t px, uint32_t lgx, float scale) {
+  extern __shared__ C2 lds[];
+  const size_t row = blockIdx.x;
+  const float2 *src = A + row * px;
+  for (uint32_t i = threadIdx.x; i < px; i += kFftThreads) {
+    float2 v = src[i];
+    lds[i] = c2(v.x, v.y);
+  }
+  __syncthreads();
+  lds_fft<U4>(lds, px, lgx, true);
+  float2 *dst = out + row * w;
+  for (uint32_t i = threadIdx.x; i < w; i += kFftThreads) dst[i] = make_float2(lds[i].x * scale, lds[i].y * scale);
+}
+
+uint32_t log2u(uint32_t n) {
+  uint32_t l = 0;
+  while ((1u << l) < n) ++l;
+  return l;
+}
+
+template <int U4>
+void launch_rows(bool inv, const float2 *in, float2 *out, uint32_t nrows, uint32_t w, uint32_t h, uint32_t px,
+                 uint32_t lgx, float scale, hipStream_t st) {
+  if (!inv)
+    hipLaunchKernelGGL(k_fft_rows<U4>, dim3(nrows), dim3(kFftThreads), px * sizeof(C2), st, in, out, w, h, px, lgx);
+  else
+    hipLaunchKernelGGL(k_ifft_rows<U4>, dim3(nrows), dim3(kFftThreads), px * sizeof(C2), st, in, out, w, h, px, lgx,
+                       scale);
+}
+
+void rows(bool inv, const float2 *in, float2 *out, uint32_t nrows, uint32_t w, uint32_t h, uint32_t px,
+          uint32_t lgx, float scale, hipStream_t st) {
+  if (px <= 4 * kFftThreads) launch_rows<1>(inv, in, out, nrows, w, h, px, lgx, scale, st);
+  else if (px <= 8 * kFftThreads) launch_rows<2>(inv, in, out, nrows, w, h, px, lgx, scale, st);
+  else if (px <= 16 * kFftThreads) launch_rows<4>(inv, in, out, nrows, w, h, px, lgx, scale, st);
+  else launch_rows<8>(inv, in, out, nrows, w, h, px, lgx, scale, st);
+}
+
+void columns(float2 *B, uint32_t ncols, uint32_t h, uint32_t px, uint32_t py, uint32_t lgy, const AsmParams &P,
+             hipStream_t st) {
+  const size_t sh = py * sizeof(C2);
+  if (py <= 4 * kFftThreads)
+    hipLaunchKernelGGL(k_fft_columns<1>, dim3(ncols), dim3(kFftThreads), sh, st, B, h, px, py, lgy, P);
+  else if (py <= 8 * kFftThreads)
+    hipLaunchKernelGGL(k_fft_columns<2>, dim3(ncols), dim3(kFftThreads), sh, st, B, h, px, py, lgy, P);
+  else if (py <= 16 * kFftThreads)
+    hipLaunchKernelGGL(k_fft_columns<4>, dim3(ncols), dim3(kFftThreads), sh, st, B, h, px, py, lgy, P);
+  else
+    hipLaunchKernelGGL(k_fft_columns<8>, dim3(ncols), dim3(kFftThreads), sh, st, B, h, px, py, lgy, P);
+}
+
+}  // namespace
+
+uint32_t asm_padded(uint32_t n) {
+  uint32_t p = 1;
+  while (p < 2 * n) p *= 2;
+  return p;
+}
+
+hipError_t launch_asm(const float2 *in, float2 *out, float2 *A, float2 *B, uint32_t nf, uint32_t w, uint32_t h,
+                      const AsmParams &P, hipStream_t st) {
+  const uint32_t px = asm_padded(w), py = asm_padded(h);
+  if (px > (uint32_t)kFftMax || py > (uint32_t)kFftMax || nf == 0 || w == 0 || h == 0) return hipErrorInvalidValue;
+  const uint32_t lgx = log2u(px), lgy = log2u(py);
+  rows(false, in, A, nf * h, w, h, px, lgx, 1.0f, st);
+  hipLaunchKernelGGL(k_transpose, dim3((px + 31) / 32, (h + 31) / 32, nf), dim3(256), 0, st, A, B, h, px);
+  columns(B, nf * px, h, px, py, lgy, P, st);
+  hipLaunchKernelGGL(k_transpose, dim3((h + 31) / 32, (px + 31) / 32, nf), dim3(256), 0, st, B, A, px, h);
+  rows(true, A, out, nf * h, w, h, px, lgx, 1.0f / ((float)px * (float)py), st);
+  return hipGetLastError();
+}
+
+}  // namespace hpt

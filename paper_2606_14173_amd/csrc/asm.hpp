@@ -1,0 +1,29 @@
+// Angular-spectrum propagation launcher (second stage of the two-stage
+// scheme, Sec. 4.4).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hpt {
+
+// Transfer-function constants of one propagation, computed on the host in FP64.
+struct AsmParams {
+  double dfx, dfy;        // frequency steps 1 / (Px d), 1 / (Py d)
+  double lim_x, lim_y;    // band limits 1 / (lambda sqrt((2 z dfx)^2 + 1)) (and y)
+  double inv_lam, inv_lam2;
+  double z;
+  double z_rev_frac;      // frac(z / lambda)
+  uint32_t band_limit;
+};
+
+// Padded length of one axis: the next power of two >= 2 n.
+uint32_t asm_padded(uint32_t n);
+
+// nf fields in [nf][h][w] -> out (may alias in); A, B: scratch of
+// nf * h * asm_padded(w) complex64 each. hipErrorInvalidValue if a padded
+// axis exceeds 8192 or a size is zero.
+hipError_t launch_asm(const float2 *in, float2 *out, float2 *A, float2 *B, uint32_t nf, uint32_t w, uint32_t h,
+                      const AsmParams &P, hipStream_t st);
+
+}  // namespace hpt

@@ -1,6 +1,7 @@
-// Host BVH builder: binned SAH over primitive centroids, leaves of at most 4
-// primitives, flattened into BVH2 nodes of 64 bytes that hold both child
-// boxes (one node fetch tests two boxes) and primitive records in leaf order.
+// Host BVH builder: binned SAH over primitive centroids (32 bins, all three
+// axes), leaves of at most 4 primitives, flattened into BVH2 nodes of 64
+// bytes that hold both child boxes (one node fetch tests two boxes) and
+// primitive records in leaf order.
 //
 // Node layout (4 x float4):
 //   a = (c0.lo.x, c0.hi.x, c0.lo.y, c0.hi.y)
@@ -50,7 +51,7 @@ struct Builder {
   std::vector<float> nodes;     // 16 floats per node
   uint32_t max_depth = 0;
 
-  static constexpr int kBins = 16;
+  static constexpr int kBins = 32;
   static constexpr int kLeaf = 4;
 
   int32_t leaf_link(uint32_t first, uint32_t count) {
@@ -72,60 +73,62 @@ struct Builder {
     return b;
   }
 
-  // Choose a split of ids[first, first+count); returns the number in the left part.
+  // Choose a split of ids[first, first+count); returns the number in the
+  // left part. Binned SAH: kBins centroid bins on each axis, the cheapest
+  // boundary over all three axes (cost = area x count on both sides); the
+  // median on the widest axis where SAH finds no split or the tree is deep.
   uint32_t split(uint32_t first, uint32_t count, uint32_t depth) {
     AABB cb; cb.reset();
     for (uint32_t i = 0; i < count; ++i) cb.grow(&cen[3 * ids[first + i]]);
-    int axis = 0;
     float ext[3] = {cb.hi[0] - cb.lo[0], cb.hi[1] - cb.lo[1], cb.hi[2] - cb.lo[2]};
-    if (ext[1] > ext[axis]) axis = 1;
-    if (ext[2] > ext[axis]) axis = 2;
+    int wide = 0;
+    if (ext[1] > ext[wide]) wide = 1;
+    if (ext[2] > ext[wide]) wide = 2;
     auto *beg = ids.data() + first, *end = ids.data() + first + count;
     auto median = [&]() {
       uint32_t mid = count / 2;
       std::nth_element(beg, beg + mid, end, [&](uint32_t a, uint32_t b) {
-        float ca = cen[3 * a + axis], cbv = cen[3 * b + axis];
+        float ca = cen[3 * a + wide], cbv = cen[3 * b + wide];
         return ca < cbv || (ca == cbv && a < b);
       });
       return mid;
     };
-    if (ext[axis] <= 0.f || depth >= 40) return median();
-    AABB bb[kBins];
-    uint32_t bc[kBins] = {0};
-    for (auto &b : bb) b.reset();
-    float scale = kBins / ext[axis];
-    auto bin_of = [&](uint32_t id) {
-      int k = (int)((cen[3 * id + axis] - cb.lo[axis]) * scale);
+    if (ext[wide] <= 0.f || depth >= 40) return median();
+    auto bin_of = [&](uint32_t id, int axis) {
+      int k = (int)((cen[3 * id + axis] - cb.lo[axis]) * (kBins / ext[axis]));
       return std::min(std::max(k, 0), kBins - 1);
     };
-    for (uint32_t i = 0; i < count; ++i) {
-      uint32_t id = ids[first + i];
-      int k = bin_of(id);
-      bb[k].grow(box[id]);
-      bc[k]++;
-    }
-    float left_area[kBins], right_area[kBins];
-    uint32_t left_n[kBins], right_n[kBins];
-    AABB acc; acc.reset();
-    uint32_t n = 0;
-    for (int k = 0; k < kBins; ++k) {
-      acc.grow(bb[k]); n += bc[k];
-      left_area[k] = acc.area(); left_n[k] = n;
-    }
-    acc.reset(); n = 0;
-    for (int k = kBins - 1; k >= 0; --k) {
-      acc.grow(bb[k]); n += bc[k];
-      right_area[k] = acc.area(); right_n[k] = n;
-    }
     float best = INFINITY;
-    int best_k = -1;
-    for (int k = 0; k < kBins - 1; ++k) {
-      if (left_n[k] == 0 || right_n[k + 1] == 0) continue;
-      float c = left_area[k] * left_n[k] + right_area[k + 1] * right_n[k + 1];
-      if (c < best) { best = c; best_k = k; }
+    int best_k = -1, best_axis = -1;
+    for (int axis = 0; axis < 3; ++axis) {
+      if (ext[axis] <= 0.f) continue;
+      AABB bb[kBins];
+      uint32_t bc[kBins] = {0};
+      for (auto &b : bb) b.reset();
+      for (uint32_t i = 0; i < count; ++i) {
+        uint32_t id = ids[first + i];
+        int k = bin_of(id, axis);
+        bb[k].grow(box[id]);
+        bc[k]++;
+      }
+      float right_area[kBins];
+      uint32_t right_n[kBins];
+      AABB acc; acc.reset();
+      uint32_t n = 0;
+      for (int k = kBins - 1; k >= 0; --k) {
+        acc.grow(bb[k]); n += bc[k];
+        right_area[k] = acc.area(); right_n[k] = n;
+      }
+      acc.reset(); n = 0;
+      for (int k = 0; k < kBins - 1; ++k) {
+        acc.grow(bb[k]); n += bc[k];
+        if (n == 0 || right_n[k + 1] == 0) continue;
+        float c = acc.area() * (float)n + right_area[k + 1] * (float)right_n[k + 1];
+        if (c < best) { best = c; best_k = k; best_axis = axis; }
+      }
     }
     if (best_k < 0) return median();
-    auto *m = std::partition(beg, end, [&](uint32_t id) { return bin_of(id) <= best_k; });
+    auto *m = std::partition(beg, end, [&](uint32_t id) { return bin_of(id, best_axis) <= best_k; });
     uint32_t nl = (uint32_t)(m - beg);
     if (nl == 0 || nl == count) return median();
     return nl;

@@ -63,7 +63,9 @@ __device__ __forceinline__ F3 to_f(D3 a) { return {(float)a.x, (float)a.y, (floa
 __device__ __forceinline__ D3 to_d(F3 a) { return {a.x, a.y, a.z}; }
 
 // ------------------------------------------------------------------ traversal
-struct Hit { float t; int32_t gid; };
+// Closest hit so far: distance and leaf-order index of the primitive (-1:
+// none). Equal distances go to the lower global id.
+struct Hit { float t; int32_t prim; };
 
 // Read-only scene data addressed as global memory (address space 1), so the
 // compiler issues global loads (counted by vmcnt only) rather than flat loads.
@@ -185,7 +187,11 @@ __device__ __forceinline__ void leaf_test(const RayPre &r, GF4 P, int32_t node, 
       float4 p2 = ld4(p + 2);
       h = tri_hit(r, f3(p0.x, p0.y, p0.z), f3(p1.x, p1.y, p1.z), f3(p2.x, p2.y, p2.z), tmin, best.t, t);
     }
-    if (h && (t < best.t || gid < best.gid)) { best.t = t; best.gid = gid; }
+    if (h) {
+      // t <= best.t here; on a tie (rare: a shared edge) compare global ids
+      bool take = t < best.t || best.prim < 0 || gid < __float_as_int(ld4(P + 3 * (size_t)best.prim).w);
+      if (take) { best.t = t; best.prim = (int32_t)(first + k); }
+    }
   }
 }
 
@@ -210,17 +216,20 @@ __device__ __forceinline__ void trav_init(Trav &T, F3 o, F3 d, float tmin, int32
   T.node = empty ? kDone : 0;
   T.sp = 0;
   T.best.t = INFINITY;
-  T.best.gid = -1;
+  T.best.prim = -1;
 }
 
 // Traversal stack of one lane: the first kStackLds entries in LDS (lanes
 // interleaved with stride `stride`), deeper ones in global memory (`spill`,
 // one column per thread, entries `sstride` apart). Entries past the LDS
 // part are rare: they need a path with that many pending far children.
+typedef int32_t __attribute__((address_space(3))) *LdsI32;
+typedef int32_t __attribute__((address_space(1))) *GlbI32;
+
 struct Stack {
-  int32_t *lds;
+  LdsI32 lds;
   uint32_t stride;
-  int32_t *spill;
+  GlbI32 spill;
   uint32_t sstride;
 };
 
@@ -233,7 +242,10 @@ __device__ __forceinline__ void push(const Stack &S, int &sp, int32_t v) {
 __device__ __forceinline__ int32_t pop(const Stack &S, int &sp) {
   if (sp == 0) return kDone;
   --sp;
-  return sp < kStackLds ? S.lds[sp * S.stride] : S.spill[(size_t)(sp - kStackLds) * S.sstride];
+  int32_t v;
+  if (sp < kStackLds) v = S.lds[sp * S.stride];
+  else v = S.spill[(size_t)(sp - kStackLds) * S.sstride];
+  return v;
 }
 
 // Advance this lane by one round: descend inner nodes, postponing the first
@@ -299,9 +311,9 @@ __device__ __forceinline__ double tri_t64(double4 pl, D3 o, D3 d) {
   return (pl.w - (pl.x * o.x + pl.y * o.y + pl.z * o.z)) / (pl.x * d.x + pl.y * d.y + pl.z * d.z);
 }
 
-__device__ __forceinline__ double sph_t64(const float *s, D3 o, D3 d, double tmin) {
-  D3 c = {s[0], s[1], s[2]};
-  double rad = s[3];
+__device__ __forceinline__ double sph_t64(double4 s, D3 o, D3 d, double tmin) {
+  D3 c = {s.x, s.y, s.z};
+  double rad = s.w;
   D3 oc = o - c;
   double b = dot(oc, d);
   double cc = dot(oc, oc) - rad * rad;

@@ -46,14 +46,24 @@ struct MaterialDev {
   float pad;
 };
 
+// What shading needs of a hit primitive, one record per primitive in leaf
+// order (the traversal reports the leaf-order index of the closest hit), so
+// that a hit costs one 64-byte read. Triangle: unit normal (v1-v0)x(v2-v0)
+// and offset n.v0 of its plane in FP64. Sphere: centre and radius (the
+// float32 input, exact in FP64).
+struct alignas(64) HitRec {
+  double g[4];
+  int32_t gid;     // global id: spheres [0, n_sph), then triangles
+  uint32_t mat;    // material index
+  uint32_t pad[6];
+};
+static_assert(sizeof(HitRec) == 64, "HitRec is one 64-byte record");
+
 // Device view of one resident scene.
 struct SceneDev {
   const float4 *nodes;       // BVH2: 4 x float4 per node (two child boxes + links)
   const float4 *prims;       // 3 x float4 per primitive in leaf order
-  const float *tri_v;        // [n_tri][9] original float32 vertices
-  const double4 *tri_plane;  // [n_tri] unit normal (v1-v0)x(v2-v0) and offset n.v0, in FP64
-  const float *sph;          // [n_sph][4]
-  const uint32_t *prim_mat;  // [n_sph + n_tri] by global id
+  const HitRec *hits;        // [n_sph + n_tri] in leaf order
   const MaterialDev *mats;
   uint32_t n_sph, n_tri, n_mat, n_nodes;
   float env[3];
@@ -119,8 +129,8 @@ struct BatchDev {
   // two ray queues
   uint32_t *q_slot[2];
   float4 *q_ray[2];          // 2 per entry: (o, tmin), (d, exclude id bits)
-  float *q_t[2];
-  int32_t *q_gid[2];
+  float *q_t[2];             // hit distance
+  int32_t *q_prim[2];        // leaf-order primitive index of the hit, -1: none
   uint32_t *counters;        // [0], [1]: queue lengths; [2]: rays traced; [4], [5]: traversal claims
   unsigned long long *work;  // [0] node visits, [1] primitive tests (counting traversal)
   int32_t *stack_spill;      // [kStackSpill][spill_threads] traversal stack beyond the LDS part

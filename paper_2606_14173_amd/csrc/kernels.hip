@@ -37,18 +37,12 @@ __device__ __forceinline__ uint32_t xcd_block() {
   return (b % 8u) * (g / 8u) + b / 8u;
 }
 
-__device__ __forceinline__ const float *tri_ptr(const SceneDev &S, int32_t gid) {
-  return S.tri_v + 9 * (size_t)(gid - (int32_t)S.n_sph);
-}
-
-__device__ __forceinline__ F3 normal32(const SceneDev &S, int32_t gid, F3 x) {
-  if (gid < (int32_t)S.n_sph) {
-    const float *s = S.sph + 4 * gid;
-    return (1.0f / s[3]) * (x - f3(s[0], s[1], s[2]));
-  }
-  const float *v = tri_ptr(S, gid);
-  return normalize(cross(f3(v[3] - v[0], v[4] - v[1], v[5] - v[2]),
-                         f3(v[6] - v[0], v[7] - v[1], v[8] - v[2])));
+// FP32 geometric normal at x of the primitive of record H (unnormalised
+// input never reaches here: planes are stored unit length).
+__device__ __forceinline__ F3 hit_normal32(const SceneDev &S, const HitRec &H, F3 x) {
+  if (H.gid < (int32_t)S.n_sph)
+    return (1.0f / (float)H.g[3]) * (x - f3((float)H.g[0], (float)H.g[1], (float)H.g[2]));
+  return f3((float)H.g[0], (float)H.g[1], (float)H.g[2]);
 }
 
 // Pixel order of a crop: 8x8 tiles, tiles row-major, pixels row-major inside
@@ -109,8 +103,8 @@ __device__ __forceinline__ void push_ray(const BatchDev &B, int q, uint32_t pos,
 }
 
 // ------------------------------------------------------------------ raygen
-// One thread per slot. A block of kRaygenBlock consecutive slots (one 8x8
-// pixel tile x 16 samples for a 16-sample unit) counting-sorts its rays by
+// One thread per slot. A block of kRaygenBlock consecutive slots (a few
+// neighbouring pixels x their samples; slots are pixel-major) counting-sorts its rays by
 // direction (8x8 Morton bins over the cone, or over the octahedral square
 // for cache paths) before writing the first queue, so that each wave traces
 // rays of similar origin and direction. The queue order changes nothing but
@@ -258,8 +252,8 @@ __global__ void __launch_bounds__(kBlock) k_trace(BatchDev B, int q) {
   }
   uint32_t *claim = B.counters + 4 + q;
   const uint32_t lane = __lane_id();
-  const Stack St{stack + threadIdx.x, kBlock, B.stack_spill + xcd_block() * blockDim.x + threadIdx.x,
-                 B.spill_threads};
+  const Stack St{(LdsI32)(stack + threadIdx.x), kBlock,
+                 (GlbI32)(B.stack_spill + xcd_block() * blockDim.x + threadIdx.x), B.spill_threads};
   uint32_t nv = 0, nt = 0;
   uint32_t next = 0, end = 0;  // unassigned entries of the wave's chunk
   bool more = true;            // the queue may hold unclaimed entries
@@ -306,7 +300,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(BatchDev B, int q) {
       if (T.node != kDone) trav_step<COUNT>(T, N, P, St, nv, nt);
       if (T.node == kDone) {
         B.q_t[q][i] = T.best.t;
-        B.q_gid[q][i] = T.best.gid;
+        B.q_prim[q][i] = T.best.prim;
         i = -1;
       }
     }
@@ -446,11 +440,12 @@ __device__ __forceinline__ void image_point(const BatchDev &B, const UnitDev &U,
 // on primitive gid. Returns a ray to trace in `e`, or finishes the path.
 __device__ __forceinline__ void tail_interaction(const BatchDev &B, const UnitDev &U, const JobDev &J,
                                                  const SceneDev &S, uint32_t slot, F3 x, F3 d_in,
-                                                 int32_t gid, uint32_t b, uint32_t bP, uint32_t comp,
+                                                 const HitRec &H, uint32_t b, uint32_t bP, uint32_t comp,
                                                  uint32_t stream, float beta, float L,
                                                  unsigned long long sig, Emit &e) {
-  const MaterialDev m = S.mats[S.prim_mat[gid]];
-  F3 ng = normal32(S, gid, x);
+  const int32_t gid = H.gid;
+  const MaterialDev m = S.mats[H.mat];
+  F3 ng = hit_normal32(S, H, x);
   bool holo = U.kind == UNIT_HOLO;
   if (m.type == HPT_EMITTER) {
     sig_add(sig, EV_EMIT);
@@ -502,11 +497,14 @@ __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, 
   uint32_t meta = B.s_meta[slot];
   uint32_t stage = meta & 1u, b = (meta >> 1) & 63u, bP = (meta >> 7) & 63u;
   float t = B.q_t[q][i];
-  int32_t gid = B.q_gid[q][i];
+  int32_t hp = B.q_prim[q][i];
   unsigned long long sig = B.s_sig[slot];
   bool holo = U.kind == UNIT_HOLO;
   uint32_t comp = holo ? J.comp[U.ch] : U.ch;
   uint32_t stream = (comp << 16) | (holo ? 0u : 2u);
+  HitRec H;
+  if (hp >= 0) H = S.hits[hp];
+  const int32_t gid = hp >= 0 ? H.gid : -1;
   if (stage == STAGE_PREFIX) {
     if (gid < 0) {
       sig_add(sig, 0xFFFFFFFFu);
@@ -522,15 +520,15 @@ __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, 
     double ell = B.s_ell[slot];
     float ncur = B.s_W[slot];
     bool tri = gid >= (int32_t)S.n_sph;
-    const MaterialDev m = S.mats[S.prim_mat[gid]];
+    const MaterialDev m = S.mats[H.mat];
     bool delta = m.type == HPT_MIRROR || m.type == HPT_DIELECTRIC;
     double t64;
-    double4 pl = tri ? S.tri_plane[gid - (int32_t)S.n_sph] : make_double4(0, 0, 0, 0);
+    const double4 pl = make_double4(H.g[0], H.g[1], H.g[2], H.g[3]);  // plane, or centre and radius
     if (J.phase_mode == HPT_PHASE_FP32) {
       t64 = (double)t;
       ell = (double)((float)ell + ncur * t);
     } else {
-      t64 = tri ? tri_t64(pl, o, d) : sph_t64(S.sph + 4 * gid, o, d, kTminD);
+      t64 = tri ? tri_t64(pl, o, d) : sph_t64(pl, o, d, kTminD);
       ell += (double)ncur * t64;
     }
     D3 x = o + t64 * d;
@@ -540,10 +538,7 @@ __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, 
                     (uint32_t)(J.seed >> 32));
       D3 ng;
       if (tri) ng = D3{pl.x, pl.y, pl.z};
-      else {
-        const float *s = S.sph + 4 * gid;
-        ng = (1.0 / (double)s[3]) * (x - D3{s[0], s[1], s[2]});
-      }
+      else ng = (1.0 / pl.w) * (x - D3{pl.x, pl.y, pl.z});
       double dn = dot(d, ng);
       D3 nf = dn < 0 ? ng : (-1.0) * ng;
       double wgt = 1.0;
@@ -579,7 +574,7 @@ __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, 
     // first non-delta hit: the real image point P
     sig_add(sig, EV_IMAGE_POINT);
     image_point(B, U, J, slot, ell, b);
-    tail_interaction(B, U, J, S, slot, to_f(x), to_f(d), gid, b, b, comp, stream, 1.0f, 0.0f, sig, e);
+    tail_interaction(B, U, J, S, slot, to_f(x), to_f(d), H, b, b, comp, stream, 1.0f, 0.0f, sig, e);
     return;
   }
   // incoherent tail (or cache path)
@@ -595,15 +590,22 @@ __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, 
   sig_add(sig, (uint32_t)gid + 1u);
   F3 d_in = f3(r1.x, r1.y, r1.z);
   F3 x = f3(r0.x, r0.y, r0.z) + t * d_in;
-  tail_interaction(B, U, J, S, slot, x, d_in, gid, b, bP, comp, stream, beta, L, sig, e);
+  tail_interaction(B, U, J, S, slot, x, d_in, H, b, bP, comp, stream, beta, L, sig, e);
 }
 
 __global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
   uint32_t n = B.counters[q];
   int qo = q ^ 1;
   if (blockIdx.x == 0 && threadIdx.x == 0) B.counters[4 + q] = 0;  // traversal claims of queue q
-  uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
+  // Neighbouring queue entries touch the same slot windows: the blocks that
+  // have entries (the first ceil(n / blockDim) of the grid, which the
+  // hardware deals to the 8 XCDs in turn) are remapped so that each XCD
+  // takes one contiguous eighth of the queue.
+  const uint32_t nb8 = ((n + blockDim.x - 1) / blockDim.x + 7u) & ~7u;
+  const uint32_t b = blockIdx.x;
+  const uint32_t blk = b < nb8 ? (b % 8u) * (nb8 / 8u) + b / 8u : b;
+  const uint32_t stride = max(gridDim.x, nb8) * blockDim.x;
+  for (uint32_t base = blk * blockDim.x; base < n; base += stride) {
     uint32_t i = base + threadIdx.x;
     Emit e;
     e.on = false;
@@ -828,7 +830,7 @@ hipError_t launch_trace(const BatchDev &B, int q, bool count, hipStream_t st) {
 }
 
 hipError_t launch_shade(const BatchDev &B, int q, hipStream_t st) {
-  hipLaunchKernelGGL(k_shade, dim3(grid_for(B.n_paths)), dim3(kBlock), 0, st, B, q);
+  hipLaunchKernelGGL(k_shade, dim3(round8(grid_for(B.n_paths))), dim3(kBlock), 0, st, B, q);
   return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "../../include/hpt.h"
+#include "asm.hpp"
 #include "bvh_build.hpp"
 #include "hpt_types.hpp"
 #include "kernels.hpp"
@@ -232,10 +233,18 @@ hpt_status build_grf(hpt_ctx *C, uint32_t gw, uint32_t gh, uint32_t T, uint64_t 
 }
 
 // ---------------------------------------------------------------- jobs
-void split_units(Job *J) {
+// Units of about min(2^20, batch capacity) paths: up to 256 samples of a
+// block of pixels. Deep sample chunks keep a batch's pixels (consecutive
+// blocks in the 8x8-tile order) in a band of rows, so that the image points
+// its paths look up in the random-field table stay within a band of the table
+// (the cone footprint around those rows) that the L2 and the memory-side
+// cache can hold. A unit never exceeds the capacity (>= 2^16 >= 64 x 256), so
+// every unit fits a batch.
+void split_units(Job *J, uint32_t capacity) {
   uint32_t P = J->host.crop_w * J->host.crop_h, S = J->host.n_s;
-  uint32_t Pu = std::min<uint32_t>(P, 1u << 16);
-  uint32_t Su = std::max<uint32_t>(1u, std::min<uint32_t>(S, (1u << 20) / Pu));
+  uint32_t Su = std::min<uint32_t>(S, 256u);
+  uint32_t target = std::min<uint32_t>(1u << 20, capacity);
+  uint32_t Pu = std::min<uint32_t>(P, std::max<uint32_t>(64u, target / Su));
   uint32_t nblk = (P + Pu - 1) / Pu;
   for (uint32_t s0 = 0; s0 < S; s0 += Su)
     for (uint32_t c = 0; c < J->host.n_ch; ++c)
@@ -249,11 +258,11 @@ void split_units(Job *J) {
       }
 }
 
-void split_cache_units(Job *J) {
+void split_cache_units(Job *J, uint32_t capacity) {
   uint32_t E = J->host.cache_res * J->host.cache_res * J->host.cache_res * J->host.cache_bins *
                J->host.cache_bins;
   uint32_t spb = J->host.cache_spb;
-  uint32_t Eu = std::max<uint32_t>(1u, std::min<uint32_t>(E, (1u << 20) / spb));
+  uint32_t Eu = std::max<uint32_t>(1u, std::min<uint32_t>(E, std::min<uint32_t>(1u << 20, capacity) / spb));
   uint32_t nblk = (E + Eu - 1) / Eu;
   for (uint32_t c = 0; c < 3; ++c)
     for (uint32_t r = 0; r < nblk; ++r) {
@@ -557,7 +566,7 @@ hpt_status alloc_batch(hpt_ctx *C) {
         A((void **)&B.r_fy, 4ull * N) && A((void **)&B.r_r64, 8ull * N) && A((void **)&B.r_tex, 4ull * N);
   for (int q = 0; q < 2 && ok; ++q)
     ok &= A((void **)&B.q_slot[q], 4ull * N) && A((void **)&B.q_ray[q], 32ull * N) &&
-          A((void **)&B.q_t[q], 4ull * N) && A((void **)&B.q_gid[q], 4ull * N);
+          A((void **)&B.q_t[q], 4ull * N) && A((void **)&B.q_prim[q], 4ull * N);
   ok &= A((void **)&B.counters, 64);
   ok &= A((void **)&B.work, 64);
   B.spill_threads = trace_grid(N) * trace_block();
@@ -727,26 +736,35 @@ hpt_status hpt_scene_upload(hpt_ctx *C, const hpt_scene_desc *d, uint64_t *out) 
     for (int c = 0; c < 3; ++c) { m.rgb[c] = d->mat_rgb[3 * i + c]; m.emit[c] = d->mat_emit[3 * i + c]; }
     m.rough = d->mat_rough[i]; m.ior = d->mat_ior[i]; m.pad = 0.f;
   }
-  // FP64 plane of every triangle for the coherent-prefix refinement
-  std::vector<double> planes(4 * std::max<size_t>(d->n_tri, 1), 0.0);
-  for (uint32_t i = 0; i < d->n_tri; ++i) {
-    const float *v = d->tri + 9 * (size_t)i;
-    double e1[3] = {(double)v[3] - v[0], (double)v[4] - v[1], (double)v[5] - v[2]};
-    double e2[3] = {(double)v[6] - v[0], (double)v[7] - v[1], (double)v[8] - v[2]};
-    double nx = e1[1] * e2[2] - e1[2] * e2[1], ny = e1[2] * e2[0] - e1[0] * e2[2],
-           nz = e1[0] * e2[1] - e1[1] * e2[0];
-    double len = std::sqrt(nx * nx + ny * ny + nz * nz);
-    if (len > 0) { nx /= len; ny /= len; nz /= len; }
-    planes[4 * i] = nx; planes[4 * i + 1] = ny; planes[4 * i + 2] = nz;
-    planes[4 * i + 3] = nx * v[0] + ny * v[1] + nz * v[2];
+  // one shading record per primitive in leaf order: FP64 plane of a triangle
+  // (the coherent-prefix refinement and the hit normal) or the sphere itself
+  std::vector<HitRec> hits(n);
+  for (uint32_t i = 0; i < n; ++i) {
+    uint32_t g;
+    std::memcpy(&g, &bvh.prims[12 * (size_t)i + 3], 4);
+    HitRec &r = hits[i];
+    std::memset(&r, 0, sizeof(r));
+    r.gid = (int32_t)g;
+    if (g < d->n_sph) {
+      for (int a = 0; a < 4; ++a) r.g[a] = d->sph[4 * (size_t)g + a];
+      r.mat = d->sph_mat[g];
+    } else {
+      const float *v = d->tri + 9 * (size_t)(g - d->n_sph);
+      double e1[3] = {(double)v[3] - v[0], (double)v[4] - v[1], (double)v[5] - v[2]};
+      double e2[3] = {(double)v[6] - v[0], (double)v[7] - v[1], (double)v[8] - v[2]};
+      double nx = e1[1] * e2[2] - e1[2] * e2[1], ny = e1[2] * e2[0] - e1[0] * e2[2],
+             nz = e1[0] * e2[1] - e1[1] * e2[0];
+      double len = std::sqrt(nx * nx + ny * ny + nz * nz);
+      if (len > 0) { nx /= len; ny /= len; nz /= len; }
+      r.g[0] = nx; r.g[1] = ny; r.g[2] = nz;
+      r.g[3] = nx * v[0] + ny * v[1] + nz * v[2];
+      r.mat = d->tri_mat[g - d->n_sph];
+    }
   }
-  std::vector<uint32_t> prim_mat(std::max<uint32_t>(n, 1));
-  for (uint32_t i = 0; i < d->n_sph; ++i) prim_mat[i] = d->sph_mat[i];
-  for (uint32_t i = 0; i < d->n_tri; ++i) prim_mat[d->n_sph + i] = d->tri_mat[i];
   std::lock_guard<std::mutex> g(C->mu);
   (void)hipSetDevice(C->device);
-  size_t need = bvh.nodes.size() * 4 + bvh.prims.size() * 4 + 68ull * d->n_tri + 16ull * d->n_sph +
-                4ull * prim_mat.size() + sizeof(MaterialDev) * mats.size() + sizeof(SceneDev);
+  size_t need = bvh.nodes.size() * 4 + bvh.prims.size() * 4 + sizeof(HitRec) * hits.size() +
+                sizeof(MaterialDev) * mats.size() + sizeof(SceneDev);
   if (C->used + need > C->budget) evict_grfs(C, need);
   if (C->used + need > C->budget) return fail(HPT_EBUDGET, "scene does not fit the budget");
   auto put = [&](const void *src, size_t bytes, void **dst) {
@@ -762,11 +780,8 @@ hpt_status hpt_scene_upload(hpt_ctx *C, const hpt_scene_desc *d, uint64_t *out) 
   if (n > 0) {
     ok &= put(bvh.nodes.data(), bvh.nodes.size() * 4, &p); h.nodes = (const float4 *)p;
     ok &= put(bvh.prims.data(), bvh.prims.size() * 4, &p); h.prims = (const float4 *)p;
+    ok &= put(hits.data(), sizeof(HitRec) * hits.size(), &p); h.hits = (const HitRec *)p;
   }
-  ok &= put(d->tri, 36ull * d->n_tri, &p); h.tri_v = (const float *)p;
-  ok &= put(planes.data(), 32ull * d->n_tri, &p); h.tri_plane = (const double4 *)p;
-  ok &= put(d->sph, 16ull * d->n_sph, &p); h.sph = (const float *)p;
-  ok &= put(prim_mat.data(), 4ull * prim_mat.size(), &p); h.prim_mat = (const uint32_t *)p;
   ok &= put(mats.data(), sizeof(MaterialDev) * mats.size(), &p); h.mats = (const MaterialDev *)p;
   h.n_sph = d->n_sph; h.n_tri = d->n_tri; h.n_mat = d->n_mat; h.n_nodes = n ? bvh.n_nodes : 0;
   for (int c = 0; c < 3; ++c) h.env[c] = d->env[c];
@@ -866,7 +881,7 @@ hpt_status hpt_cache_build(hpt_ctx *C, uint64_t scene, const hpt_cache_desc *cd)
     jd.cache_res = cd->res; jd.cache_bins = cd->bins; jd.cache_spb = cd->spb;
     jd.spp = 1;
     jd.T = 1;
-    split_cache_units(J.get());
+    split_cache_units(J.get(), C->capacity);
     J->bytes = sizeof(JobDev);
     J->t_submit = Clock::now();
     S->users++;
@@ -979,7 +994,7 @@ hpt_status hpt_trace_submit(hpt_ctx *C, uint64_t scene, const hpt_job_desc *d, v
   uint64_t fixed = C->batch_bytes;
   for (auto &kv : C->scenes) fixed += kv.second->bytes + kv.second->cache_bytes;
   if (fixed + J->bytes + J->grf_bytes > C->budget) return fail(HPT_EBUDGET, "job can never fit the budget");
-  split_units(J.get());
+  split_units(J.get(), C->capacity);
   J->id = C->next_id++;
   J->t_submit = Clock::now();
   S->users++;
@@ -1110,6 +1125,63 @@ hpt_status hpt_grf_read(hpt_ctx *C, uint32_t gw, uint32_t gh, uint32_t T, uint64
   hpt_status s = build_grf(C, gw, gh, T, seed, C->aux, &G);
   if (s != HPT_OK) return s;
   if (hipMemcpy(host, G->d, G->bytes, hipMemcpyDeviceToHost) != hipSuccess) return fail(HPT_EDEVICE, "copy failed");
+  return HPT_OK;
+}
+
+hpt_status hpt_asm_propagate(hpt_ctx *C, const void *d_in, void *d_out, uint32_t n_fields, uint32_t width,
+                             uint32_t height, double pitch, double lambda, double distance, uint32_t flags) {
+  if (!C || !d_in || !d_out) return fail(HPT_EINVAL, "null argument");
+  if (n_fields < 1 || width < 1 || height < 1 || width > 4096 || height > 4096)
+    return fail(HPT_EINVAL, "field size out of range (1..4096 per axis, at least one field)");
+  if (!(pitch > 0) || !std::isfinite(pitch) || !(lambda > 0) || !std::isfinite(lambda) || !std::isfinite(distance))
+    return fail(HPT_EINVAL, "bad pitch, wavelength or distance");
+  if (flags & ~HPT_ASM_BAND_LIMIT) return fail(HPT_EINVAL, "unknown flags");
+  const uint32_t px = asm_padded(width), py = asm_padded(height);
+  AsmParams P;
+  P.dfx = 1.0 / (px * pitch);
+  P.dfy = 1.0 / (py * pitch);
+  P.lim_x = 1.0 / (lambda * std::sqrt(std::pow(2.0 * distance * P.dfx, 2) + 1.0));
+  P.lim_y = 1.0 / (lambda * std::sqrt(std::pow(2.0 * distance * P.dfy, 2) + 1.0));
+  P.inv_lam = 1.0 / lambda;
+  P.inv_lam2 = P.inv_lam * P.inv_lam;
+  P.z = distance;
+  const double zr = distance / lambda;
+  P.z_rev_frac = zr - std::floor(zr);
+  P.band_limit = (flags & HPT_ASM_BAND_LIMIT) ? 1u : 0u;
+  // scratch for a chunk of fields: two [h][Px] complex64 buffers per field
+  const uint64_t per = 2ull * height * px * sizeof(float2);
+  float2 *A = nullptr, *B = nullptr;
+  uint32_t chunk = 0;
+  {
+    std::lock_guard<std::mutex> g(C->mu);
+    (void)hipSetDevice(C->device);
+    uint64_t free_b = C->budget > C->used ? C->budget - C->used : 0;
+    if (free_b < per) evict_grfs(C, per);
+    free_b = C->budget > C->used ? C->budget - C->used : 0;
+    chunk = (uint32_t)std::min<uint64_t>({(uint64_t)n_fields, free_b / per, std::max<uint64_t>(1, (1ull << 30) / per)});
+    if (chunk == 0) return fail(HPT_EBUDGET, "propagation scratch does not fit the budget");
+    const size_t half = (size_t)chunk * height * px * sizeof(float2);
+    if (C->alloc((void **)&A, half) != hipSuccess) return fail(HPT_ENOMEM, "scratch allocation failed");
+    if (C->alloc((void **)&B, half) != hipSuccess) {
+      C->release(A, half);
+      return fail(HPT_ENOMEM, "scratch allocation failed");
+    }
+  }
+  hipError_t e = hipSuccess;
+  const size_t field = (size_t)width * height;
+  for (uint32_t f0 = 0; f0 < n_fields && e == hipSuccess; f0 += chunk) {
+    uint32_t nf = std::min(chunk, n_fields - f0);
+    e = launch_asm((const float2 *)d_in + f0 * field, (float2 *)d_out + f0 * field, A, B, nf, width, height, P,
+                   C->aux);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(C->aux);
+  {
+    std::lock_guard<std::mutex> g(C->mu);
+    const size_t half = (size_t)chunk * height * px * sizeof(float2);
+    C->release(A, half);
+    C->release(B, half);
+  }
+  if (e != hipSuccess) return fail(HPT_EDEVICE, std::string("propagation failed: ") + hipGetErrorString(e));
   return HPT_OK;
 }
 
