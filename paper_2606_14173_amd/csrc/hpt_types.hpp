@@ -113,24 +113,34 @@ struct UnitDev {
 };
 
 // Path state, records and queues of one batch (structure of arrays).
+// One ray queue: entry k is a live ray with the state its path carries from
+// bounce to bounce (structure of arrays, so each field is read and written
+// coalesced). The FP64 fields are read and written only while the ray is in
+// the coherent prefix.
+struct RayQueue {
+  uint32_t *slot, *unit;
+  uint32_t *meta;                  // stage | b << 1 | bP << 7
+  uint32_t *ka, *kb;               // Philox key words of the path
+  unsigned long long *sig;         // path signature so far
+  float *bpre;                     // beta_pre: product of the delta weights
+  float *wt;                       // medium index in the prefix, then the weight W
+  float *beta, *L;                 // tail throughput and radiance
+  double *ox, *oy, *oz, *dx, *dy, *dz, *ell, *al, *be;
+  float4 *ray;                     // 2 per entry: (o, tmin), (d, exclude id bits), traversal input
+  float *t;                        // hit distance
+  int32_t *prim;                   // leaf-order primitive index of the hit, -1: none
+};
+
 struct BatchDev {
   const UnitDev *units;
   uint32_t n_units, n_paths, n_acc, lds_unused;
-  uint32_t *s_meta;          // stage | b << 1 | bP << 7 | glass << 13
-  uint32_t *s_unit, *s_ka, *s_kb;
-  double *s_ox, *s_oy, *s_oz, *s_dx, *s_dy, *s_dz, *s_ell, *s_al, *s_be;
-  float *s_bpre, *s_beta, *s_L, *s_W;
-  unsigned long long *s_sig;
-  int32_t *s_first;
-  // per-path results consumed by the accumulation
-  float *r_amp, *r_rev, *r_fx, *r_fy;
+  // per path slot
+  unsigned long long *s_sig;  // final signature (debug records and signature sums only)
+  int32_t *s_first;           // first hit (debug records only)
+  float *r_amp, *r_rev, *r_fx, *r_fy;   // results consumed by the accumulation
   double *r_r64;
   uint32_t *r_tex;
-  // two ray queues
-  uint32_t *q_slot[2];
-  float4 *q_ray[2];          // 2 per entry: (o, tmin), (d, exclude id bits)
-  float *q_t[2];             // hit distance
-  int32_t *q_prim[2];        // leaf-order primitive index of the hit, -1: none
+  RayQueue Q[2];
   uint32_t *counters;        // [0], [1]: queue lengths; [2]: rays traced; [4], [5]: traversal claims
   unsigned long long *work;  // [0] node visits, [1] primitive tests (counting traversal)
   int32_t *stack_spill;      // [kStackSpill][spill_threads] traversal stack beyond the LDS part

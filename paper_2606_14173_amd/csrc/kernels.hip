@@ -95,11 +95,51 @@ __device__ __forceinline__ uint32_t morton8(float u, float v) {
   return k;
 }
 
-__device__ __forceinline__ void push_ray(const BatchDev &B, int q, uint32_t pos, uint32_t slot, F3 o,
-                                         F3 d, int32_t excl) {
-  B.q_slot[q][pos] = slot;
-  B.q_ray[q][2 * pos] = make_float4(o.x, o.y, o.z, kTmin);
-  B.q_ray[q][2 * pos + 1] = make_float4(d.x, d.y, d.z, __int_as_float(excl));
+// State of one live ray that shading changes, loaded from entry i of queue
+// q; the read-only words (Philox keys, direction cosines) stay in the source
+// entry, are read where they are used, and are copied to the ray's next
+// entry when the path continues.
+struct RayState {
+  uint32_t i;                // entry in the source queue
+  uint32_t slot, unit, meta;
+  unsigned long long sig;
+  float bpre, wt, beta, L;   // wt: medium index while in the prefix, then the weight W
+  D3 o, d;                   // FP64 ray of the coherent prefix
+  double ell;
+};
+
+__device__ __forceinline__ void load_state(const RayQueue &Q, uint32_t i, RayState &r) {
+  r.i = i;
+  r.slot = Q.slot[i]; r.unit = Q.unit[i]; r.meta = Q.meta[i];
+  r.sig = Q.sig[i];
+  r.bpre = Q.bpre[i]; r.wt = Q.wt[i]; r.beta = Q.beta[i]; r.L = Q.L[i];
+  if ((r.meta & 1u) == STAGE_PREFIX) {
+    r.o = D3{Q.ox[i], Q.oy[i], Q.oz[i]};
+    r.d = D3{Q.dx[i], Q.dy[i], Q.dz[i]};
+    r.ell = Q.ell[i];
+  }
+}
+
+// Entry k of queue Q for the continuing ray r (read-only words from entry
+// r.i of the source queue S, or from ka, kb, al, be when S is null).
+__device__ __forceinline__ void store_state(const RayQueue &Q, uint32_t k, const RayState &r, const RayQueue *S,
+                                            uint32_t ka, uint32_t kb, double al, double be, F3 o, F3 d,
+                                            int32_t excl) {
+  const bool prefix = (r.meta & 1u) == STAGE_PREFIX;
+  if (S) {
+    ka = S->ka[r.i]; kb = S->kb[r.i];
+    if (prefix) { al = S->al[r.i]; be = S->be[r.i]; }
+  }
+  Q.slot[k] = r.slot; Q.unit[k] = r.unit; Q.meta[k] = r.meta; Q.ka[k] = ka; Q.kb[k] = kb;
+  Q.sig[k] = r.sig;
+  Q.bpre[k] = r.bpre; Q.wt[k] = r.wt; Q.beta[k] = r.beta; Q.L[k] = r.L;
+  if (prefix) {
+    Q.ox[k] = r.o.x; Q.oy[k] = r.o.y; Q.oz[k] = r.o.z;
+    Q.dx[k] = r.d.x; Q.dy[k] = r.d.y; Q.dz[k] = r.d.z;
+    Q.ell[k] = r.ell; Q.al[k] = al; Q.be[k] = be;
+  }
+  Q.ray[2 * k] = make_float4(o.x, o.y, o.z, kTmin);
+  Q.ray[2 * k + 1] = make_float4(d.x, d.y, d.z, __int_as_float(excl));
 }
 
 // ------------------------------------------------------------------ raygen
@@ -111,117 +151,130 @@ __device__ __forceinline__ void push_ray(const BatchDev &B, int q, uint32_t pos,
 // the traversal's coherence: every path keeps its slot.
 constexpr int kRaygenBlock = 1024;
 
+// s1-s2 for path slot i (or a cache path): its state, read-only key words,
+// FP32 ray and direction-sort key.
+__device__ __forceinline__ void gen_path(const BatchDev &B, uint32_t i, RayState &st, uint32_t &ska,
+                                         uint32_t &skb, double &sal, double &sbe, F3 &ro, F3 &rd,
+                                         uint32_t &key) {
+  uint32_t u = find_unit(B.units, B.n_units, i, false);
+  const UnitDev U = B.units[u];
+  const JobDev &J = *U.job;
+  uint32_t p_local, s_local;
+  slot_decode(U, i, p_local, s_local);
+  st.i = i;
+  st.slot = i;
+  st.unit = u;
+  st.sig = kSigInit;
+  st.bpre = 1.f;
+  st.wt = 1.0f;  // refractive index of the current medium while in the prefix
+  st.beta = 1.f;
+  st.L = 0.f;
+  if (U.kind == UNIT_HOLO) {
+    uint32_t comp = J.comp[U.ch];
+    uint32_t cx, cy;
+    crop_xy(J, U.p_lo + p_local, cx, cy);
+    uint32_t px = J.crop_x0 + cx, py = J.crop_y0 + cy;
+    uint32_t gpix = py * J.width + px, smp = U.s_lo + s_local;
+    ska = gpix;
+    skb = smp;
+    U4 w = philox(gpix, smp, 0u, comp << 16, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
+    D3 xp = {((double)px + 0.5 - 0.5 * (double)J.width) * J.pitch,
+             ((double)py + 0.5 - 0.5 * (double)J.height) * J.pitch, 0.0};
+    D3 O, d;
+    double al, be;
+    if (J.phase_mode != HPT_PHASE_FP32) {
+      // s1: direction cosines uniform on the disc of radius lambda/(2d)
+      double rad = J.s_cone[U.ch] * sqrt(ud(w.x));
+      double sn, cs;
+      sincospi(2.0 * ud(w.y), &sn, &cs);
+      al = rad * cs; be = rad * sn;
+      D3 v = {al, be, sqrt(1.0 - al * al - be * be)};
+      if (J.identity_T) {
+        O = xp;
+        d = normalize(v);
+      } else {  // s2: into world space through the inverse of T (Eq. 3)
+        const double *M = J.Ti;
+        O = {M[0] * xp.x + M[1] * xp.y + M[2] * xp.z + M[3], M[4] * xp.x + M[5] * xp.y + M[6] * xp.z + M[7],
+             M[8] * xp.x + M[9] * xp.y + M[10] * xp.z + M[11]};
+        d = normalize(D3{M[0] * v.x + M[1] * v.y + M[2] * v.z, M[4] * v.x + M[5] * v.y + M[6] * v.z,
+                         M[8] * v.x + M[9] * v.y + M[10] * v.z});
+      }
+    } else {
+      float rad = J.s_cone_f[U.ch] * sqrtf(uf(w.x));
+      float sn, cs;
+      sincospif(2.0f * uf(w.y), &sn, &cs);
+      float alf = rad * cs, bef = rad * sn;
+      F3 v = f3(alf, bef, sqrtf(1.0f - alf * alf - bef * bef));
+      al = alf; be = bef;
+      F3 O32, d32;
+      if (J.identity_T) {
+        O32 = to_f(xp);
+        d32 = normalize(v);
+      } else {
+        float M[12];
+        for (int k = 0; k < 12; ++k) M[k] = (float)J.Ti[k];
+        F3 x = to_f(xp);
+        O32 = f3(M[0] * x.x + M[1] * x.y + M[2] * x.z + M[3], M[4] * x.x + M[5] * x.y + M[6] * x.z + M[7],
+                 M[8] * x.x + M[9] * x.y + M[10] * x.z + M[11]);
+        d32 = normalize(f3(M[0] * v.x + M[1] * v.y + M[2] * v.z, M[4] * v.x + M[5] * v.y + M[6] * v.z,
+                           M[8] * v.x + M[9] * v.y + M[10] * v.z));
+      }
+      O = to_d(O32); d = to_d(d32);
+    }
+    sal = al; sbe = be;
+    st.o = O; st.d = d;
+    st.ell = 0.0;
+    st.meta = STAGE_PREFIX;
+    ro = to_f(O); rd = to_f(d);
+    key = morton8((float)(al / J.s_cone[U.ch]), (float)(be / J.s_cone[U.ch]));
+  } else {
+    // radiance-cache path: a point uniform in the cell, a direction uniform
+    // in the bin's octahedral square
+    const SceneDev &S = *J.scene;
+    uint32_t comp = U.ch;
+    uint32_t e = U.p_lo + p_local, j = U.s_lo + s_local;
+    uint32_t nb = J.cache_bins * J.cache_bins;
+    uint32_t cell = e / nb, bin = e - cell * nb;
+    uint32_t res = J.cache_res;
+    uint32_t ix = cell % res, iy = (cell / res) % res, iz = cell / (res * res);
+    uint32_t bu = bin % J.cache_bins, bv = bin / J.cache_bins;
+    uint32_t ka = cell, kb = (bin << 16) | j;
+    uint32_t sw = (comp << 16) | 2u;
+    U4 w0 = philox(ka, kb, 0u, sw, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
+    U4 w1 = philox(ka, kb, 1u, sw, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
+    D3 lo = {S.cache_lo_d[0], S.cache_lo_d[1], S.cache_lo_d[2]};
+    D3 ext = {S.cache_hi_d[0] - lo.x, S.cache_hi_d[1] - lo.y, S.cache_hi_d[2] - lo.z};
+    D3 x = {lo.x + (ix + ud(w0.x)) / res * ext.x, lo.y + (iy + ud(w0.y)) / res * ext.y,
+            lo.z + (iz + ud(w0.z)) / res * ext.z};
+    double pu = -1.0 + 2.0 * (bu + ud(w0.w)) / J.cache_bins;
+    double pv = -1.0 + 2.0 * (bv + ud(w1.x)) / J.cache_bins;
+    D3 d = oct_decode64(pu, pv);
+    ska = ka;
+    skb = kb;
+    st.meta = STAGE_TAIL;  // b = 0, bP = 0
+    ro = to_f(x); rd = to_f(d);
+    key = morton8((float)pu, (float)pv);
+  }
+}
+
 __global__ void __launch_bounds__(kRaygenBlock) k_raygen(BatchDev B) {
   __shared__ uint32_t hist[64], base[64];
+  __shared__ uint16_t perm[kRaygenBlock];
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t g0 = blockIdx.x * blockDim.x;
   if (i == 0) { B.counters[0] = B.n_paths; B.counters[1] = 0; }
   if (threadIdx.x < 64) hist[threadIdx.x] = 0;
   __syncthreads();
   const bool valid = i < B.n_paths;
-  F3 ro = f3(0.f, 0.f, 0.f), rd = f3(0.f, 0.f, 1.f);
   uint32_t key = 0;
+  RayState st;
+  uint32_t ska = 0, skb = 0;
+  double sal = 0.0, sbe = 0.0;
+  F3 ro = f3(0.f, 0.f, 0.f), rd = f3(0.f, 0.f, 1.f);
   if (valid) {
-    uint32_t u = find_unit(B.units, B.n_units, i, false);
-    const UnitDev U = B.units[u];
-    const JobDev &J = *U.job;
-    uint32_t p_local, s_local;
-    slot_decode(U, i, p_local, s_local);
-    B.s_unit[i] = u;
-    B.s_L[i] = 0.f;
-    B.s_beta[i] = 1.f;
-    B.s_bpre[i] = 1.f;
     B.s_first[i] = -1;
-    B.s_sig[i] = kSigInit;
     B.r_amp[i] = 0.f;
-    if (U.kind == UNIT_HOLO) {
-      uint32_t comp = J.comp[U.ch];
-      uint32_t cx, cy;
-      crop_xy(J, U.p_lo + p_local, cx, cy);
-      uint32_t px = J.crop_x0 + cx, py = J.crop_y0 + cy;
-      uint32_t gpix = py * J.width + px, smp = U.s_lo + s_local;
-      B.s_ka[i] = gpix;
-      B.s_kb[i] = smp;
-      U4 w = philox(gpix, smp, 0u, comp << 16, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
-      D3 xp = {((double)px + 0.5 - 0.5 * (double)J.width) * J.pitch,
-               ((double)py + 0.5 - 0.5 * (double)J.height) * J.pitch, 0.0};
-      D3 O, d;
-      double al, be;
-      if (J.phase_mode != HPT_PHASE_FP32) {
-        // s1: direction cosines uniform on the disc of radius lambda/(2d)
-        double rad = J.s_cone[U.ch] * sqrt(ud(w.x));
-        double sn, cs;
-        sincospi(2.0 * ud(w.y), &sn, &cs);
-        al = rad * cs; be = rad * sn;
-        D3 v = {al, be, sqrt(1.0 - al * al - be * be)};
-        if (J.identity_T) {
-          O = xp;
-          d = normalize(v);
-        } else {  // s2: into world space through the inverse of T (Eq. 3)
-          const double *M = J.Ti;
-          O = {M[0] * xp.x + M[1] * xp.y + M[2] * xp.z + M[3], M[4] * xp.x + M[5] * xp.y + M[6] * xp.z + M[7],
-               M[8] * xp.x + M[9] * xp.y + M[10] * xp.z + M[11]};
-          d = normalize(D3{M[0] * v.x + M[1] * v.y + M[2] * v.z, M[4] * v.x + M[5] * v.y + M[6] * v.z,
-                           M[8] * v.x + M[9] * v.y + M[10] * v.z});
-        }
-      } else {
-        float rad = J.s_cone_f[U.ch] * sqrtf(uf(w.x));
-        float sn, cs;
-        sincospif(2.0f * uf(w.y), &sn, &cs);
-        float alf = rad * cs, bef = rad * sn;
-        F3 v = f3(alf, bef, sqrtf(1.0f - alf * alf - bef * bef));
-        al = alf; be = bef;
-        F3 O32, d32;
-        if (J.identity_T) {
-          O32 = to_f(xp);
-          d32 = normalize(v);
-        } else {
-          float M[12];
-          for (int k = 0; k < 12; ++k) M[k] = (float)J.Ti[k];
-          F3 x = to_f(xp);
-          O32 = f3(M[0] * x.x + M[1] * x.y + M[2] * x.z + M[3], M[4] * x.x + M[5] * x.y + M[6] * x.z + M[7],
-                   M[8] * x.x + M[9] * x.y + M[10] * x.z + M[11]);
-          d32 = normalize(f3(M[0] * v.x + M[1] * v.y + M[2] * v.z, M[4] * v.x + M[5] * v.y + M[6] * v.z,
-                             M[8] * v.x + M[9] * v.y + M[10] * v.z));
-        }
-        O = to_d(O32); d = to_d(d32);
-      }
-      B.s_al[i] = al; B.s_be[i] = be;
-      B.s_ox[i] = O.x; B.s_oy[i] = O.y; B.s_oz[i] = O.z;
-      B.s_dx[i] = d.x; B.s_dy[i] = d.y; B.s_dz[i] = d.z;
-      B.s_ell[i] = 0.0;
-      B.s_W[i] = 1.0f;  // refractive index of the current medium while in the prefix
-      B.s_meta[i] = STAGE_PREFIX;
-      ro = to_f(O); rd = to_f(d);
-      key = morton8((float)(al / J.s_cone[U.ch]), (float)(be / J.s_cone[U.ch]));
-    } else {
-      // radiance-cache path: a point uniform in the cell, a direction uniform
-      // in the bin's octahedral square
-      const SceneDev &S = *J.scene;
-      uint32_t comp = U.ch;
-      uint32_t e = U.p_lo + p_local, j = U.s_lo + s_local;
-      uint32_t nb = J.cache_bins * J.cache_bins;
-      uint32_t cell = e / nb, bin = e - cell * nb;
-      uint32_t res = J.cache_res;
-      uint32_t ix = cell % res, iy = (cell / res) % res, iz = cell / (res * res);
-      uint32_t bu = bin % J.cache_bins, bv = bin / J.cache_bins;
-      uint32_t ka = cell, kb = (bin << 16) | j;
-      uint32_t sw = (comp << 16) | 2u;
-      U4 w0 = philox(ka, kb, 0u, sw, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
-      U4 w1 = philox(ka, kb, 1u, sw, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
-      D3 lo = {S.cache_lo_d[0], S.cache_lo_d[1], S.cache_lo_d[2]};
-      D3 ext = {S.cache_hi_d[0] - lo.x, S.cache_hi_d[1] - lo.y, S.cache_hi_d[2] - lo.z};
-      D3 x = {lo.x + (ix + ud(w0.x)) / res * ext.x, lo.y + (iy + ud(w0.y)) / res * ext.y,
-              lo.z + (iz + ud(w0.z)) / res * ext.z};
-      double pu = -1.0 + 2.0 * (bu + ud(w0.w)) / J.cache_bins;
-      double pv = -1.0 + 2.0 * (bv + ud(w1.x)) / J.cache_bins;
-      D3 d = oct_decode64(pu, pv);
-      B.s_ka[i] = ka;
-      B.s_kb[i] = kb;
-      B.s_meta[i] = STAGE_TAIL;  // b = 0, bP = 0
-      ro = to_f(x); rd = to_f(d);
-      key = morton8((float)pu, (float)pv);
-    }
+    gen_path(B, i, st, ska, skb, sal, sbe, ro, rd, key);  // the sort key only
   }
   uint32_t rank = valid ? atomicAdd(&hist[key], 1u) : 0u;
   __syncthreads();
@@ -230,7 +283,16 @@ __global__ void __launch_bounds__(kRaygenBlock) k_raygen(BatchDev B) {
     for (int k = 0; k < 64; ++k) { base[k] = acc; acc += hist[k]; }
   }
   __syncthreads();
-  if (valid) push_ray(B, 0, g0 + base[key] + rank, i, ro, rd, -1);
+  if (valid) perm[base[key] + rank] = (uint16_t)threadIdx.x;
+  __syncthreads();
+  // entry g0 + t of the first queue: the path at sorted position t,
+  // generated again (its random numbers are a function of the path), so that
+  // the queue entries are written in order
+  const uint32_t nv = min((uint32_t)blockDim.x, B.n_paths - g0);
+  if (threadIdx.x < nv) {
+    gen_path(B, g0 + perm[threadIdx.x], st, ska, skb, sal, sbe, ro, rd, key);
+    store_state(B.Q[0], g0 + threadIdx.x, st, nullptr, ska, skb, sal, sbe, ro, rd, -1);
+  }
 }
 
 // ------------------------------------------------------------------ trace
@@ -281,12 +343,11 @@ __global__ void __launch_bounds__(kBlock) k_trace(BatchDev B, int q) {
         uint32_t k = next + (uint32_t)__popcll(need & ((1ull << lane) - 1ull));
         if (k < end) {
           i = k;
-          uint32_t slot = B.q_slot[q][k];
           if (!B.scene_uniform) {
-            S = B.units[B.s_unit[slot]].scene;
+            S = B.units[B.Q[q].unit[k]].scene;
             N = as_global(S->nodes); P = as_global(S->prims); nn = S->n_nodes;
           }
-          float4 r0 = B.q_ray[q][2 * k], r1 = B.q_ray[q][2 * k + 1];
+          float4 r0 = B.Q[q].ray[2 * k], r1 = B.Q[q].ray[2 * k + 1];
           trav_init(T, f3(r0.x, r0.y, r0.z), f3(r1.x, r1.y, r1.z), r0.w, __float_as_int(r1.w), nn == 0);
         }
       }
@@ -299,8 +360,8 @@ __global__ void __launch_bounds__(kBlock) k_trace(BatchDev B, int q) {
     if (i >= 0) {
       if (T.node != kDone) trav_step<COUNT>(T, N, P, St, nv, nt);
       if (T.node == kDone) {
-        B.q_t[q][i] = T.best.t;
-        B.q_prim[q][i] = T.best.prim;
+        B.Q[q].t[i] = T.best.t;
+        B.Q[q].prim[i] = T.best.prim;
         i = -1;
       }
     }
@@ -318,7 +379,53 @@ __global__ void __launch_bounds__(kBlock) k_trace(BatchDev B, int q) {
 }
 
 // ------------------------------------------------------------------ shade
-struct Emit { bool on; F3 o, d; int32_t excl; };
+struct Emit { bool on; };
+
+// A workgroup's continuing rays, staged in LDS (one column per lane, field by
+// field so that lanes never share a bank) from the point where shading
+// finalises them until the compaction has given them their entry in the next
+// queue; this keeps the new state out of registers for the rest of the pass.
+struct StageLds {
+  uint32_t i[kBlock], slot[kBlock], unit[kBlock], meta[kBlock];
+  unsigned long long sig[kBlock];
+  float bpre[kBlock], wt[kBlock], beta[kBlock], L[kBlock];
+  double ox[kBlock], oy[kBlock], oz[kBlock], dx[kBlock], dy[kBlock], dz[kBlock], ell[kBlock];
+  float rox[kBlock], roy[kBlock], roz[kBlock], rdx[kBlock], rdy[kBlock], rdz[kBlock];
+  int32_t excl[kBlock];
+};
+
+__device__ __forceinline__ void stage_put(StageLds &G, const RayState &r, F3 o, F3 d, int32_t excl, Emit &e) {
+  const uint32_t t = threadIdx.x;
+  G.i[t] = r.i; G.slot[t] = r.slot; G.unit[t] = r.unit; G.meta[t] = r.meta;
+  G.sig[t] = r.sig;
+  G.bpre[t] = r.bpre; G.wt[t] = r.wt; G.beta[t] = r.beta; G.L[t] = r.L;
+  if ((r.meta & 1u) == STAGE_PREFIX) {
+    G.ox[t] = r.o.x; G.oy[t] = r.o.y; G.oz[t] = r.o.z;
+    G.dx[t] = r.d.x; G.dy[t] = r.d.y; G.dz[t] = r.d.z;
+    G.ell[t] = r.ell;
+  }
+  G.rox[t] = o.x; G.roy[t] = o.y; G.roz[t] = o.z;
+  G.rdx[t] = d.x; G.rdy[t] = d.y; G.rdz[t] = d.z;
+  G.excl[t] = excl;
+  e.on = true;
+}
+
+// Entry k of queue Q from this lane's staged ray; the read-only words come
+// from its entry in the source queue S.
+__device__ __forceinline__ void stage_store(const StageLds &G, const RayQueue &Q, uint32_t k, const RayQueue &S) {
+  const uint32_t t = threadIdx.x, i = G.i[t], meta = G.meta[t];
+  Q.slot[k] = G.slot[t]; Q.unit[k] = G.unit[t]; Q.meta[k] = meta;
+  Q.ka[k] = S.ka[i]; Q.kb[k] = S.kb[i];
+  Q.sig[k] = G.sig[t];
+  Q.bpre[k] = G.bpre[t]; Q.wt[k] = G.wt[t]; Q.beta[k] = G.beta[t]; Q.L[k] = G.L[t];
+  if ((meta & 1u) == STAGE_PREFIX) {
+    Q.ox[k] = G.ox[t]; Q.oy[k] = G.oy[t]; Q.oz[k] = G.oz[t];
+    Q.dx[k] = G.dx[t]; Q.dy[k] = G.dy[t]; Q.dz[k] = G.dz[t];
+    Q.ell[k] = G.ell[t]; Q.al[k] = S.al[i]; Q.be[k] = S.be[i];
+  }
+  Q.ray[2 * k] = make_float4(G.rox[t], G.roy[t], G.roz[t], kTmin);
+  Q.ray[2 * k + 1] = make_float4(G.rdx[t], G.rdy[t], G.rdz[t], __int_as_float(G.excl[t]));
+}
 
 __device__ __forceinline__ void write_rec_tail(const JobDev &J, const UnitDev &U, const BatchDev &B,
                                                uint32_t slot, int32_t kind, uint32_t b, float A,
@@ -332,16 +439,17 @@ __device__ __forceinline__ void write_rec_tail(const JobDev &J, const UnitDev &U
 }
 
 // End of a hologram path or a cache path.
-__device__ __forceinline__ void finish(const BatchDev &B, const UnitDev &U, const JobDev &J, uint32_t slot,
-                                       int32_t kind, uint32_t b, float L, unsigned long long sig,
-                                       bool has_image) {
+__device__ __forceinline__ void finish(const BatchDev &B, const UnitDev &U, const JobDev &J,
+                                       const RayState &r, int32_t kind, uint32_t b, float L,
+                                       unsigned long long sig, bool has_image) {
+  const uint32_t slot = r.slot;
   sig_add(sig, 0x100u | (uint32_t)kind);
-  B.s_sig[slot] = sig;
+  if (J.debug & 5u) B.s_sig[slot] = sig;  // records and signature sums
   if (U.kind == UNIT_CACHE) { B.r_amp[slot] = L; return; }
   float A = 0.f, amp = 0.f;
   if (has_image) {
-    A = sqrtf(B.s_bpre[slot] * L);
-    amp = A * B.s_W[slot] / (float)J.spp;
+    A = sqrtf(r.bpre * L);
+    amp = A * r.wt / (float)J.spp;
   }
   B.r_amp[slot] = amp;
   if (J.debug & 1u) write_rec_tail(J, U, B, slot, kind, b, A, amp, sig);
@@ -351,11 +459,12 @@ __device__ __forceinline__ void finish(const BatchDev &B, const UnitDev &U, cons
 // hit after optical path length ell: P' = O + ell v, Q = T P',
 // r = |Q - x_p|, weight W = r / p(v) with p(v) = v_z / (pi s^2); phase
 // record and the random-field texel that Q falls in.
-__device__ __forceinline__ void image_point(const BatchDev &B, const UnitDev &U, const JobDev &J,
-                                            uint32_t slot, double ell, uint32_t bP) {
-  uint32_t gpix = B.s_ka[slot];
+__device__ __forceinline__ void image_point(const BatchDev &B, const RayQueue &Q, const UnitDev &U,
+                                            const JobDev &J, RayState &st, double ell, uint32_t bP) {
+  const uint32_t slot = st.slot;
+  uint32_t gpix = Q.ka[st.i];
   uint32_t px = gpix % J.width, py = gpix / J.width;
-  double al = B.s_al[slot], be = B.s_be[slot];
+  double al = Q.al[st.i], be = Q.be[st.i];
   double s = J.s_cone[U.ch];
   double r, qx, qy, u, v, rev;
   float W;
@@ -427,7 +536,7 @@ __device__ __forceinline__ void image_point(const BatchDev &B, const UnitDev &U,
   B.r_fx[slot] = (float)(u - fu);
   B.r_fy[slot] = (float)(v - fv);
   B.r_rev[slot] = (float)rev;
-  B.s_W[slot] = W;
+  st.wt = W;
   if (J.debug & 1u) {
     uint32_t p_local, s_local;
     slot_decode(U, slot, p_local, s_local);
@@ -438,8 +547,9 @@ __device__ __forceinline__ void image_point(const BatchDev &B, const UnitDev &U,
 
 // One interaction of the incoherent tail at x (index b), reached along d_in
 // on primitive gid. Returns a ray to trace in `e`, or finishes the path.
-__device__ __forceinline__ void tail_interaction(const BatchDev &B, const UnitDev &U, const JobDev &J,
-                                                 const SceneDev &S, uint32_t slot, F3 x, F3 d_in,
+__device__ __forceinline__ void tail_interaction(const BatchDev &B, const RayQueue &Q, StageLds &G,
+                                                 const UnitDev &U, const JobDev &J, const SceneDev &S,
+                                                 RayState &st, F3 x, F3 d_in,
                                                  const HitRec &H, uint32_t b, uint32_t bP, uint32_t comp,
                                                  uint32_t stream, float beta, float L,
                                                  unsigned long long sig, Emit &e) {
@@ -450,14 +560,14 @@ __device__ __forceinline__ void tail_interaction(const BatchDev &B, const UnitDe
   if (m.type == HPT_EMITTER) {
     sig_add(sig, EV_EMIT);
     if (dot(d_in, ng) < 0.f) L += beta * (comp == 0 ? m.emit[0] : (comp == 1 ? m.emit[1] : m.emit[2]));
-    finish(B, U, J, slot, K_EMITTER, b, L, sig, holo);
+    finish(B, U, J, st, K_EMITTER, b, L, sig, holo);
     return;
   }
-  if (b >= J.max_bounces) { finish(B, U, J, slot, K_MAXB_TAIL, b, L, sig, holo); return; }
-  U4 w = philox(B.s_ka[slot], B.s_kb[slot], b << 8, stream, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
+  if (b >= J.max_bounces) { finish(B, U, J, st, K_MAXB_TAIL, b, L, sig, holo); return; }
+  U4 w = philox(Q.ka[st.i], Q.kb[st.i], b << 8, stream, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
   Lobe lb = sample_lobe(m, comp, d_in, ng, uf(w.x), uf(w.y), uf(w.z));
   sig_add(sig, lb.ev);
-  if (lb.w == 0.f) { finish(B, U, J, slot, K_ABSORBED, b, L, sig, holo); return; }
+  if (lb.w == 0.f) { finish(B, U, J, st, K_ABSORBED, b, L, sig, holo); return; }
   beta *= lb.w;
   if (holo && J.use_cache && !lb.delta && (b - bP + 1) >= J.cache_depth) {
     uint32_t res = S.cache_res, nb = S.cache_bins * S.cache_bins;
@@ -471,34 +581,36 @@ __device__ __forceinline__ void tail_interaction(const BatchDev &B, const UnitDe
     sig_add(sig, 0x50000000u | bin);
     if (J.debug & 1u) {
       uint32_t p_local, s_local;
-      slot_decode(U, slot, p_local, s_local);
+      slot_decode(U, st.slot, p_local, s_local);
       hpt_path_record *R = J.rec + rec_index(J, U, p_local, s_local);
       R->cache_cell = (int32_t)cell;
       R->cache_bin = (int32_t)bin;
     }
     size_t ce = (size_t)comp * res * res * res * nb + (size_t)cell * nb + bin;
     L += beta * __half2float(__ushort_as_half(S.cache[ce]));
-    finish(B, U, J, slot, K_CACHE, b, L, sig, true);
+    finish(B, U, J, st, K_CACHE, b, L, sig, true);
     return;
   }
-  B.s_beta[slot] = beta;
-  B.s_L[slot] = L;
-  B.s_sig[slot] = sig;
-  B.s_meta[slot] = STAGE_TAIL | (b << 1) | (bP << 7);
-  e.on = true; e.o = x; e.d = lb.d;
-  e.excl = gid >= (int32_t)S.n_sph ? gid : -1;
+  st.beta = beta;
+  st.L = L;
+  st.sig = sig;
+  st.meta = STAGE_TAIL | (b << 1) | (bP << 7);
+  stage_put(G, st, x, lb.d, gid >= (int32_t)S.n_sph ? gid : -1, e);
 }
 
-__device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, Emit &e) {
-  uint32_t slot = B.q_slot[q][i];
-  const UnitDev &U = B.units[B.s_unit[slot]];
+// Shade entry i of queue q, whose state is st; st is updated in place for a
+// path that continues (e.on).
+__device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, RayState &st, StageLds &G,
+                                          Emit &e) {
+  const UnitDev &U = B.units[st.unit];
   const JobDev &J = *U.job;
   const SceneDev &S = *J.scene;
-  uint32_t meta = B.s_meta[slot];
+  const RayQueue &Q = B.Q[q];
+  uint32_t meta = st.meta;
   uint32_t stage = meta & 1u, b = (meta >> 1) & 63u, bP = (meta >> 7) & 63u;
-  float t = B.q_t[q][i];
-  int32_t hp = B.q_prim[q][i];
-  unsigned long long sig = B.s_sig[slot];
+  float t = Q.t[i];
+  int32_t hp = Q.prim[i];
+  unsigned long long sig = st.sig;
   bool holo = U.kind == UNIT_HOLO;
   uint32_t comp = holo ? J.comp[U.ch] : U.ch;
   uint32_t stream = (comp << 16) | (holo ? 0u : 2u);
@@ -508,17 +620,16 @@ __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, 
   if (stage == STAGE_PREFIX) {
     if (gid < 0) {
       sig_add(sig, 0xFFFFFFFFu);
-      finish(B, U, J, slot, K_ESCAPE_PREFIX, b, 0.f, sig, false);
+      finish(B, U, J, st, K_ESCAPE_PREFIX, b, 0.f, sig, false);
       return;
     }
     b += 1;
-    if (b == 1) B.s_first[slot] = gid;
+    if (b == 1 && (J.debug & 1u)) B.s_first[st.slot] = gid;
     sig_add(sig, (uint32_t)gid + 1u);
-    if (b > J.max_bounces) { finish(B, U, J, slot, K_MAXB_PREFIX, b, 0.f, sig, false); return; }
-    D3 o = {B.s_ox[slot], B.s_oy[slot], B.s_oz[slot]};
-    D3 d = {B.s_dx[slot], B.s_dy[slot], B.s_dz[slot]};
-    double ell = B.s_ell[slot];
-    float ncur = B.s_W[slot];
+    if (b > J.max_bounces) { finish(B, U, J, st, K_MAXB_PREFIX, b, 0.f, sig, false); return; }
+    D3 o = st.o, d = st.d;
+    double ell = st.ell;
+    float ncur = st.wt;
     bool tri = gid >= (int32_t)S.n_sph;
     const MaterialDev m = S.mats[H.mat];
     bool delta = m.type == HPT_MIRROR || m.type == HPT_DIELECTRIC;
@@ -534,8 +645,7 @@ __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, 
     D3 x = o + t64 * d;
     if (J.phase_mode == HPT_PHASE_FP32) x = to_d(to_f(o) + t * to_f(d));
     if (delta) {
-      U4 w = philox(B.s_ka[slot], B.s_kb[slot], b << 8, stream, (uint32_t)J.seed,
-                    (uint32_t)(J.seed >> 32));
+      U4 w = philox(Q.ka[i], Q.kb[i], b << 8, stream, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
       D3 ng;
       if (tri) ng = D3{pl.x, pl.y, pl.z};
       else ng = (1.0 / pl.w) * (x - D3{pl.x, pl.y, pl.z});
@@ -561,39 +671,40 @@ __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, 
       }
       if (J.phase_mode == HPT_PHASE_FP32) d = to_d(normalize(to_f(d)));
       sig_add(sig, ev);
-      B.s_bpre[slot] *= (float)wgt;
-      B.s_ox[slot] = x.x; B.s_oy[slot] = x.y; B.s_oz[slot] = x.z;
-      B.s_dx[slot] = d.x; B.s_dy[slot] = d.y; B.s_dz[slot] = d.z;
-      B.s_ell[slot] = ell;
-      B.s_W[slot] = ncur;
-      B.s_sig[slot] = sig;
-      B.s_meta[slot] = STAGE_PREFIX | (b << 1);
-      e.on = true; e.o = to_f(x); e.d = to_f(d); e.excl = tri ? gid : -1;
+      st.bpre *= (float)wgt;
+      st.o = x;
+      st.d = d;
+      st.ell = ell;
+      st.wt = ncur;
+      st.sig = sig;
+      st.meta = STAGE_PREFIX | (b << 1);
+      stage_put(G, st, to_f(x), to_f(d), tri ? gid : -1, e);
       return;
     }
     // first non-delta hit: the real image point P
     sig_add(sig, EV_IMAGE_POINT);
-    image_point(B, U, J, slot, ell, b);
-    tail_interaction(B, U, J, S, slot, to_f(x), to_f(d), H, b, b, comp, stream, 1.0f, 0.0f, sig, e);
+    image_point(B, Q, U, J, st, ell, b);
+    tail_interaction(B, Q, G, U, J, S, st, to_f(x), to_f(d), H, b, b, comp, stream, 1.0f, 0.0f, sig, e);
     return;
   }
   // incoherent tail (or cache path)
-  float beta = B.s_beta[slot], L = B.s_L[slot];
-  float4 r0 = B.q_ray[q][2 * i], r1 = B.q_ray[q][2 * i + 1];
+  float beta = st.beta, L = st.L;
+  float4 r0 = Q.ray[2 * i], r1 = Q.ray[2 * i + 1];
   if (gid < 0) {
     L += beta * S.env[comp];
     sig_add(sig, 0xFFFFFFFEu);
-    finish(B, U, J, slot, K_ENV, b, L, sig, holo);
+    finish(B, U, J, st, K_ENV, b, L, sig, holo);
     return;
   }
   b += 1;
   sig_add(sig, (uint32_t)gid + 1u);
   F3 d_in = f3(r1.x, r1.y, r1.z);
   F3 x = f3(r0.x, r0.y, r0.z) + t * d_in;
-  tail_interaction(B, U, J, S, slot, x, d_in, H, b, bP, comp, stream, beta, L, sig, e);
+  tail_interaction(B, Q, G, U, J, S, st, x, d_in, H, b, bP, comp, stream, beta, L, sig, e);
 }
 
 __global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
+  __shared__ StageLds G;
   uint32_t n = B.counters[q];
   int qo = q ^ 1;
   if (blockIdx.x == 0 && threadIdx.x == 0) B.counters[4 + q] = 0;  // traversal claims of queue q
@@ -606,10 +717,15 @@ __global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
   const uint32_t blk = b < nb8 ? (b % 8u) * (nb8 / 8u) + b / 8u : b;
   const uint32_t stride = max(gridDim.x, nb8) * blockDim.x;
   for (uint32_t base = blk * blockDim.x; base < n; base += stride) {
-    uint32_t i = base + threadIdx.x;
+    const uint32_t i = base + threadIdx.x;
+    const bool live = i < n;
     Emit e;
     e.on = false;
-    if (i < n) shade_one(B, q, i, e);
+    if (live) {
+      RayState st;
+      load_state(B.Q[q], i, st);
+      shade_one(B, q, i, st, G, e);
+    }
     // compaction: one atomic per wave, lane offsets from the ballot
     unsigned long long m = __ballot(e.on);
     uint32_t cnt = (uint32_t)__popcll(m);
@@ -620,7 +736,7 @@ __global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
     uint32_t pos0 = 0;
     if (lane == first) pos0 = atomicAdd(&B.counters[qo], cnt);
     pos0 = __shfl(pos0, (int)first);
-    if (e.on) push_ray(B, qo, pos0 + before, B.q_slot[q][i], e.o, e.d, e.excl);
+    if (e.on) stage_store(G, B.Q[qo], pos0 + before, B.Q[q]);
   }
 }
 

@@ -48,8 +48,9 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
 }
 
 constexpr uint32_t kMaxUnitsPerBatch = 4096;
-// path state, results and two queues
-constexpr size_t kBytesPerPath = 4 * 4 + 9 * 8 + 4 * 4 + 8 + 4 + 4 * 4 + 8 + 4 + 2 * (4 + 32 + 4 + 4);
+// per path: final signature, first hit, results; per queue entry (two
+// queues): state (40 B), FP64 prefix ray (72 B), FP32 ray (32 B), hit (8 B)
+constexpr size_t kBytesPerPath = 8 + 4 + 4 * 4 + 8 + 4 + 2 * (40 + 72 + 32 + 8);
 
 struct Scene {
   uint64_t id = 0;
@@ -555,18 +556,20 @@ hpt_status alloc_batch(hpt_ctx *C) {
     return true;
   };
   bool ok = true;
-  ok &= A((void **)&B.s_meta, 4ull * N) && A((void **)&B.s_unit, 4ull * N) && A((void **)&B.s_ka, 4ull * N) &&
-        A((void **)&B.s_kb, 4ull * N);
-  ok &= A((void **)&B.s_ox, 8ull * N) && A((void **)&B.s_oy, 8ull * N) && A((void **)&B.s_oz, 8ull * N) &&
-        A((void **)&B.s_dx, 8ull * N) && A((void **)&B.s_dy, 8ull * N) && A((void **)&B.s_dz, 8ull * N) &&
-        A((void **)&B.s_ell, 8ull * N) && A((void **)&B.s_al, 8ull * N) && A((void **)&B.s_be, 8ull * N);
-  ok &= A((void **)&B.s_bpre, 4ull * N) && A((void **)&B.s_beta, 4ull * N) && A((void **)&B.s_L, 4ull * N) &&
-        A((void **)&B.s_W, 4ull * N) && A((void **)&B.s_sig, 8ull * N) && A((void **)&B.s_first, 4ull * N);
+  ok &= A((void **)&B.s_sig, 8ull * N) && A((void **)&B.s_first, 4ull * N);
   ok &= A((void **)&B.r_amp, 4ull * N) && A((void **)&B.r_rev, 4ull * N) && A((void **)&B.r_fx, 4ull * N) &&
         A((void **)&B.r_fy, 4ull * N) && A((void **)&B.r_r64, 8ull * N) && A((void **)&B.r_tex, 4ull * N);
-  for (int q = 0; q < 2 && ok; ++q)
-    ok &= A((void **)&B.q_slot[q], 4ull * N) && A((void **)&B.q_ray[q], 32ull * N) &&
-          A((void **)&B.q_t[q], 4ull * N) && A((void **)&B.q_prim[q], 4ull * N);
+  for (int q = 0; q < 2 && ok; ++q) {
+    RayQueue &Q = B.Q[q];
+    ok &= A((void **)&Q.slot, 4ull * N) && A((void **)&Q.unit, 4ull * N) && A((void **)&Q.meta, 4ull * N) &&
+          A((void **)&Q.ka, 4ull * N) && A((void **)&Q.kb, 4ull * N) && A((void **)&Q.sig, 8ull * N) &&
+          A((void **)&Q.bpre, 4ull * N) && A((void **)&Q.wt, 4ull * N) && A((void **)&Q.beta, 4ull * N) &&
+          A((void **)&Q.L, 4ull * N);
+    ok &= A((void **)&Q.ox, 8ull * N) && A((void **)&Q.oy, 8ull * N) && A((void **)&Q.oz, 8ull * N) &&
+          A((void **)&Q.dx, 8ull * N) && A((void **)&Q.dy, 8ull * N) && A((void **)&Q.dz, 8ull * N) &&
+          A((void **)&Q.ell, 8ull * N) && A((void **)&Q.al, 8ull * N) && A((void **)&Q.be, 8ull * N);
+    ok &= A((void **)&Q.ray, 32ull * N) && A((void **)&Q.t, 4ull * N) && A((void **)&Q.prim, 4ull * N);
+  }
   ok &= A((void **)&B.counters, 64);
   ok &= A((void **)&B.work, 64);
   B.spill_threads = trace_grid(N) * trace_block();
