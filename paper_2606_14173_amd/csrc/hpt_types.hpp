@@ -112,7 +112,6 @@ struct UnitDev {
   const SceneDev *scene;
 };
 
-// Path state, records and queues of one batch (structure of arrays).
 // One ray queue: entry k is a live ray with the state its path carries from
 // bounce to bounce (structure of arrays, so each field is read and written
 // coalesced). The FP64 fields are read and written only while the ray is in
@@ -146,6 +145,7 @@ struct BatchDev {
   int32_t *stack_spill;      // [kStackSpill][spill_threads] traversal stack beyond the LDS part
   uint32_t spill_threads;    // threads the spill has a column for
   const SceneDev *scene_uniform;  // the one scene of every unit, or null for mixed batches
+  const JobDev *job_uniform;      // the one job of every unit, or null
 };
 
 }  // namespace hpt

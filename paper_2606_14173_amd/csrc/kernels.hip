@@ -599,11 +599,12 @@ __device__ __forceinline__ void tail_interaction(const BatchDev &B, const RayQue
 }
 
 // Shade entry i of queue q, whose state is st; st is updated in place for a
-// path that continues (e.on).
+// path that continues (e.on). Jl: the batch's one job in LDS (its scene and
+// materials too), or null when the batch mixes jobs.
 __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, RayState &st, StageLds &G,
-                                          Emit &e) {
+                                          const JobDev *Jl, Emit &e) {
   const UnitDev &U = B.units[st.unit];
-  const JobDev &J = *U.job;
+  const JobDev &J = Jl ? *Jl : *U.job;
   const SceneDev &S = *J.scene;
   const RayQueue &Q = B.Q[q];
   uint32_t meta = st.meta;
@@ -703,8 +704,14 @@ __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, 
   tail_interaction(B, Q, G, U, J, S, st, x, d_in, H, b, bP, comp, stream, beta, L, sig, e);
 }
 
+constexpr uint32_t kLdsMats = 64;  // materials a workgroup keeps in LDS
+
 __global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
   __shared__ StageLds G;
+  __shared__ JobDev lds_job;
+  __shared__ SceneDev lds_scene;
+  __shared__ MaterialDev lds_mats[kLdsMats];
+  __shared__ uint32_t wave_cnt[kBlock / 64], wave_base[kBlock / 64 + 1];
   uint32_t n = B.counters[q];
   int qo = q ^ 1;
   if (blockIdx.x == 0 && threadIdx.x == 0) B.counters[4 + q] = 0;  // traversal claims of queue q
@@ -716,6 +723,30 @@ __global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
   const uint32_t b = blockIdx.x;
   const uint32_t blk = b < nb8 ? (b % 8u) * (nb8 / 8u) + b / 8u : b;
   const uint32_t stride = max(gridDim.x, nb8) * blockDim.x;
+  if (blk * blockDim.x >= n) return;  // no entries for this workgroup
+  // A batch of one job: its job, scene and material descriptors are copied
+  // to LDS once per workgroup, so shading reads them without the dependent
+  // global loads unit -> job -> scene -> material.
+  const JobDev *Jl = nullptr;
+  if (B.job_uniform && B.scene_uniform) {
+    const uint32_t t = threadIdx.x;
+    const uint32_t *jsrc = (const uint32_t *)B.job_uniform, *ssrc = (const uint32_t *)B.scene_uniform;
+    for (uint32_t k = t; k < sizeof(JobDev) / 4; k += blockDim.x) ((uint32_t *)&lds_job)[k] = jsrc[k];
+    for (uint32_t k = t; k < sizeof(SceneDev) / 4; k += blockDim.x) ((uint32_t *)&lds_scene)[k] = ssrc[k];
+    const uint32_t nm = B.scene_uniform->n_mat;
+    if (nm <= kLdsMats) {
+      const uint32_t *msrc = (const uint32_t *)B.scene_uniform->mats;
+      for (uint32_t k = t; k < nm * (uint32_t)(sizeof(MaterialDev) / 4); k += blockDim.x)
+        ((uint32_t *)lds_mats)[k] = msrc[k];
+    }
+    __syncthreads();
+    if (t == 0) {
+      lds_job.scene = &lds_scene;
+      if (nm <= kLdsMats) lds_scene.mats = lds_mats;
+    }
+    __syncthreads();
+    Jl = &lds_job;
+  }
   for (uint32_t base = blk * blockDim.x; base < n; base += stride) {
     const uint32_t i = base + threadIdx.x;
     const bool live = i < n;
@@ -724,19 +755,22 @@ __global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
     if (live) {
       RayState st;
       load_state(B.Q[q], i, st);
-      shade_one(B, q, i, st, G, e);
+      shade_one(B, q, i, st, G, Jl, e);
     }
-    // compaction: one atomic per wave, lane offsets from the ballot
+    // compaction: wave counts from ballots, one atomic per workgroup (all
+    // workgroups add to the same counter, so fewer atomics is what matters)
     unsigned long long m = __ballot(e.on);
-    uint32_t cnt = (uint32_t)__popcll(m);
-    if (cnt == 0) continue;
-    uint32_t lane = __lane_id();
-    uint32_t before = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-    uint32_t first = (uint32_t)__ffsll((long long)m) - 1u;
-    uint32_t pos0 = 0;
-    if (lane == first) pos0 = atomicAdd(&B.counters[qo], cnt);
-    pos0 = __shfl(pos0, (int)first);
-    if (e.on) stage_store(G, B.Q[qo], pos0 + before, B.Q[q]);
+    const uint32_t lane = __lane_id(), wv = threadIdx.x / 64u;
+    if (lane == 0) wave_cnt[wv] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint32_t tot = 0;
+      for (uint32_t k = 0; k < kBlock / 64; ++k) { wave_base[k] = tot; tot += wave_cnt[k]; }
+      wave_base[kBlock / 64] = tot ? atomicAdd(&B.counters[qo], tot) : 0u;
+    }
+    __syncthreads();
+    const uint32_t before = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    if (e.on) stage_store(G, B.Q[qo], wave_base[kBlock / 64] + wave_base[wv] + before, B.Q[q]);
   }
 }
 

@@ -395,8 +395,11 @@ hpt_status run_batch(hpt_ctx *C, const std::vector<Picked> &P, uint32_t profile,
   }
   BatchDev B = C->batch;
   B.scene_uniform = P.empty() ? nullptr : P[0].job->scene->dev;
-  for (auto &p : P)
+  B.job_uniform = P.empty() ? nullptr : P[0].job->dev;
+  for (auto &p : P) {
     if (p.job->scene->dev != B.scene_uniform) B.scene_uniform = nullptr;
+    if (p.job->dev != B.job_uniform) B.job_uniform = nullptr;
+  }
   B.units = C->d_units;
   B.n_units = (uint32_t)P.size();
   B.n_paths = slot;
