@@ -19,6 +19,13 @@ constexpr int kStackSpill = kStackMax - kStackLds;  // further entries per lane 
 #endif
 constexpr int kTraceChunk = HPT_TRACE_CHUNK;  // queue entries a traversal wave claims at a time
 constexpr uint32_t kTraceGridMax = 2048;      // traversal workgroups per launch (8 per CU)
+#ifndef HPT_CLAIM_CLASSES
+#define HPT_CLAIM_CLASSES 8
+#endif
+constexpr uint32_t kClaimClasses = HPT_CLAIM_CLASSES;  // chunk classes, one claim counter each
+static_assert(kTraceGridMax % kClaimClasses == 0 && kClaimClasses % 8 == 0,
+              "the traversal grid (a multiple of 8, capped) must give every class workgroups");
+constexpr uint32_t kClaimStride = 32;         // words between claim counters (own 128-byte line)
 constexpr float kTmin = 1e-7f;       // self-intersection guard (metres)
 constexpr double kTminD = 1e-7;
 
@@ -140,7 +147,8 @@ struct BatchDev {
   double *r_r64;
   uint32_t *r_tex;
   RayQueue Q[2];
-  uint32_t *counters;        // [0], [1]: queue lengths; [2]: rays traced; [4], [5]: traversal claims
+  uint32_t *counters;        // [0], [1]: queue lengths; [2]: rays traced
+  uint32_t *claims;          // traversal claim counters: queue q, class c at [(8 q + c) * kClaimStride]
   unsigned long long *work;  // [0] node visits, [1] primitive tests (counting traversal)
   int32_t *stack_spill;      // [kStackSpill][spill_threads] traversal stack beyond the LDS part
   uint32_t spill_threads;    // threads the spill has a column for

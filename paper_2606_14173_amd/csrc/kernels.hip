@@ -296,12 +296,16 @@ __global__ void __launch_bounds__(kRaygenBlock) k_raygen(BatchDev B) {
 }
 
 // ------------------------------------------------------------------ trace
-// FP32 closest hit for every ray of queue q. Waves claim kTraceChunk
-// consecutive queue entries at a time from the queue's claim counter
-// (counters[4 + q], zeroed by the shading pass of the previous use of the
-// queue), and a lane that finishes its ray takes the next entry of the
-// wave's chunk, so lanes do not idle while the wave's longest ray finishes
-// and the launch ends when the queue is drained, however short the queue.
+// FP32 closest hit for every ray of queue q. The queue is cut into chunks of
+// kTraceChunk entries; chunk j belongs to class j mod kClaimClasses, and the
+// waves of workgroups with blockIdx mod kClaimClasses = c claim the chunks of
+// class c one at a time from that class's counter (zeroed by the shading pass
+// of the previous use of the queue), so the claim atomics are spread over
+// kClaimClasses addresses (all atomics on one counter serialise). A lane that
+// finishes its ray takes the next entry of the wave's chunk, so lanes do not
+// idle while the wave's longest ray finishes, and the launch ends when the
+// queue is drained, however short the queue. The grid is a multiple of
+// kClaimClasses workgroups, so every class is drained.
 // The traversal stack is kStackLds entries per lane in LDS, then the lane's
 // column of the global spill.
 template <bool COUNT>
@@ -312,7 +316,9 @@ __global__ void __launch_bounds__(kBlock) k_trace(BatchDev B, int q) {
     B.counters[q ^ 1] = 0;
     B.counters[2] += n;
   }
-  uint32_t *claim = B.counters + 4 + q;
+  const uint32_t cls = blockIdx.x % kClaimClasses;
+  uint32_t *claim = B.claims + ((uint32_t)q * kClaimClasses + cls) * kClaimStride;
+  const uint32_t n_chunks = (n + kTraceChunk - 1) / kTraceChunk;
   const uint32_t lane = __lane_id();
   const Stack St{(LdsI32)(stack + threadIdx.x), kBlock,
                  (GlbI32)(B.stack_spill + xcd_block() * blockDim.x + threadIdx.x), B.spill_threads};
@@ -326,14 +332,14 @@ __global__ void __launch_bounds__(kBlock) k_trace(BatchDev B, int q) {
   uint32_t nn = S ? S->n_nodes : 0;
   for (;;) {
     if (more && next >= end && __any(i < 0)) {  // claim the next chunk
-      uint32_t c = 0;
-      if (lane == 0) c = atomicAdd(claim, (uint32_t)kTraceChunk);
-      c = __shfl(c, 0);
-      if (c >= n) {
+      uint32_t k = 0;
+      if (lane == 0) k = atomicAdd(claim, 1u);
+      const uint32_t j = __shfl(k, 0) * kClaimClasses + cls;  // chunk index
+      if (j >= n_chunks) {
         more = false;
       } else {
-        next = c;
-        end = min(n, c + (uint32_t)kTraceChunk);
+        next = j * (uint32_t)kTraceChunk;
+        end = min(n, next + (uint32_t)kTraceChunk);
       }
     }
     // refill idle lanes from the chunk, in lane order
@@ -714,7 +720,8 @@ __global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
   __shared__ uint32_t wave_cnt[kBlock / 64], wave_base[kBlock / 64 + 1];
   uint32_t n = B.counters[q];
   int qo = q ^ 1;
-  if (blockIdx.x == 0 && threadIdx.x == 0) B.counters[4 + q] = 0;  // traversal claims of queue q
+  if (blockIdx.x == 0 && threadIdx.x < kClaimClasses)  // traversal claims of queue q
+    B.claims[((uint32_t)q * kClaimClasses + threadIdx.x) * kClaimStride] = 0;
   // Neighbouring queue entries touch the same slot windows: the blocks that
   // have entries (the first ceil(n / blockDim) of the grid, which the
   // hardware deals to the 8 XCDs in turn) are remapped so that each XCD
@@ -965,7 +972,8 @@ uint32_t trace_grid(uint32_t n_paths) {
   // enough waves to fill every CU; waves beyond the resident ones find the
   // queue drained and exit
   uint64_t waves = ((uint64_t)n_paths + kTraceChunk - 1) / kTraceChunk;
-  uint32_t g = round8((uint32_t)((waves * 64 + kBlock - 1) / kBlock));
+  uint32_t g = (uint32_t)((waves * 64 + kBlock - 1) / kBlock);
+  g = (g + kClaimClasses - 1) / kClaimClasses * kClaimClasses;  // every class has workgroups
   return g < kTraceGridMax ? g : kTraceGridMax;
 }
 

@@ -422,6 +422,8 @@ hpt_status run_batch(hpt_ctx *C, const std::vector<Picked> &P, uint32_t profile,
   };
   e = hipMemcpyAsync(C->d_units, C->h_units, P.size() * sizeof(UnitDev), hipMemcpyHostToDevice, C->stream);
   if (e == hipSuccess) e = hipMemsetAsync(B.counters, 0, 8 * sizeof(uint32_t), C->stream);
+  if (e == hipSuccess)
+    e = hipMemsetAsync(B.claims, 0, 2 * kClaimClasses * kClaimStride * sizeof(uint32_t), C->stream);
   if (e == hipSuccess && profile >= 2) e = hipMemsetAsync(B.work, 0, 2 * sizeof(unsigned long long), C->stream);
   if (e == hipSuccess) e = hipEventRecord(C->ev0, C->stream);
   timed(HPT_K_RAYGEN, [&] { return launch_raygen(B, C->stream); });
@@ -574,6 +576,7 @@ hpt_status alloc_batch(hpt_ctx *C) {
     ok &= A((void **)&Q.ray, 32ull * N) && A((void **)&Q.t, 4ull * N) && A((void **)&Q.prim, 4ull * N);
   }
   ok &= A((void **)&B.counters, 64);
+  ok &= A((void **)&B.claims, 2 * kClaimClasses * kClaimStride * sizeof(uint32_t));
   ok &= A((void **)&B.work, 64);
   B.spill_threads = trace_grid(N) * trace_block();
   ok &= A((void **)&B.stack_spill, (size_t)kStackSpill * B.spill_threads * sizeof(int32_t));
