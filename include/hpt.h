@@ -222,8 +222,8 @@ hpt_status hpt_ctx_stats_get(hpt_ctx *ctx, hpt_ctx_stats *out);
  *     re, im), row-major; may be the same buffer. Caller-owned.
  *   width, height: 1..4096; pitch, lambda > 0 (metres); distance finite.
  * Synchronous (returns when d_out is written). Scratch (two [height][P_x]
- * complex64 buffers per field of a chunk of fields, at most 1 GiB) is taken
- * from the context's budget for the call. EINVAL on bad arguments, EBUDGET if
+ * complex64 buffers per field of a chunk of fields, at most 1 GiB, and the
+ * transforms' twiddle tables) is taken from the context's budget for the call. EINVAL on bad arguments, EBUDGET if
  * one field's scratch does not fit, EDEVICE on a HIP error. */
 #define HPT_ASM_BAND_LIMIT 1u
 hpt_status hpt_asm_propagate(hpt_ctx *ctx, const void *d_in, void *d_out, uint32_t n_fields,

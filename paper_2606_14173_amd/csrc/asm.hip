@@ -18,8 +18,8 @@
 // Line FFTs run in LDS, one workgroup per line: radix-4 Stockham stages
 // (Govindaraju et al., SC 2008 formulation), a final radix-2 stage when
 // log2(n) is odd; each stage reads its operands into registers, synchronises,
-// and writes the results back in place. Twiddles exp(-+2 pi i k / L) come from
-// sincospif of the exact rational k / L.
+// and writes the results back in place. Twiddles come from a table of
+// exp(-2 pi i m / n), m < n, per transform length, built once per call in FP64.
 #include <hip/hip_runtime.h>
 
 #include "asm.hpp"
@@ -38,11 +38,11 @@ __device__ __forceinline__ C2 mul(C2 a, C2 b) { return {a.x * b.x - a.y * b.y, a
 // multiply by -i (forward) or +i (inverse)
 __device__ __forceinline__ C2 rot(C2 a, bool inv) { return inv ? c2(-a.y, a.x) : c2(a.y, -a.x); }
 
-// exp(s 2 pi i num / den) with s = -1 forward, +1 inverse
-__device__ __forceinline__ C2 twiddle(uint32_t num, uint32_t den, bool inv) {
-  float sn, cs;
-  sincospif(2.0f * (float)num / (float)den, &sn, &cs);
-  return c2(cs, inv ? sn : -sn);
+// exp(s 2 pi i m / n) with s = -1 forward, +1 inverse, from the table
+// tw[m] = exp(-2 pi i m / n) of the transform length n.
+__device__ __forceinline__ C2 twiddle(const float2 *tw, uint32_t m, bool inv) {
+  const float2 v = tw[m];
+  return c2(v.x, inv ? -v.y : v.y);
 }
 
 // In-place FFT of the n = 2^lg values in LDS buffer x (all threads of the
@@ -51,7 +51,7 @@ __device__ __forceinline__ C2 twiddle(uint32_t num, uint32_t den, bool inv) {
 // (static indices), written back after the whole stage has been read.
 // U4: butterflies per thread and radix-4 stage (n <= 4 * U4 * kFftThreads).
 template <int U4>
-__device__ void lds_fft(C2 *x, uint32_t n, uint32_t lg, bool inv) {
+__device__ void lds_fft(C2 *x, uint32_t n, uint32_t lg, bool inv, const float2 *tw) {
   constexpr int U2 = 2 * U4;
   const uint32_t tid = threadIdx.x;
   uint32_t Ns = 1;
@@ -64,10 +64,11 @@ __device__ void lds_fft(C2 *x, uint32_t n, uint32_t lg, bool inv) {
       if (j < q) {
         const uint32_t k = j % Ns;
         C2 a0 = x[j], a1 = x[j + q], a2 = x[j + 2 * q], a3 = x[j + 3 * q];
-        if (Ns > 1) {
-          a1 = mul(a1, twiddle(k, 4 * Ns, inv));
-          a2 = mul(a2, twiddle(2 * k, 4 * Ns, inv));
-          a3 = mul(a3, twiddle(3 * k, 4 * Ns, inv));
+        if (Ns > 1) {  // exp(-+2 pi i e k / (4 Ns)) = tw[e k n / (4 Ns)]
+          const uint32_t st = k * (n / (4 * Ns));
+          a1 = mul(a1, twiddle(tw, st, inv));
+          a2 = mul(a2, twiddle(tw, 2 * st, inv));
+          a3 = mul(a3, twiddle(tw, 3 * st, inv));
         }
         C2 b0 = add(a0, a2), b1 = sub(a0, a2), b2 = add(a1, a3), b3 = rot(sub(a1, a3), inv);
         v[u][0] = add(b0, b2);
@@ -99,7 +100,7 @@ __device__ void lds_fft(C2 *x, uint32_t n, uint32_t lg, bool inv) {
       const uint32_t j = tid + (uint32_t)u * kFftThreads;
       if (j < hn) {
         C2 a0 = x[j], a1 = x[j + hn];
-        if (Ns > 1) a1 = mul(a1, twiddle(j % Ns, 2 * Ns, inv));
+        if (Ns > 1) a1 = mul(a1, twiddle(tw, (j % Ns) * (n / (2 * Ns)), inv));
         v[u][0] = add(a0, a1);
         v[u][1] = sub(a0, a1);
       }
@@ -121,7 +122,7 @@ __device__ void lds_fft(C2 *x, uint32_t n, uint32_t lg, bool inv) {
 // Forward FFT of row (f, y) of in [nf][h][w], zero-padded to Px -> A [nf][h][Px].
 template <int U4>
 __global__ void __launch_bounds__(kFftThreads) k_fft_rows(const float2 *in, float2 *A, uint32_t w, uint32_t h,
-                                                          uint32_t px, uint32_t lgx) {
+                                                          uint32_t px, uint32_t lgx, const float2 *tw) {
   extern __shared__ C2 lds[];
   const size_t row = blockIdx.x;  // f * h + y
   const float2 *src = in + row * w;
@@ -130,7 +131,7 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows(const float2 *in, floa
     lds[i] = c2(v.x, v.y);
   }
   __syncthreads();
-  lds_fft<U4>(lds, px, lgx, false);
+  lds_fft<U4>(lds, px, lgx, false, tw);
   float2 *dst = A + row * px;
   for (uint32_t i = threadIdx.x; i < px; i += kFftThreads) dst[i] = make_float2(lds[i].x, lds[i].y);
 }
@@ -154,49 +155,74 @@ __global__ void __launch_bounds__(256) k_transpose(const float2 *in, float2 *out
   }
 }
 
-// Column kx of every field: B [nf][Px][h] holds the row spectra transposed.
-// Zero-pad the column to Py, FFT, multiply by H(f_x, f_y), inverse FFT, and
-// keep rows [0, h).
+// Column kx of all nf fields: B [nf][Px][h] holds the row spectra
+// transposed. The transfer function of the column is computed once (each
+// thread keeps its rows' values in registers) and applied to every field:
+// zero-pad the column to Py, FFT, multiply by H(f_x, f_y), inverse FFT, keep
+// rows [0, h).
 template <int U4>
-__global__ void __launch_bounds__(kFftThreads) k_fft_columns(float2 *B, uint32_t h, uint32_t px, uint32_t py,
-                                                             uint32_t lgy, AsmParams P) {
+__global__ void __launch_bounds__(kFftThreads) k_fft_columns(float2 *B, uint32_t nf, uint32_t h, uint32_t px,
+                                                             uint32_t py, uint32_t lgy, AsmParams P,
+                                                             const float2 *tw) {
   extern __shared__ C2 lds[];
-  const size_t line = blockIdx.x;  // f * Px + kx
-  const uint32_t kx = (uint32_t)(line % px);
-  float2 *col = B + line * h;
-  for (uint32_t i = threadIdx.x; i < py; i += kFftThreads) {
-    float2 v = i < h ? col[i] : make_float2(0.f, 0.f);
-    lds[i] = c2(v.x, v.y);
-  }
-  __syncthreads();
-  lds_fft<U4>(lds, py, lgy, false);
-  // transfer function: FFT frequency order k / (P d) for k < P/2, (k - P) / (P d) otherwise
+  constexpr int UH = 4 * U4;  // rows per thread (py <= 4 * U4 * kFftThreads)
+  const uint32_t kx = blockIdx.x, t = threadIdx.x;
+  // FFT frequency order: k / (P d) for k < P/2, (k - P) / (P d) otherwise
   const double fx = (kx < px / 2 ? (double)kx : (double)kx - (double)px) * P.dfx;
   const bool ok_x = !P.band_limit || fabs(fx) <= P.lim_x;
-  for (uint32_t i = threadIdx.x; i < py; i += kFftThreads) {
-    const double fy = (i < py / 2 ? (double)i : (double)i - (double)py) * P.dfy;
-    const double f2 = fx * fx + fy * fy;
-    C2 hv = c2(0.f, 0.f);
-    if (ok_x && (!P.band_limit || fabs(fy) <= P.lim_y) && f2 < P.inv_lam2) {
-      // z sqrt(1/lambda^2 - f^2) = z/lambda - z f^2 / (1/lambda + sqrt(1/lambda^2 - f^2)),
-      // the first term reduced modulo 1 on the host
-      const double rev = P.z_rev_frac - P.z * f2 / (P.inv_lam + sqrt(P.inv_lam2 - f2));
-      const double fr = rev - floor(rev);
-      double sn, cs;
-      sincospi(2.0 * fr, &sn, &cs);
-      hv = c2((float)cs, (float)sn);
+  C2 Hr[UH];
+#pragma unroll
+  for (int u = 0; u < UH; ++u) {
+    const uint32_t i = t + (uint32_t)u * kFftThreads;
+    Hr[u] = c2(0.f, 0.f);
+    if (i < py) {
+      const double fy = (i < py / 2 ? (double)i : (double)i - (double)py) * P.dfy;
+      const double f2 = fx * fx + fy * fy;
+      if (ok_x && (!P.band_limit || fabs(fy) <= P.lim_y) && f2 < P.inv_lam2) {
+        // z sqrt(1/lambda^2 - f^2) = z/lambda - z f^2 / (1/lambda + sqrt(1/lambda^2 - f^2)),
+        // the first term reduced modulo 1 on the host
+        const double rev = P.z_rev_frac - P.z * f2 / (P.inv_lam + sqrt(P.inv_lam2 - f2));
+        const double fr = rev - floor(rev);
+        double sn, cs;
+        sincospi(2.0 * fr, &sn, &cs);
+        Hr[u] = c2((float)cs, (float)sn);
+      }
     }
-    lds[i] = mul(lds[i], hv);
   }
-  __syncthreads();
-  lds_fft<U4>(lds, py, lgy, true);
-  for (uint32_t i = threadIdx.x; i < h; i += kFftThreads) col[i] = make_float2(lds[i].x, lds[i].y);
+  for (uint32_t f = 0; f < nf; ++f) {
+    float2 *col = B + ((size_t)f * px + kx) * h;
+    for (uint32_t i = t; i < py; i += kFftThreads) {
+      float2 v = i < h ? col[i] : make_float2(0.f, 0.f);
+      lds[i] = c2(v.x, v.y);
+    }
+    __syncthreads();
+    lds_fft<U4>(lds, py, lgy, false, tw);
+#pragma unroll
+    for (int u = 0; u < UH; ++u) {
+      const uint32_t i = t + (uint32_t)u * kFftThreads;
+      if (i < py) lds[i] = mul(lds[i], Hr[u]);
+    }
+    __syncthreads();
+    lds_fft<U4>(lds, py, lgy, true, tw);
+    for (uint32_t i = t; i < h; i += kFftThreads) col[i] = make_float2(lds[i].x, lds[i].y);
+    __syncthreads();  // before the next field overwrites the buffer
+  }
+}
+
+// tw[m] = exp(-2 pi i m / n), m < n (FP64, rounded).
+__global__ void k_twiddles(float2 *tw, uint32_t n) {
+  const uint32_t m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n) return;
+  double sn, cs;
+  sincospi(2.0 * (double)m / (double)n, &sn, &cs);
+  tw[m] = make_float2((float)cs, (float)-sn);
 }
 
 // Inverse FFT of row (f, y) of A [nf][h][Px]; keep [0, w), scale -> out [nf][h][w].
 template <int U4>
 __global__ void __launch_bounds__(kFftThreads) k_ifft_rows(const float2 *A, float2 *out, uint32_t w, uint32_t h,
-                                                           uint32_t px, uint32_t lgx, float scale) {
+                                                           uint32_t px, uint32_t lgx, float scale,
+                                                           const float2 *tw) {
   extern __shared__ C2 lds[];
   const size_t row = blockIdx.x;
   const float2 *src = A + row * px;
@@ -205,7 +231,7 @@ __global__ void __launch_bounds__(kFftThreads) k_ifft_rows(const float2 *A, floa
     lds[i] = c2(v.x, v.y);
   }
   __syncthreads();
-  lds_fft<U4>(lds, px, lgx, true);
+  lds_fft<U4>(lds, px, lgx, true, tw);
   float2 *dst = out + row * w;
   for (uint32_t i = threadIdx.x; i < w; i += kFftThreads) dst[i] = make_float2(lds[i].x * scale, lds[i].y * scale);
 }
@@ -218,33 +244,34 @@ uint32_t log2u(uint32_t n) {
 
 template <int U4>
 void launch_rows(bool inv, const float2 *in, float2 *out, uint32_t nrows, uint32_t w, uint32_t h, uint32_t px,
-                 uint32_t lgx, float scale, hipStream_t st) {
+                 uint32_t lgx, float scale, const float2 *tw, hipStream_t st) {
   if (!inv)
-    hipLaunchKernelGGL(k_fft_rows<U4>, dim3(nrows), dim3(kFftThreads), px * sizeof(C2), st, in, out, w, h, px, lgx);
+    hipLaunchKernelGGL(k_fft_rows<U4>, dim3(nrows), dim3(kFftThreads), px * sizeof(C2), st, in, out, w, h, px, lgx,
+                       tw);
   else
     hipLaunchKernelGGL(k_ifft_rows<U4>, dim3(nrows), dim3(kFftThreads), px * sizeof(C2), st, in, out, w, h, px, lgx,
-                       scale);
+                       scale, tw);
 }
 
 void rows(bool inv, const float2 *in, float2 *out, uint32_t nrows, uint32_t w, uint32_t h, uint32_t px,
-          uint32_t lgx, float scale, hipStream_t st) {
-  if (px <= 4 * kFftThreads) launch_rows<1>(inv, in, out, nrows, w, h, px, lgx, scale, st);
-  else if (px <= 8 * kFftThreads) launch_rows<2>(inv, in, out, nrows, w, h, px, lgx, scale, st);
-  else if (px <= 16 * kFftThreads) launch_rows<4>(inv, in, out, nrows, w, h, px, lgx, scale, st);
-  else launch_rows<8>(inv, in, out, nrows, w, h, px, lgx, scale, st);
+          uint32_t lgx, float scale, const float2 *tw, hipStream_t st) {
+  if (px <= 4 * kFftThreads) launch_rows<1>(inv, in, out, nrows, w, h, px, lgx, scale, tw, st);
+  else if (px <= 8 * kFftThreads) launch_rows<2>(inv, in, out, nrows, w, h, px, lgx, scale, tw, st);
+  else if (px <= 16 * kFftThreads) launch_rows<4>(inv, in, out, nrows, w, h, px, lgx, scale, tw, st);
+  else launch_rows<8>(inv, in, out, nrows, w, h, px, lgx, scale, tw, st);
 }
 
-void columns(float2 *B, uint32_t ncols, uint32_t h, uint32_t px, uint32_t py, uint32_t lgy, const AsmParams &P,
-             hipStream_t st) {
+void columns(float2 *B, uint32_t nf, uint32_t h, uint32_t px, uint32_t py, uint32_t lgy, const AsmParams &P,
+             const float2 *tw, hipStream_t st) {
   const size_t sh = py * sizeof(C2);
   if (py <= 4 * kFftThreads)
-    hipLaunchKernelGGL(k_fft_columns<1>, dim3(ncols), dim3(kFftThreads), sh, st, B, h, px, py, lgy, P);
+    hipLaunchKernelGGL(k_fft_columns<1>, dim3(px), dim3(kFftThreads), sh, st, B, nf, h, px, py, lgy, P, tw);
   else if (py <= 8 * kFftThreads)
-    hipLaunchKernelGGL(k_fft_columns<2>, dim3(ncols), dim3(kFftThreads), sh, st, B, h, px, py, lgy, P);
+    hipLaunchKernelGGL(k_fft_columns<2>, dim3(px), dim3(kFftThreads), sh, st, B, nf, h, px, py, lgy, P, tw);
   else if (py <= 16 * kFftThreads)
-    hipLaunchKernelGGL(k_fft_columns<4>, dim3(ncols), dim3(kFftThreads), sh, st, B, h, px, py, lgy, P);
+    hipLaunchKernelGGL(k_fft_columns<4>, dim3(px), dim3(kFftThreads), sh, st, B, nf, h, px, py, lgy, P, tw);
   else
-    hipLaunchKernelGGL(k_fft_columns<8>, dim3(ncols), dim3(kFftThreads), sh, st, B, h, px, py, lgy, P);
+    hipLaunchKernelGGL(k_fft_columns<8>, dim3(px), dim3(kFftThreads), sh, st, B, nf, h, px, py, lgy, P, tw);
 }
 
 }  // namespace
@@ -255,16 +282,23 @@ uint32_t asm_padded(uint32_t n) {
   return p;
 }
 
-hipError_t launch_asm(const float2 *in, float2 *out, float2 *A, float2 *B, uint32_t nf, uint32_t w, uint32_t h,
-                      const AsmParams &P, hipStream_t st) {
+hipError_t launch_asm_twiddles(float2 *tw, uint32_t w, uint32_t h, hipStream_t st) {
+  const uint32_t px = asm_padded(w), py = asm_padded(h);
+  hipLaunchKernelGGL(k_twiddles, dim3((px + 255) / 256), dim3(256), 0, st, tw, px);
+  hipLaunchKernelGGL(k_twiddles, dim3((py + 255) / 256), dim3(256), 0, st, tw + px, py);
+  return hipGetLastError();
+}
+
+hipError_t launch_asm(const float2 *in, float2 *out, float2 *A, float2 *B, const float2 *tw, uint32_t nf,
+                      uint32_t w, uint32_t h, const AsmParams &P, hipStream_t st) {
   const uint32_t px = asm_padded(w), py = asm_padded(h);
   if (px > (uint32_t)kFftMax || py > (uint32_t)kFftMax || nf == 0 || w == 0 || h == 0) return hipErrorInvalidValue;
   const uint32_t lgx = log2u(px), lgy = log2u(py);
-  rows(false, in, A, nf * h, w, h, px, lgx, 1.0f, st);
+  rows(false, in, A, nf * h, w, h, px, lgx, 1.0f, tw, st);
   hipLaunchKernelGGL(k_transpose, dim3((px + 31) / 32, (h + 31) / 32, nf), dim3(256), 0, st, A, B, h, px);
-  columns(B, nf * px, h, px, py, lgy, P, st);
+  columns(B, nf, h, px, py, lgy, P, tw + px, st);
   hipLaunchKernelGGL(k_transpose, dim3((h + 31) / 32, (px + 31) / 32, nf), dim3(256), 0, st, B, A, px, h);
-  rows(true, A, out, nf * h, w, h, px, lgx, 1.0f / ((float)px * (float)py), st);
+  rows(true, A, out, nf * h, w, h, px, lgx, 1.0f / ((float)px * (float)py), tw, st);
   return hipGetLastError();
 }
 

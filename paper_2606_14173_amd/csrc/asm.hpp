@@ -20,10 +20,14 @@ struct AsmParams {
 // Padded length of one axis: the next power of two >= 2 n.
 uint32_t asm_padded(uint32_t n);
 
+// Twiddle tables for fields of w x h: tw[0, Px) for the rows, tw[Px, Px + Py)
+// for the columns (Px, Py: the padded sizes).
+hipError_t launch_asm_twiddles(float2 *tw, uint32_t w, uint32_t h, hipStream_t st);
+
 // nf fields in [nf][h][w] -> out (may alias in); A, B: scratch of
-// nf * h * asm_padded(w) complex64 each. hipErrorInvalidValue if a padded
-// axis exceeds 8192 or a size is zero.
-hipError_t launch_asm(const float2 *in, float2 *out, float2 *A, float2 *B, uint32_t nf, uint32_t w, uint32_t h,
-                      const AsmParams &P, hipStream_t st);
+// nf * h * asm_padded(w) complex64 each; tw: the tables above.
+// hipErrorInvalidValue if a padded axis exceeds 8192 or a size is zero.
+hipError_t launch_asm(const float2 *in, float2 *out, float2 *A, float2 *B, const float2 *tw, uint32_t nf,
+                      uint32_t w, uint32_t h, const AsmParams &P, hipStream_t st);
 
 }  // namespace hpt

@@ -1159,7 +1159,8 @@ hpt_status hpt_asm_propagate(hpt_ctx *C, const void *d_in, void *d_out, uint32_t
   P.band_limit = (flags & HPT_ASM_BAND_LIMIT) ? 1u : 0u;
   // scratch for a chunk of fields: two [h][Px] complex64 buffers per field
   const uint64_t per = 2ull * height * px * sizeof(float2);
-  float2 *A = nullptr, *B = nullptr;
+  float2 *A = nullptr, *B = nullptr, *W = nullptr;
+  const size_t tw_bytes = (size_t)(px + py) * sizeof(float2);  // twiddle tables
   uint32_t chunk = 0;
   {
     std::lock_guard<std::mutex> g(C->mu);
@@ -1175,13 +1176,18 @@ hpt_status hpt_asm_propagate(hpt_ctx *C, const void *d_in, void *d_out, uint32_t
       C->release(A, half);
       return fail(HPT_ENOMEM, "scratch allocation failed");
     }
+    if (C->alloc((void **)&W, tw_bytes) != hipSuccess) {
+      C->release(A, half);
+      C->release(B, half);
+      return fail(HPT_ENOMEM, "scratch allocation failed");
+    }
   }
-  hipError_t e = hipSuccess;
+  hipError_t e = launch_asm_twiddles(W, width, height, C->aux);
   const size_t field = (size_t)width * height;
   for (uint32_t f0 = 0; f0 < n_fields && e == hipSuccess; f0 += chunk) {
     uint32_t nf = std::min(chunk, n_fields - f0);
-    e = launch_asm((const float2 *)d_in + f0 * field, (float2 *)d_out + f0 * field, A, B, nf, width, height, P,
-                   C->aux);
+    e = launch_asm((const float2 *)d_in + f0 * field, (float2 *)d_out + f0 * field, A, B, W, nf, width, height,
+                   P, C->aux);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(C->aux);
   {
@@ -1189,6 +1195,7 @@ hpt_status hpt_asm_propagate(hpt_ctx *C, const void *d_in, void *d_out, uint32_t
     const size_t half = (size_t)chunk * height * px * sizeof(float2);
     C->release(A, half);
     C->release(B, half);
+    C->release(W, tw_bytes);
   }
   if (e != hipSuccess) return fail(HPT_EDEVICE, std::string("propagation failed: ") + hipGetErrorString(e));
   return HPT_OK;
