@@ -128,7 +128,7 @@ __device__ __forceinline__ bool tri_hit(const RayPre &r, F3 v0, F3 v1, F3 v2, fl
   float det = U + V + W;
   if (det == 0.f) return false;
   float T = r.Sz * (U * Az + V * Bz + W * Cz);
-  float t = T / det;
+  float t = T * __builtin_amdgcn_rcpf(det);  // hardware reciprocal (1 ulp)
   if (!(t > tmin) || t > tbest) return false;
   t_out = t;
   return true;
@@ -211,7 +211,7 @@ constexpr int32_t kDone = 0x7FFFFFFF;
 
 __device__ __forceinline__ void trav_init(Trav &T, F3 o, F3 d, float tmin, int32_t exclude, bool empty) {
   T.r = ray_pre(o, d);
-  T.tmin = tmin;
+  T.tmin = tmin * 1.0f + 0.0f;  // an arithmetic result: no canonicalisation in the loop
   T.exclude = exclude;
   T.node = empty ? kDone : 0;
   T.sp = 0;
@@ -249,10 +249,11 @@ __device__ __forceinline__ int32_t pop(const Stack &S, int &sp) {
 }
 
 // Advance this lane by one round: descend inner nodes, postponing the first
-// leaf reached and continuing with the next stack entry, until every active
-// lane of the wave holds a leaf or has nothing left to descend; then test
-// the postponed leaf (Aila and Laine's speculative "while-while", which keeps
-// lanes descending instead of idling while others look for a leaf). Leaves
+// leaf reached and continuing with the next stack entry, until all but at
+// most kTraceStragglers lanes of the wave hold a leaf or have nothing left to
+// descend; then test the postponed leaf (Aila and Laine's speculative
+// "while-while", which keeps lanes descending instead of idling while others
+// look for a leaf; lanes still descending carry on next round). Leaves
 // may be tested out of front-to-back order; the closest-hit and tie rules
 // make the result independent of the order. COUNT adds node visits and
 // primitive tests to nv / nt.
@@ -289,7 +290,10 @@ __device__ __forceinline__ void trav_step(Trav &T, GF4 N, GF4 P, const Stack &St
       node = pop(St, sp);
     }
     bool ready = has_leaf || node == kDone || node < 0;
-    if (__all(ready)) break;
+    // leave the descent once at most kTraceStragglers lanes are still
+    // looking for a leaf (waiting for all of them leaves most of the wave
+    // idle); the stragglers resume where they are in the next step
+    if (__popcll(__ballot(!ready)) <= kTraceStragglers) break;
   }
   if (has_leaf) {
     if (COUNT) nt += ((uint32_t)(~leaf) & 7u) + 1u;
