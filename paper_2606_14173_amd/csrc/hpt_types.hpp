@@ -33,12 +33,8 @@ constexpr double kTminD = 1e-7;
 enum Stage : uint32_t { STAGE_PREFIX = 0, STAGE_TAIL = 1 };
 enum UnitKind : uint32_t { UNIT_HOLO = 0, UNIT_CACHE = 1 };
 
-// Lanes per pixel in the accumulation: the next power of two >= T.
-__host__ __device__ inline uint32_t frame_group(uint32_t T) {
-  uint32_t g = 1;
-  while (g < T) g <<= 1;
-  return g;
-}
+// Lanes per pixel in the accumulation: one per frame.
+__host__ __device__ inline uint32_t frame_group(uint32_t T) { return T; }
 
 // Path events hashed into the signature (same codes as the FP64 reference).
 enum : uint32_t { EV_MIRROR = 1, EV_DIEL_REFL = 2, EV_DIEL_REFR = 3, EV_LAMBERT = 4, EV_GGX = 5,
@@ -144,8 +140,9 @@ struct BatchDev {
   // per path slot
   unsigned long long *s_sig;  // final signature (debug records and signature sums only)
   int32_t *s_first;           // first hit (debug records only)
-  float *r_amp, *r_rev, *r_fx, *r_fy;   // results consumed by the accumulation
-  double *r_r64;
+  float *r_amp, *r_fx, *r_fy;   // results consumed by the accumulation
+  float2 *r_cs;                 // unit phasor exp(i k r) (FP32 and split phase)
+  double2 *r_cs64;              // the same in FP64 (FP64 phase)
   uint32_t *r_tex;
   RayQueue Q[2];
   uint32_t *counters;        // [0], [1]: queue lengths; [2]: rays traced

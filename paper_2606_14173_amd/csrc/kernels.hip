@@ -501,7 +501,6 @@ __device__ __forceinline__ void image_point(const BatchDev &B, const RayQueue &Q
     qx = Q.x; qy = Q.y;
     u = Q.x / J.pitch + 0.5 * (double)J.width - 0.5;
     v = Q.y / J.pitch + 0.5 * (double)J.height - 0.5;
-    B.r_r64[slot] = r;
   } else {
     float alf = (float)al, bef = (float)be;
     float vz = sqrtf(1.0f - alf * alf - bef * bef);
@@ -532,7 +531,6 @@ __device__ __forceinline__ void image_point(const BatchDev &B, const RayQueue &Q
     r = rf; qx = Q.x; qy = Q.y;
     u = Q.x / (float)J.pitch + 0.5f * (float)J.width - 0.5f;
     v = Q.y / (float)J.pitch + 0.5f * (float)J.height - 0.5f;
-    B.r_r64[slot] = r;
   }
   double fu = floor(u), fv = floor(v);
   int64_t i0 = (int64_t)fu % (int64_t)J.grf_w, j0 = (int64_t)fv % (int64_t)J.grf_h;
@@ -541,7 +539,17 @@ __device__ __forceinline__ void image_point(const BatchDev &B, const RayQueue &Q
   B.r_tex[slot] = (uint32_t)i0 | ((uint32_t)j0 << 16);
   B.r_fx[slot] = (float)(u - fu);
   B.r_fy[slot] = (float)(v - fv);
-  B.r_rev[slot] = (float)rev;
+  // unit phasor exp(i k r) of the path (the same for all T frames), in the
+  // precision the accumulation of this mode sums in
+  if (J.phase_mode == HPT_PHASE_FP64) {
+    double sn, cs;
+    sincospi(2.0 * rev, &sn, &cs);
+    B.r_cs64[slot] = make_double2(cs, sn);
+  } else {
+    float sn, cs;
+    sincospif(2.0f * (float)rev, &sn, &cs);
+    B.r_cs[slot] = make_float2(cs, sn);
+  }
   st.wt = W;
   if (J.debug & 1u) {
     uint32_t p_local, s_local;
@@ -782,12 +790,13 @@ __global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
 }
 
 // ------------------------------------------------------------------ accumulate
-// s8-s9 and Path Reuse. A group of G = frame_group(T) consecutive lanes owns
-// one pixel of a unit; lane t of the group owns frame t. The group walks the
-// unit's samples in order; for each path it forms A W exp(i k r) / spp once
-// (the same value in every lane) and lane t multiplies it by the unit phasor
-// of frame t at Q, so the T frames of a texel are read by consecutive lanes
-// from consecutive addresses. Partial sums are added to the field at the end.
+// s8-s9 and Path Reuse. A group of T consecutive lanes owns one pixel of a
+// unit; lane t of the group owns frame t. The group walks the unit's samples
+// in order; for each path it forms A W exp(i k r) / spp from the amplitude and
+// the phasor the shading stored (the same value in every lane) and lane t
+// multiplies it by the unit phasor of frame t at Q, so the T frames of a
+// texel are read by consecutive lanes from consecutive addresses. Partial
+// sums are added to the field at the end.
 template <bool F64>
 __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
   uint32_t idx = xcd_block() * blockDim.x + threadIdx.x;
@@ -818,15 +827,11 @@ __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
     if (amp != 0.f) {
       R br, bi;
       if (F64) {
-        double x = B.r_r64[slot] * J.inv_lambda[U.ch];
-        double f = x - floor(x);
-        double sn, cs;
-        sincospi(2.0 * f, &sn, &cs);
-        br = (R)((double)amp * cs); bi = (R)((double)amp * sn);
+        const double2 cs = B.r_cs64[slot];
+        br = (R)((double)amp * cs.x); bi = (R)((double)amp * cs.y);
       } else {
-        float sn, cs;
-        sincospif(2.0f * B.r_rev[slot], &sn, &cs);
-        br = (R)(amp * cs); bi = (R)(amp * sn);
+        const float2 cs = B.r_cs[slot];
+        br = (R)(amp * cs.x); bi = (R)(amp * cs.y);
       }
       if (J.random_phase) {
         uint32_t tex = B.r_tex[slot];

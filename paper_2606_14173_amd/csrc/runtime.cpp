@@ -50,7 +50,7 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
 constexpr uint32_t kMaxUnitsPerBatch = 4096;
 // per path: final signature, first hit, results; per queue entry (two
 // queues): state (40 B), FP64 prefix ray (72 B), FP32 ray (32 B), hit (8 B)
-constexpr size_t kBytesPerPath = 8 + 4 + 4 * 4 + 8 + 4 + 2 * (40 + 72 + 32 + 8);
+constexpr size_t kBytesPerPath = 8 + 4 + 4 + 8 + 16 + 4 + 4 + 4 + 2 * (40 + 72 + 32 + 8);
 
 struct Scene {
   uint64_t id = 0;
@@ -562,8 +562,8 @@ hpt_status alloc_batch(hpt_ctx *C) {
   };
   bool ok = true;
   ok &= A((void **)&B.s_sig, 8ull * N) && A((void **)&B.s_first, 4ull * N);
-  ok &= A((void **)&B.r_amp, 4ull * N) && A((void **)&B.r_rev, 4ull * N) && A((void **)&B.r_fx, 4ull * N) &&
-        A((void **)&B.r_fy, 4ull * N) && A((void **)&B.r_r64, 8ull * N) && A((void **)&B.r_tex, 4ull * N);
+  ok &= A((void **)&B.r_amp, 4ull * N) && A((void **)&B.r_cs, 8ull * N) && A((void **)&B.r_cs64, 16ull * N) &&
+        A((void **)&B.r_fx, 4ull * N) && A((void **)&B.r_fy, 4ull * N) && A((void **)&B.r_tex, 4ull * N);
   for (int q = 0; q < 2 && ok; ++q) {
     RayQueue &Q = B.Q[q];
     ok &= A((void **)&Q.slot, 4ull * N) && A((void **)&Q.unit, 4ull * N) && A((void **)&Q.meta, 4ull * N) &&
