@@ -56,7 +56,7 @@ typedef struct hpt_ctx hpt_ctx;
  * bytes for scenes, caches, random-phase tables, fields and path state
  * (0 = 90% of the device's free memory). The batch buffers (path state and
  * traversal stack spill) take at most a quarter of it, which sets the batch
- * capacity in paths (a power of two, 2^16 to 2^24); EBUDGET if even 2^16
+ * capacity in paths (a power of two, 2^16 to 2^26); EBUDGET if even 2^16
  * paths do not fit. Spawns the scheduler thread. */
 hpt_status hpt_create(int device, uint64_t hbm_budget_bytes, hpt_ctx **out);
 /* Cancel queued work, wait for running batches, free everything. */

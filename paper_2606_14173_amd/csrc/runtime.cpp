@@ -624,12 +624,13 @@ hpt_status hpt_create(int device, uint64_t budget, hpt_ctx **out) {
   size_t free_b = 0, total_b = 0;
   (void)hipMemGetInfo(&free_b, &total_b);
   C->budget = budget ? budget : (uint64_t)(0.9 * (double)free_b);
-  // path capacity: a power of two, at most 2^24, batch buffers (path state
+  // path capacity: a power of two, at most 2^26 (larger batches mean fewer
+  // launches and fewer load-imbalanced launch tails), batch buffers (path state
   // and traversal stack spill) at most a quarter of the budget
   auto batch_bytes = [](uint32_t n) {
     return (uint64_t)n * kBytesPerPath + (uint64_t)kStackSpill * 4 * trace_grid(n) * trace_block();
   };
-  uint32_t c = 1u << 24;
+  uint32_t c = 1u << 26;
   while (c > (1u << 16) && batch_bytes(c) > C->budget / 4) c /= 2;
   if (batch_bytes(c) > C->budget) return fail(HPT_EBUDGET, "budget too small for path state");
   C->capacity = c;
