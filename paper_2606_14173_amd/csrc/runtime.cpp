@@ -48,9 +48,10 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
 }
 
 constexpr uint32_t kMaxUnitsPerBatch = 4096;
-// per path: final signature, first hit, results; per queue entry (two
-// queues): state (40 B), FP64 prefix ray (72 B), FP32 ray (32 B), hit (8 B)
-constexpr size_t kBytesPerPath = 8 + 4 + 4 + 8 + 16 + 4 + 4 + 4 + 2 * (40 + 72 + 32 + 8);
+// per path, in two sets: final signature, first hit, results; per queue
+// entry (two queues): state (40 B), FP64 prefix ray (72 B), FP32 ray (32 B),
+// hit (8 B)
+constexpr size_t kBytesPerPath = 2 * (8 + 4 + 4 + 8 + 16 + 4 + 4 + 4) + 2 * (40 + 72 + 32 + 8);
 
 struct Scene {
   uint64_t id = 0;
@@ -97,6 +98,7 @@ struct Job {
   size_t n_rec = 0, n_contrib = 0, n_sig = 0;
   std::vector<Unit> units;
   size_t next = 0, done = 0;
+  uint32_t in_flight = 0;     // units in the batch the GPU may still be running
   JobState state = JS_QUEUED;
   hpt_status status = HPT_OK;
   std::string err;
@@ -126,6 +128,9 @@ bool affine_inverse(const double *M, double *Ti) {
   return true;
 }
 
+// One unit of a job picked into a batch.
+struct Picked { Job *job; size_t unit; };
+
 }  // namespace
 
 struct hpt_ctx {
@@ -144,16 +149,42 @@ struct hpt_ctx {
   std::deque<Job *> queue;     // submitted, not yet admitted
   std::vector<Job *> running;  // admitted, units left
   std::vector<std::unique_ptr<Grf>> grfs;
-  // batch buffers
+  // batch buffers: queues, counters and stack spill shared by consecutive
+  // batches (one stream runs their tracing in order); per-path results and
+  // unit tables in two sets, so that batch k's accumulation (on its own
+  // stream) overlaps batch k+1's tracing
   std::vector<void *> batch_bufs;
   uint64_t batch_bytes = 0;   // device bytes of batch_bufs
   BatchDev batch{};
-  UnitDev *d_units = nullptr, *h_units = nullptr;
+  hipStream_t acc = nullptr;  // accumulation stream
+  static constexpr int kEvents = 80;
+  struct Slot {
+    unsigned long long *s_sig = nullptr;
+    int32_t *s_first = nullptr;
+    float *r_amp = nullptr, *r_fx = nullptr, *r_fy = nullptr;
+    float2 *r_cs = nullptr;
+    double2 *r_cs64 = nullptr;
+    uint32_t *r_tex = nullptr;
+    UnitDev *d_units = nullptr, *h_units = nullptr;
+    uint32_t *h_cnt = nullptr;            // pinned: the batch's counters after its last shading pass
+    unsigned long long *h_work = nullptr; // pinned: node visits, primitive tests
+    hipEvent_t ev0 = nullptr, ev_rg = nullptr, ev_shade = nullptr, ev_done = nullptr;
+    BatchDev B{};               // the batch's device view (for its accumulation)
+    bool has_f64 = false, has_f32 = false;
+    bool acc_pending = false;   // accumulation not enqueued yet
+    hipEvent_t pev[kEvents] = {};
+    int ne = 0;
+    int seg_kind[kEvents / 2] = {};
+    // the batch in this slot
+    std::vector<Picked> P;
+    uint32_t profile = 0, paths = 0;
+    bool has_holo = false, has_cache = false;
+    hpt_status launch_status = HPT_OK;
+    std::string err;
+  } slots[2];
   uint64_t batches = 0, jobs_done = 0;
   // profiling (guarded by mu; events used by the scheduler thread only)
   uint32_t profile = 0;
-  static constexpr int kEvents = 160;
-  hipEvent_t pev[kEvents] = {};
   hpt_kernel_time ktime[HPT_K_KINDS] = {};
   uint64_t node_visits = 0, prim_tests = 0;
 
@@ -341,8 +372,6 @@ hpt_status admit(hpt_ctx *C, Job *J) {
   return HPT_OK;
 }
 
-struct Picked { Job *job; size_t unit; };
-
 // Fill one batch round-robin over the running jobs.
 std::vector<Picked> pick_batch(hpt_ctx *C) {
   std::vector<Picked> out;
@@ -372,14 +401,55 @@ std::vector<Picked> pick_batch(hpt_ctx *C) {
   return out;
 }
 
-// Run one batch on the context stream (lock not held).
-hpt_status run_batch(hpt_ctx *C, const std::vector<Picked> &P, uint32_t profile, double &gpu_ms,
-                     uint64_t &rays, hpt_kernel_time *kt, uint64_t *work) {
+// Profiling helper: run `launch` on stream st, bracketed by an event pair of
+// slot L when profiling.
+template <class F>
+void timed_launch(hpt_ctx::Slot &L, int kind, hipStream_t st, hipError_t &e, F &&launch) {
+  if (e != hipSuccess) return;
+  if (L.profile && L.ne + 2 <= hpt_ctx::kEvents) {
+    e = hipEventRecord(L.pev[L.ne], st);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(L.pev[L.ne + 1], st);
+    L.seg_kind[L.ne / 2] = kind;
+    L.ne += 2;
+  } else {
+    e = launch();
+  }
+}
+
+// Enqueue the accumulation (or cache reduction) of slot si on the
+// accumulation stream, after the batch's last shading pass and after the
+// event `after` (the next batch's ray generation, so that the memory-bound
+// accumulation runs beside the ALU-bound tracing rather than beside the
+// memory-bound ray generation).
+hipError_t launch_accumulation(hpt_ctx *C, int si, hipEvent_t after) {
+  hpt_ctx::Slot &L = C->slots[si];
+  L.acc_pending = false;
+  hipError_t e = hipStreamWaitEvent(C->acc, L.ev_shade, 0);
+  if (e == hipSuccess && after) e = hipStreamWaitEvent(C->acc, after, 0);
+  const BatchDev &B = L.B;
+  if (L.has_holo)
+    timed_launch(L, HPT_K_ACCUMULATE, C->acc, e, [&] { return launch_accumulate(B, L.has_f64, L.has_f32, C->acc); });
+  if (L.has_cache) timed_launch(L, HPT_K_CACHE_REDUCE, C->acc, e, [&] { return launch_cache_reduce(B, C->acc); });
+  if (e == hipSuccess) e = hipEventRecord(L.ev_done, C->acc);
+  return e;
+}
+
+// Enqueue the batch of slot si (lock not held): raygen, then tracing and
+// shading on the context stream; the batch's counters are copied to pinned
+// memory after its last shading pass. The accumulation of the previous batch
+// (slot `prev`, if still pending) is enqueued behind this batch's ray
+// generation; this batch's own accumulation is left pending for the next
+// batch or for finish_batch. The slot's result set and unit table are free:
+// the batch that used them before has been finished.
+hpt_status launch_batch(hpt_ctx *C, int si, int prev) {
+  hpt_ctx::Slot &L = C->slots[si];
+  const std::vector<Picked> &P = L.P;
   uint32_t slot = 0, acc = 0, max_b = 0;
-  bool has_f64 = false, has_f32 = false, has_holo = false, has_cache = false;
+  L.has_holo = L.has_cache = L.has_f64 = L.has_f32 = false;
   for (size_t k = 0; k < P.size(); ++k) {
     const Unit &u = P[k].job->units[P[k].unit];
-    UnitDev &d = C->h_units[k];
+    UnitDev &d = L.h_units[k];
     d.kind = u.kind; d.ch = u.ch; d.p_lo = u.p_lo; d.p_n = u.p_n; d.s_lo = u.s_lo; d.s_n = u.s_n;
     d.slot_base = slot; d.acc_base = acc; d.job = P[k].job->dev; d.scene = P[k].job->scene->dev;
     const JobDev &J = P[k].job->host;
@@ -387,97 +457,147 @@ hpt_status run_batch(hpt_ctx *C, const std::vector<Picked> &P, uint32_t profile,
     acc += u.kind == UNIT_HOLO ? u.p_n * frame_group(J.T) : u.p_n;
     max_b = std::max(max_b, J.max_bounces);
     if (u.kind == UNIT_HOLO) {
-      has_holo = true;
-      if (J.phase_mode == HPT_PHASE_FP64) has_f64 = true; else has_f32 = true;
+      L.has_holo = true;
+      if (J.phase_mode == HPT_PHASE_FP64) L.has_f64 = true; else L.has_f32 = true;
     } else {
-      has_cache = true;
+      L.has_cache = true;
     }
   }
-  BatchDev B = C->batch;
+  L.paths = slot;
+  BatchDev &B = L.B;
+  B = C->batch;
+  B.s_sig = L.s_sig; B.s_first = L.s_first;
+  B.r_amp = L.r_amp; B.r_fx = L.r_fx; B.r_fy = L.r_fy; B.r_cs = L.r_cs; B.r_cs64 = L.r_cs64; B.r_tex = L.r_tex;
   B.scene_uniform = P.empty() ? nullptr : P[0].job->scene->dev;
   B.job_uniform = P.empty() ? nullptr : P[0].job->dev;
   for (auto &p : P) {
     if (p.job->scene->dev != B.scene_uniform) B.scene_uniform = nullptr;
     if (p.job->dev != B.job_uniform) B.job_uniform = nullptr;
   }
-  B.units = C->d_units;
+  B.units = L.d_units;
   B.n_units = (uint32_t)P.size();
   B.n_paths = slot;
   B.n_acc = acc;
-  // event pairs around each launch when profiling
-  int ne = 0;
-  int seg_kind[hpt_ctx::kEvents / 2];
+  const uint32_t profile = L.profile;
+  L.ne = 0;
   hipError_t e = hipSuccess;
-  auto timed = [&](int kind, auto &&launch) {
-    if (e != hipSuccess) return;
-    if (profile && ne + 2 <= hpt_ctx::kEvents) {
-      e = hipEventRecord(C->pev[ne], C->stream);
-      if (e == hipSuccess) e = launch();
-      if (e == hipSuccess) e = hipEventRecord(C->pev[ne + 1], C->stream);
-      seg_kind[ne / 2] = kind;
-      ne += 2;
-    } else {
-      e = launch();
-    }
-  };
-  e = hipMemcpyAsync(C->d_units, C->h_units, P.size() * sizeof(UnitDev), hipMemcpyHostToDevice, C->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(B.counters, 0, 8 * sizeof(uint32_t), C->stream);
-  if (e == hipSuccess)
-    e = hipMemsetAsync(B.claims, 0, 2 * kClaimClasses * kClaimStride * sizeof(uint32_t), C->stream);
-  if (e == hipSuccess && profile >= 2) e = hipMemsetAsync(B.work, 0, 2 * sizeof(unsigned long long), C->stream);
-  if (e == hipSuccess) e = hipEventRecord(C->ev0, C->stream);
-  timed(HPT_K_RAYGEN, [&] { return launch_raygen(B, C->stream); });
+  hipStream_t S = C->stream;
+  e = hipMemcpyAsync(L.d_units, L.h_units, P.size() * sizeof(UnitDev), hipMemcpyHostToDevice, S);
+  if (e == hipSuccess) e = hipMemsetAsync(B.counters, 0, 8 * sizeof(uint32_t), S);
+  if (e == hipSuccess) e = hipMemsetAsync(B.claims, 0, 2 * kClaimClasses * kClaimStride * sizeof(uint32_t), S);
+  if (e == hipSuccess && profile >= 2) e = hipMemsetAsync(B.work, 0, 2 * sizeof(unsigned long long), S);
+  if (e == hipSuccess) e = hipEventRecord(L.ev0, S);
+  timed_launch(L, HPT_K_RAYGEN, S, e, [&] { return launch_raygen(B, S); });
+  if (e == hipSuccess) e = hipEventRecord(L.ev_rg, S);
+  if (e == hipSuccess && prev >= 0 && C->slots[prev].acc_pending) e = launch_accumulation(C, prev, L.ev_rg);
   for (uint32_t it = 0; it <= max_b; ++it) {
     int q = (int)(it & 1u);
-    timed(HPT_K_TRACE, [&] { return launch_trace(B, q, profile >= 2, C->stream); });
-    timed(HPT_K_SHADE, [&] { return launch_shade(B, q, C->stream); });
+    timed_launch(L, HPT_K_TRACE, S, e, [&] { return launch_trace(B, q, profile >= 2, S); });
+    timed_launch(L, HPT_K_SHADE, S, e, [&] { return launch_shade(B, q, S); });
   }
-  if (has_holo) timed(HPT_K_ACCUMULATE, [&] { return launch_accumulate(B, has_f64, has_f32, C->stream); });
-  if (has_cache) timed(HPT_K_CACHE_REDUCE, [&] { return launch_cache_reduce(B, C->stream); });
-  if (e == hipSuccess) e = hipEventRecord(C->ev1, C->stream);
-  if (e == hipSuccess) e = hipEventSynchronize(C->ev1);
-  uint32_t cnt[4] = {0, 0, 0, 0};
-  if (e == hipSuccess) e = hipMemcpy(cnt, B.counters, sizeof(cnt), hipMemcpyDeviceToHost);
-  if (e == hipSuccess && profile >= 2) e = hipMemcpy(work, B.work, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemcpyAsync(L.h_cnt, B.counters, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, S);
+  if (e == hipSuccess && profile >= 2)
+    e = hipMemcpyAsync(L.h_work, B.work, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, S);
+  if (e == hipSuccess) e = hipEventRecord(L.ev_shade, S);
+  L.acc_pending = e == hipSuccess;
+  if (e != hipSuccess) {
+    (void)hipStreamSynchronize(S);
+    (void)hipStreamSynchronize(C->acc);
+    return fail(HPT_EDEVICE, std::string("batch failed: ") + hipGetErrorString(e));
+  }
+  return HPT_OK;
+}
+
+// Wait for the batch of slot si and collect its statistics (lock not held).
+hpt_status finish_batch(hpt_ctx *C, int si, double &gpu_ms, uint64_t &rays, hpt_kernel_time *kt,
+                        uint64_t *work) {
+  hpt_ctx::Slot &L = C->slots[si];
+  if (L.launch_status != HPT_OK) return L.launch_status;
+  hipError_t e = L.acc_pending ? launch_accumulation(C, si, nullptr) : hipSuccess;
+  if (e == hipSuccess) e = hipEventSynchronize(L.ev_done);
   float ms = 0.f;
-  if (e == hipSuccess) e = hipEventElapsedTime(&ms, C->ev0, C->ev1);
-  for (int k = 0; e == hipSuccess && k < ne; k += 2) {
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, L.ev0, L.ev_done);
+  for (int k = 0; e == hipSuccess && k < L.ne; k += 2) {
     float m = 0.f;
-    e = hipEventElapsedTime(&m, C->pev[k], C->pev[k + 1]);
-    hpt_kernel_time &t = kt[seg_kind[k / 2]];
+    e = hipEventElapsedTime(&m, L.pev[k], L.pev[k + 1]);
+    hpt_kernel_time &t = kt[L.seg_kind[k / 2]];
     t.launches++;
     t.total_ms += m;
   }
   if (e != hipSuccess) return fail(HPT_EDEVICE, std::string("batch failed: ") + hipGetErrorString(e));
-  kt[HPT_K_RAYGEN].items += profile ? slot : 0;
-  kt[HPT_K_TRACE].items += profile ? cnt[2] : 0;
-  kt[HPT_K_SHADE].items += profile ? cnt[2] : 0;
-  kt[HPT_K_ACCUMULATE].items += (profile && has_holo) ? slot : 0;
-  kt[HPT_K_CACHE_REDUCE].items += (profile && has_cache) ? slot : 0;
+  const uint32_t nr = L.h_cnt[2];
+  if (L.profile >= 2) { work[0] = L.h_work[0]; work[1] = L.h_work[1]; }
+  kt[HPT_K_RAYGEN].items += L.profile ? L.paths : 0;
+  kt[HPT_K_TRACE].items += L.profile ? nr : 0;
+  kt[HPT_K_SHADE].items += L.profile ? nr : 0;
+  kt[HPT_K_ACCUMULATE].items += (L.profile && L.has_holo) ? L.paths : 0;
+  kt[HPT_K_CACHE_REDUCE].items += (L.profile && L.has_cache) ? L.paths : 0;
   gpu_ms = ms;
-  rays = cnt[2];
+  rays = nr;
   return HPT_OK;
 }
 
+// Account a finished batch and retire the jobs it completed (lock held).
+void account_batch(hpt_ctx *C, int si, hpt_status s, const std::string &err, double gpu_ms, uint64_t rays,
+                   const hpt_kernel_time *kt, const uint64_t *work) {
+  const std::vector<Picked> &P = C->slots[si].P;
+  C->batches++;
+  for (int k = 0; k < HPT_K_KINDS; ++k) {
+    C->ktime[k].launches += kt[k].launches;
+    C->ktime[k].items += kt[k].items;
+    C->ktime[k].total_ms += kt[k].total_ms;
+  }
+  C->node_visits += work[0];
+  C->prim_tests += work[1];
+  uint64_t total = 0;
+  for (auto &p : P) total += (uint64_t)p.job->units[p.unit].p_n * p.job->units[p.unit].s_n;
+  for (auto &p : P) {
+    Job *J = p.job;
+    uint64_t np = (uint64_t)J->units[p.unit].p_n * J->units[p.unit].s_n;
+    J->stats.paths += np;
+    J->stats.rays += total ? rays * np / total : 0;
+    J->stats.trace_gpu_ms += total ? gpu_ms * (double)np / (double)total : 0.0;
+    J->done++;
+    J->in_flight--;
+  }
+  std::vector<Job *> seen;
+  for (auto &p : P) {
+    Job *J = p.job;
+    if (std::find(seen.begin(), seen.end(), J) != seen.end()) continue;
+    seen.push_back(J);
+    J->stats.batches++;
+    if (J->state != JS_RUNNING) continue;
+    if (s != HPT_OK) retire(C, J, JS_FAILED, s, err);
+    else if (J->done == J->units.size()) retire(C, J, JS_DONE, HPT_OK, "");
+  }
+  C->slots[si].P.clear();
+}
+
+// The scheduler thread: admission, batch packing and the batch pipeline
+// (batch k+1 is enqueued before batch k is waited for, so the GPU always has
+// the next batch queued and batch k's accumulation overlaps batch k+1's
+// tracing).
 void scheduler(hpt_ctx *C) {
   (void)hipSetDevice(C->device);
   std::unique_lock<std::mutex> lk(C->mu);
+  int cur = 0, inflight = -1;
   for (;;) {
     C->cv.wait(lk, [&] {
-      if (C->stop) return true;
+      if (C->stop || inflight >= 0) return true;
       for (Job *J : C->running)
         if (J->cancel || J->next < J->units.size()) return true;
       return !C->queue.empty();
     });
-    if (C->stop) break;
-    // cancellations at the batch boundary
+    if (C->stop && inflight < 0) break;
+    // cancellations at the batch boundary; a job with units in flight is
+    // retired once its batch has finished
     for (size_t k = 0; k < C->running.size();) {
       Job *J = C->running[k];
-      if (J->cancel) retire(C, J, JS_CANCELED, HPT_ECANCELED, "cancelled");
+      if (J->cancel && J->in_flight == 0) retire(C, J, JS_CANCELED, HPT_ECANCELED, "cancelled");
       else ++k;
     }
     // admission in arrival order while memory allows
-    while (!C->queue.empty()) {
+    while (!C->stop && !C->queue.empty()) {
       Job *J = C->queue.front();
       if (J->cancel) {
         C->queue.pop_front();
@@ -500,46 +620,37 @@ void scheduler(hpt_ctx *C) {
         C->cv.notify_all();
       }
     }
-    std::vector<Picked> P = pick_batch(C);
-    if (P.empty()) continue;
-    for (auto &p : P)
-      if (!p.job->started) { p.job->started = true; p.job->t_start = Clock::now(); }
-    uint32_t profile = C->profile;
-    lk.unlock();
-    double gpu_ms = 0.0;
-    uint64_t rays = 0, work[2] = {0, 0};
-    hpt_kernel_time kt[HPT_K_KINDS] = {};
-    hpt_status s = run_batch(C, P, profile, gpu_ms, rays, kt, work);
-    std::string err = s == HPT_OK ? std::string() : g_err;
-    lk.lock();
-    C->batches++;
-    for (int k = 0; k < HPT_K_KINDS; ++k) {
-      C->ktime[k].launches += kt[k].launches;
-      C->ktime[k].items += kt[k].items;
-      C->ktime[k].total_ms += kt[k].total_ms;
+    int launched = -1;
+    if (!C->stop) {
+      std::vector<Picked> P = pick_batch(C);
+      if (!P.empty()) {
+        for (auto &p : P) {
+          if (!p.job->started) { p.job->started = true; p.job->t_start = Clock::now(); }
+          p.job->in_flight++;
+        }
+        hpt_ctx::Slot &L = C->slots[cur];
+        L.P = std::move(P);
+        L.profile = C->profile;
+        lk.unlock();
+        L.launch_status = launch_batch(C, cur, inflight);
+        L.err = L.launch_status == HPT_OK ? std::string() : g_err;
+        lk.lock();
+        launched = cur;
+        cur ^= 1;
+      }
     }
-    C->node_visits += work[0];
-    C->prim_tests += work[1];
-    uint64_t total = 0;
-    for (auto &p : P) total += (uint64_t)p.job->units[p.unit].p_n * p.job->units[p.unit].s_n;
-    for (auto &p : P) {
-      Job *J = p.job;
-      uint64_t np = (uint64_t)J->units[p.unit].p_n * J->units[p.unit].s_n;
-      J->stats.paths += np;
-      J->stats.rays += total ? rays * np / total : 0;
-      J->stats.trace_gpu_ms += total ? gpu_ms * (double)np / (double)total : 0.0;
-      J->done++;
+    if (inflight >= 0) {
+      lk.unlock();
+      double gpu_ms = 0.0;
+      uint64_t rays = 0, work[2] = {0, 0};
+      hpt_kernel_time kt[HPT_K_KINDS] = {};
+      hpt_status s = finish_batch(C, inflight, gpu_ms, rays, kt, work);
+      std::string err = s == HPT_OK ? std::string() : (C->slots[inflight].launch_status != HPT_OK
+                                                            ? C->slots[inflight].err : g_err);
+      lk.lock();
+      account_batch(C, inflight, s, err, gpu_ms, rays, kt, work);
     }
-    std::vector<Job *> seen;
-    for (auto &p : P) {
-      Job *J = p.job;
-      if (std::find(seen.begin(), seen.end(), J) != seen.end()) continue;
-      seen.push_back(J);
-      J->stats.batches++;
-      if (J->state != JS_RUNNING) continue;
-      if (s != HPT_OK) retire(C, J, JS_FAILED, s, err);
-      else if (J->done == J->units.size()) retire(C, J, JS_DONE, HPT_OK, "");
-    }
+    inflight = launched;
   }
   // drain: everything still queued or running is cancelled
   for (Job *J : C->queue) {
@@ -561,9 +672,12 @@ hpt_status alloc_batch(hpt_ctx *C) {
     return true;
   };
   bool ok = true;
-  ok &= A((void **)&B.s_sig, 8ull * N) && A((void **)&B.s_first, 4ull * N);
-  ok &= A((void **)&B.r_amp, 4ull * N) && A((void **)&B.r_cs, 8ull * N) && A((void **)&B.r_cs64, 16ull * N) &&
-        A((void **)&B.r_fx, 4ull * N) && A((void **)&B.r_fy, 4ull * N) && A((void **)&B.r_tex, 4ull * N);
+  for (auto &L : C->slots) {
+    ok &= A((void **)&L.s_sig, 8ull * N) && A((void **)&L.s_first, 4ull * N);
+    ok &= A((void **)&L.r_amp, 4ull * N) && A((void **)&L.r_cs, 8ull * N) && A((void **)&L.r_cs64, 16ull * N) &&
+          A((void **)&L.r_fx, 4ull * N) && A((void **)&L.r_fy, 4ull * N) && A((void **)&L.r_tex, 4ull * N);
+    ok &= A((void **)&L.d_units, kMaxUnitsPerBatch * sizeof(UnitDev));
+  }
   for (int q = 0; q < 2 && ok; ++q) {
     RayQueue &Q = B.Q[q];
     ok &= A((void **)&Q.slot, 4ull * N) && A((void **)&Q.unit, 4ull * N) && A((void **)&Q.meta, 4ull * N) &&
@@ -580,11 +694,19 @@ hpt_status alloc_batch(hpt_ctx *C) {
   ok &= A((void **)&B.work, 64);
   B.spill_threads = trace_grid(N) * trace_block();
   ok &= A((void **)&B.stack_spill, (size_t)kStackSpill * B.spill_threads * sizeof(int32_t));
-  ok &= A((void **)&C->d_units, kMaxUnitsPerBatch * sizeof(UnitDev));
   if (!ok) return fail(HPT_ENOMEM, "batch buffer allocation failed");
-  if (hipHostMalloc((void **)&C->h_units, kMaxUnitsPerBatch * sizeof(UnitDev), hipHostMallocDefault) !=
-      hipSuccess)
-    return fail(HPT_ENOMEM, "pinned unit table allocation failed");
+  for (auto &L : C->slots) {
+    if (hipHostMalloc((void **)&L.h_units, kMaxUnitsPerBatch * sizeof(UnitDev), hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostMalloc((void **)&L.h_cnt, 4 * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&L.h_work, 2 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
+      return fail(HPT_ENOMEM, "pinned batch table allocation failed");
+    if (hipEventCreate(&L.ev0) != hipSuccess || hipEventCreate(&L.ev_rg) != hipSuccess ||
+        hipEventCreate(&L.ev_shade) != hipSuccess || hipEventCreate(&L.ev_done) != hipSuccess)
+      return fail(HPT_EDEVICE, "event creation failed");
+    for (auto &ev : L.pev)
+      if (hipEventCreate(&ev) != hipSuccess) return fail(HPT_EDEVICE, "event creation failed");
+  }
   return HPT_OK;
 }
 
@@ -635,11 +757,9 @@ hpt_status hpt_create(int device, uint64_t budget, hpt_ctx **out) {
   if (batch_bytes(c) > C->budget) return fail(HPT_EBUDGET, "budget too small for path state");
   C->capacity = c;
   if (hipStreamCreateWithFlags(&C->stream, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&C->aux, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreate(&C->ev0) != hipSuccess || hipEventCreate(&C->ev1) != hipSuccess)
-    return fail(HPT_EDEVICE, "stream/event creation failed");
-  for (int k = 0; k < hpt_ctx::kEvents; ++k)
-    if (hipEventCreate(&C->pev[k]) != hipSuccess) return fail(HPT_EDEVICE, "event creation failed");
+      hipStreamCreateWithFlags(&C->acc, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&C->aux, hipStreamNonBlocking) != hipSuccess)
+    return fail(HPT_EDEVICE, "stream creation failed");
   hpt_status s = alloc_batch(C.get());
   if (s != HPT_OK) {
     for (void *p : C->batch_bufs) (void)hipFree(p);
@@ -662,6 +782,7 @@ void hpt_destroy(hpt_ctx *C) {
   if (C->worker.joinable()) C->worker.join();
   (void)hipSetDevice(C->device);
   (void)hipStreamSynchronize(C->stream);
+  (void)hipStreamSynchronize(C->acc);
   for (auto &kv : C->jobs) free_job_buffers(C, kv.second.get());
   for (auto &g : C->grfs) (void)hipFree(g->d);
   for (auto &kv : C->scenes) {
@@ -670,12 +791,17 @@ void hpt_destroy(hpt_ctx *C) {
     (void)hipFree(kv.second->cache);
   }
   for (void *p : C->batch_bufs) (void)hipFree(p);
-  if (C->h_units) (void)hipHostFree(C->h_units);
-  (void)hipEventDestroy(C->ev0);
-  (void)hipEventDestroy(C->ev1);
-  for (int k = 0; k < hpt_ctx::kEvents; ++k)
-    if (C->pev[k]) (void)hipEventDestroy(C->pev[k]);
+  for (auto &L : C->slots) {
+    if (L.h_units) (void)hipHostFree(L.h_units);
+    if (L.h_cnt) (void)hipHostFree(L.h_cnt);
+    if (L.h_work) (void)hipHostFree(L.h_work);
+    for (hipEvent_t ev : {L.ev0, L.ev_rg, L.ev_shade, L.ev_done})
+      if (ev) (void)hipEventDestroy(ev);
+    for (hipEvent_t ev : L.pev)
+      if (ev) (void)hipEventDestroy(ev);
+  }
   (void)hipStreamDestroy(C->stream);
+  (void)hipStreamDestroy(C->acc);
   (void)hipStreamDestroy(C->aux);
   delete C;
 }
