@@ -797,6 +797,8 @@ __global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
 // multiplies it by the unit phasor of frame t at Q, so the T frames of a
 // texel are read by consecutive lanes from consecutive addresses. Partial
 // sums are added to the field at the end.
+constexpr uint32_t kAccBatch = 4;  // paths whose loads are in flight together
+
 template <bool F64>
 __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
   uint32_t idx = xcd_block() * blockDim.x + threadIdx.x;
@@ -819,40 +821,71 @@ __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
   R ar = 0, ai = 0;
   unsigned long long sigsum = 0;
   const bool dbg_c = (J.debug & 2u) != 0, dbg_s = (J.debug & 4u) != 0 && t == 0;
-  for (uint32_t s = 0; s < U.s_n; ++s) {
-    uint32_t slot = U.slot_base + p_local * U.s_n + s;
-    if (dbg_s) sigsum += B.s_sig[slot];
-    float amp = B.r_amp[slot];
-    R cr = 0, ci = 0;
-    if (amp != 0.f) {
-      R br, bi;
+  const bool rp = J.random_phase != 0;
+  const uint32_t n = U.s_n, slot0 = U.slot_base + p_local * n;
+  // Paths are taken kAccBatch at a time: the records of all of them are
+  // requested, then the table corners of all of them, before the first is
+  // used, so a wave has several gathers in flight instead of two dependent
+  // round trips per path. The sum still runs in sample order.
+  for (uint32_t k0 = 0; k0 < n; k0 += kAccBatch) {
+    uint32_t tex[kAccBatch];
+    float amp[kAccBatch], fx[kAccBatch], fy[kAccBatch];
+    R csr[kAccBatch], csi[kAccBatch];
+    float2 qa[kAccBatch], qb[kAccBatch], qc[kAccBatch], qd[kAccBatch];
+#pragma unroll
+    for (uint32_t u = 0; u < kAccBatch; ++u) {
+      const bool v = k0 + u < n;
+      const uint32_t slot = slot0 + k0 + u;
+      amp[u] = v ? B.r_amp[slot] : 0.f;
       if (F64) {
-        const double2 cs = B.r_cs64[slot];
-        br = (R)((double)amp * cs.x); bi = (R)((double)amp * cs.y);
+        const double2 cs = v ? B.r_cs64[slot] : make_double2(0.0, 0.0);
+        csr[u] = (R)cs.x; csi[u] = (R)cs.y;
       } else {
-        const float2 cs = B.r_cs[slot];
-        br = (R)(amp * cs.x); bi = (R)(amp * cs.y);
+        const float2 cs = v ? B.r_cs[slot] : make_float2(0.f, 0.f);
+        csr[u] = (R)cs.x; csi[u] = (R)cs.y;
       }
-      if (J.random_phase) {
-        uint32_t tex = B.r_tex[slot];
-        uint32_t i0 = tex & 0xFFFFu, j0 = tex >> 16;
-        uint32_t i1 = i0 + 1 == gw ? 0 : i0 + 1, j1 = j0 + 1 == gh ? 0 : j0 + 1;
-        float fx = B.r_fx[slot], fy = B.r_fy[slot];
-        float2 a = G2[((size_t)j0 * gw + i0) * T], bq = G2[((size_t)j0 * gw + i1) * T];
-        float2 c = G2[((size_t)j1 * gw + i0) * T], d = G2[((size_t)j1 * gw + i1) * T];
-        float w00 = (1.f - fx) * (1.f - fy), w10 = fx * (1.f - fy), w01 = (1.f - fx) * fy, w11 = fx * fy;
-        float zr = w00 * a.x + w10 * bq.x + w01 * c.x + w11 * d.x;
-        float zi = w00 * a.y + w10 * bq.y + w01 * c.y + w11 * d.y;
-        float m2 = zr * zr + zi * zi;
-        float inv = m2 > 0.f ? rsqrtf(m2) : 0.f;
-        R pr = m2 > 0.f ? (R)(zr * inv) : (R)1, pi = (R)(zi * inv);
-        cr = br * pr - bi * pi; ci = br * pi + bi * pr;
-      } else {
-        cr = br; ci = bi;
-      }
-      ar += cr; ai += ci;
+      tex[u] = v && rp ? B.r_tex[slot] : 0u;
+      fx[u] = v && rp ? B.r_fx[slot] : 0.f;
+      fy[u] = v && rp ? B.r_fy[slot] : 0.f;
     }
-    if (dbg_c) J.contrib[rec_index(J, U, p_local, s) * T + t] = make_float2((float)cr, (float)ci);
+#pragma unroll
+    for (uint32_t u = 0; u < kAccBatch; ++u) {
+      if (rp && amp[u] != 0.f) {  // the texel is written only for paths with an image point
+        const uint32_t i0 = tex[u] & 0xFFFFu, j0 = tex[u] >> 16;
+        const uint32_t i1 = i0 + 1 == gw ? 0 : i0 + 1, j1 = j0 + 1 == gh ? 0 : j0 + 1;
+        qa[u] = G2[((size_t)j0 * gw + i0) * T]; qb[u] = G2[((size_t)j0 * gw + i1) * T];
+        qc[u] = G2[((size_t)j1 * gw + i0) * T]; qd[u] = G2[((size_t)j1 * gw + i1) * T];
+      }
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kAccBatch; ++u) {
+      const uint32_t s = k0 + u;
+      if (s >= n) break;
+      if (dbg_s) sigsum += B.s_sig[slot0 + s];
+      R cr = 0, ci = 0;
+      if (amp[u] != 0.f) {
+        R br, bi;
+        if (F64) {
+          br = (R)((double)amp[u] * csr[u]); bi = (R)((double)amp[u] * csi[u]);
+        } else {
+          br = (R)(amp[u] * csr[u]); bi = (R)(amp[u] * csi[u]);
+        }
+        if (rp) {
+          const float x = fx[u], y = fy[u];
+          const float w00 = (1.f - x) * (1.f - y), w10 = x * (1.f - y), w01 = (1.f - x) * y, w11 = x * y;
+          const float zr = w00 * qa[u].x + w10 * qb[u].x + w01 * qc[u].x + w11 * qd[u].x;
+          const float zi = w00 * qa[u].y + w10 * qb[u].y + w01 * qc[u].y + w11 * qd[u].y;
+          const float m2 = zr * zr + zi * zi;
+          const float inv = m2 > 0.f ? rsqrtf(m2) : 0.f;
+          const R pr = m2 > 0.f ? (R)(zr * inv) : (R)1, pi = (R)(zi * inv);
+          cr = br * pr - bi * pi; ci = br * pi + bi * pr;
+        } else {
+          cr = br; ci = bi;
+        }
+        ar += cr; ai += ci;
+      }
+      if (dbg_c) J.contrib[rec_index(J, U, p_local, s) * T + t] = make_float2((float)cr, (float)ci);
+    }
   }
   float2 *F = J.field + ((size_t)U.ch * T + t) * plane + (size_t)cy * J.crop_w + cx;
   float2 v = *F;

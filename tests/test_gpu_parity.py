@@ -131,6 +131,22 @@ def test_ragged_sizes(ctx, shape):
     assert r["ok"]
 
 
+@pytest.mark.parametrize("T,spp", [(16, 37), (17, 256), (33, 300), (64, 7)])
+def test_accumulation_group_sizes(ctx, T, spp):
+    """Frame counts that do not divide the wave (pixels whose lanes straddle
+    two waves), sample counts that are not multiples of the accumulation's
+    batch of four, and 300 samples (two sample ranges of one pixel, summed by
+    two accumulation passes): the field against the oracle and against the
+    library's own per-path contributions."""
+    sc = scenes.scene_tiny(0)
+    job = jobs.job_for_config(0, width=64, height=64, crop=(20, 22, 9, 7), T=T, spp=spp,
+                              grf_w=96, grf_h=80, grf_seed=9, phase_mode=jobs.PHASE_SPLIT)
+    sid = ctx.upload_scene(sc)
+    r = compare(*gpu_run(ctx, sid, job), *oracle_run(sc, job))
+    _say("T%d spp%d" % (T, spp), r)
+    assert r["ok"] and r["self_err"] < 1e-5
+
+
 def test_invalid_jobs_rejected(ctx):
     import paper_2606_14173_amd as hpt
     sc = scenes.scene_tiny(0)
