@@ -120,26 +120,17 @@ __device__ __forceinline__ void load_state(const RayQueue &Q, uint32_t i, RaySta
   }
 }
 
-// Entry k of queue Q for the continuing ray r (read-only words from entry
-// r.i of the source queue S, or from ka, kb, al, be when S is null).
-__device__ __forceinline__ void store_state(const RayQueue &Q, uint32_t k, const RayState &r, const RayQueue *S,
-                                            uint32_t ka, uint32_t kb, double al, double be, F3 o, F3 d,
-                                            int32_t excl) {
-  const bool prefix = (r.meta & 1u) == STAGE_PREFIX;
-  if (S) {
-    ka = S->ka[r.i]; kb = S->kb[r.i];
-    if (prefix) { al = S->al[r.i]; be = S->be[r.i]; }
-  }
-  Q.slot[k] = r.slot; Q.unit[k] = r.unit; Q.meta[k] = r.meta; Q.ka[k] = ka; Q.kb[k] = kb;
-  Q.sig[k] = r.sig;
-  Q.bpre[k] = r.bpre; Q.wt[k] = r.wt; Q.beta[k] = r.beta; Q.L[k] = r.L;
-  if (prefix) {
-    Q.ox[k] = r.o.x; Q.oy[k] = r.o.y; Q.oz[k] = r.o.z;
-    Q.dx[k] = r.d.x; Q.dy[k] = r.d.y; Q.dz[k] = r.d.z;
-    Q.ell[k] = r.ell; Q.al[k] = al; Q.be[k] = be;
-  }
+// Entry k of the first queue: what the first shading pass cannot rebuild
+// (slot, unit, key words, cone direction) and the FP32 ray. The start state
+// (signature, throughputs, medium, stage) is the same for every path and the
+// FP64 primary ray is a function of the pixel and the cone direction, so the
+// first shading pass rebuilds both (load_first) instead of reading them.
+__device__ __forceinline__ void store_first(const RayQueue &Q, uint32_t k, const RayState &r, uint32_t ka,
+                                            uint32_t kb, double al, double be, F3 o, F3 d) {
+  Q.slot[k] = r.slot; Q.unit[k] = r.unit; Q.ka[k] = ka; Q.kb[k] = kb;
+  if ((r.meta & 1u) == STAGE_PREFIX) { Q.al[k] = al; Q.be[k] = be; }
   Q.ray[2 * k] = make_float4(o.x, o.y, o.z, kTmin);
-  Q.ray[2 * k + 1] = make_float4(d.x, d.y, d.z, __int_as_float(excl));
+  Q.ray[2 * k + 1] = make_float4(d.x, d.y, d.z, __int_as_float(-1));
 }
 
 // ------------------------------------------------------------------ raygen
@@ -150,6 +141,46 @@ __device__ __forceinline__ void store_state(const RayQueue &Q, uint32_t k, const
 // rays of similar origin and direction. The queue order changes nothing but
 // the traversal's coherence: every path keeps its slot.
 constexpr int kRaygenBlock = 1024;
+
+// s1-s2: the primary ray of SLM pixel (px, py) with cone direction cosines
+// (al, be): origin at the pixel, direction (al, be, sqrt(1 - al^2 - be^2)),
+// both carried into world space by the inverse of T (Eq. 3). FP32 phase
+// builds it in FP32 (al, be hold FP32 values there).
+__device__ __forceinline__ void primary_ray(const JobDev &J, uint32_t px, uint32_t py, double al, double be,
+                                            D3 &O, D3 &d) {
+  D3 xp = {((double)px + 0.5 - 0.5 * (double)J.width) * J.pitch,
+           ((double)py + 0.5 - 0.5 * (double)J.height) * J.pitch, 0.0};
+  if (J.phase_mode != HPT_PHASE_FP32) {
+    D3 v = {al, be, sqrt(1.0 - al * al - be * be)};
+    if (J.identity_T) {
+      O = xp;
+      d = normalize(v);
+    } else {
+      const double *M = J.Ti;
+      O = {M[0] * xp.x + M[1] * xp.y + M[2] * xp.z + M[3], M[4] * xp.x + M[5] * xp.y + M[6] * xp.z + M[7],
+           M[8] * xp.x + M[9] * xp.y + M[10] * xp.z + M[11]};
+      d = normalize(D3{M[0] * v.x + M[1] * v.y + M[2] * v.z, M[4] * v.x + M[5] * v.y + M[6] * v.z,
+                       M[8] * v.x + M[9] * v.y + M[10] * v.z});
+    }
+  } else {
+    const float alf = (float)al, bef = (float)be;
+    F3 v = f3(alf, bef, sqrtf(1.0f - alf * alf - bef * bef));
+    F3 O32, d32;
+    if (J.identity_T) {
+      O32 = to_f(xp);
+      d32 = normalize(v);
+    } else {
+      float M[12];
+      for (int k = 0; k < 12; ++k) M[k] = (float)J.Ti[k];
+      F3 x = to_f(xp);
+      O32 = f3(M[0] * x.x + M[1] * x.y + M[2] * x.z + M[3], M[4] * x.x + M[5] * x.y + M[6] * x.z + M[7],
+               M[8] * x.x + M[9] * x.y + M[10] * x.z + M[11]);
+      d32 = normalize(f3(M[0] * v.x + M[1] * v.y + M[2] * v.z, M[4] * v.x + M[5] * v.y + M[6] * v.z,
+                         M[8] * v.x + M[9] * v.y + M[10] * v.z));
+    }
+    O = to_d(O32); d = to_d(d32);
+  }
+}
 
 // s1-s2 for path slot i (or a cache path): its state, read-only key words,
 // FP32 ray and direction-sort key.
@@ -178,9 +209,6 @@ __device__ __forceinline__ void gen_path(const BatchDev &B, uint32_t i, RayState
     ska = gpix;
     skb = smp;
     U4 w = philox(gpix, smp, 0u, comp << 16, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
-    D3 xp = {((double)px + 0.5 - 0.5 * (double)J.width) * J.pitch,
-             ((double)py + 0.5 - 0.5 * (double)J.height) * J.pitch, 0.0};
-    D3 O, d;
     double al, be;
     if (J.phase_mode != HPT_PHASE_FP32) {
       // s1: direction cosines uniform on the disc of radius lambda/(2d)
@@ -188,39 +216,14 @@ __device__ __forceinline__ void gen_path(const BatchDev &B, uint32_t i, RayState
       double sn, cs;
       sincospi(2.0 * ud(w.y), &sn, &cs);
       al = rad * cs; be = rad * sn;
-      D3 v = {al, be, sqrt(1.0 - al * al - be * be)};
-      if (J.identity_T) {
-        O = xp;
-        d = normalize(v);
-      } else {  // s2: into world space through the inverse of T (Eq. 3)
-        const double *M = J.Ti;
-        O = {M[0] * xp.x + M[1] * xp.y + M[2] * xp.z + M[3], M[4] * xp.x + M[5] * xp.y + M[6] * xp.z + M[7],
-             M[8] * xp.x + M[9] * xp.y + M[10] * xp.z + M[11]};
-        d = normalize(D3{M[0] * v.x + M[1] * v.y + M[2] * v.z, M[4] * v.x + M[5] * v.y + M[6] * v.z,
-                         M[8] * v.x + M[9] * v.y + M[10] * v.z});
-      }
     } else {
       float rad = J.s_cone_f[U.ch] * sqrtf(uf(w.x));
       float sn, cs;
       sincospif(2.0f * uf(w.y), &sn, &cs);
-      float alf = rad * cs, bef = rad * sn;
-      F3 v = f3(alf, bef, sqrtf(1.0f - alf * alf - bef * bef));
-      al = alf; be = bef;
-      F3 O32, d32;
-      if (J.identity_T) {
-        O32 = to_f(xp);
-        d32 = normalize(v);
-      } else {
-        float M[12];
-        for (int k = 0; k < 12; ++k) M[k] = (float)J.Ti[k];
-        F3 x = to_f(xp);
-        O32 = f3(M[0] * x.x + M[1] * x.y + M[2] * x.z + M[3], M[4] * x.x + M[5] * x.y + M[6] * x.z + M[7],
-                 M[8] * x.x + M[9] * x.y + M[10] * x.z + M[11]);
-        d32 = normalize(f3(M[0] * v.x + M[1] * v.y + M[2] * v.z, M[4] * v.x + M[5] * v.y + M[6] * v.z,
-                           M[8] * v.x + M[9] * v.y + M[10] * v.z));
-      }
-      O = to_d(O32); d = to_d(d32);
+      al = rad * cs; be = rad * sn;
     }
+    D3 O, d;
+    primary_ray(J, px, py, al, be, O, d);
     sal = al; sbe = be;
     st.o = O; st.d = d;
     st.ell = 0.0;
@@ -254,6 +257,25 @@ __device__ __forceinline__ void gen_path(const BatchDev &B, uint32_t i, RayState
     st.meta = STAGE_TAIL;  // b = 0, bP = 0
     ro = to_f(x); rd = to_f(d);
     key = morton8((float)pu, (float)pv);
+  }
+}
+
+// State of entry i of the first queue, as gen_path made it (store_first).
+__device__ __forceinline__ void load_first(const BatchDev &B, const RayQueue &Q, uint32_t i, RayState &r,
+                                           const JobDev *Jl) {
+  r.i = i;
+  r.slot = Q.slot[i]; r.unit = Q.unit[i];
+  r.sig = kSigInit;
+  r.bpre = 1.f; r.wt = 1.f; r.beta = 1.f; r.L = 0.f;
+  const UnitDev &U = B.units[r.unit];
+  if (U.kind == UNIT_HOLO) {
+    const JobDev &J = Jl ? *Jl : *U.job;
+    const uint32_t gpix = Q.ka[i];
+    r.meta = STAGE_PREFIX;
+    primary_ray(J, gpix % J.width, gpix / J.width, Q.al[i], Q.be[i], r.o, r.d);
+    r.ell = 0.0;
+  } else {
+    r.meta = STAGE_TAIL;
   }
 }
 
@@ -291,7 +313,7 @@ __global__ void __launch_bounds__(kRaygenBlock) k_raygen(BatchDev B) {
   const uint32_t nv = min((uint32_t)blockDim.x, B.n_paths - g0);
   if (threadIdx.x < nv) {
     gen_path(B, g0 + perm[threadIdx.x], st, ska, skb, sal, sbe, ro, rd, key);
-    store_state(B.Q[0], g0 + threadIdx.x, st, nullptr, ska, skb, sal, sbe, ro, rd, -1);
+    store_first(B.Q[0], g0 + threadIdx.x, st, ska, skb, sal, sbe, ro, rd);
   }
 }
 
@@ -720,6 +742,7 @@ __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, 
 
 constexpr uint32_t kLdsMats = 64;  // materials a workgroup keeps in LDS
 
+template <bool FIRST>
 __global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
   __shared__ StageLds G;
   __shared__ JobDev lds_job;
@@ -769,7 +792,8 @@ __global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
     e.on = false;
     if (live) {
       RayState st;
-      load_state(B.Q[q], i, st);
+      if (FIRST) load_first(B, B.Q[q], i, st, Jl);
+      else load_state(B.Q[q], i, st);
       shade_one(B, q, i, st, G, Jl, e);
     }
     // compaction: wave counts from ballots, one atomic per workgroup (all
@@ -1025,8 +1049,11 @@ hipError_t launch_trace(const BatchDev &B, int q, bool count, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_shade(const BatchDev &B, int q, hipStream_t st) {
-  hipLaunchKernelGGL(k_shade, dim3(round8(grid_for(B.n_paths))), dim3(kBlock), 0, st, B, q);
+hipError_t launch_shade(const BatchDev &B, int q, bool first, hipStream_t st) {
+  if (first)
+    hipLaunchKernelGGL(k_shade<true>, dim3(round8(grid_for(B.n_paths))), dim3(kBlock), 0, st, B, q);
+  else
+    hipLaunchKernelGGL(k_shade<false>, dim3(round8(grid_for(B.n_paths))), dim3(kBlock), 0, st, B, q);
   return hipGetLastError();
 }
 

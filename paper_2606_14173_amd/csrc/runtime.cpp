@@ -493,7 +493,7 @@ hpt_status launch_batch(hpt_ctx *C, int si, int prev) {
   for (uint32_t it = 0; it <= max_b; ++it) {
     int q = (int)(it & 1u);
     timed_launch(L, HPT_K_TRACE, S, e, [&] { return launch_trace(B, q, profile >= 2, S); });
-    timed_launch(L, HPT_K_SHADE, S, e, [&] { return launch_shade(B, q, S); });
+    timed_launch(L, HPT_K_SHADE, S, e, [&] { return launch_shade(B, q, it == 0, S); });
   }
   if (e == hipSuccess) e = hipMemcpyAsync(L.h_cnt, B.counters, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, S);
   if (e == hipSuccess && profile >= 2)
