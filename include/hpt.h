@@ -230,6 +230,28 @@ hpt_status hpt_asm_propagate(hpt_ctx *ctx, const void *d_in, void *d_out, uint32
                              uint32_t width, uint32_t height, double pitch, double lambda,
                              double distance, uint32_t flags);
 
+/* Reconstruction (simulated viewing of the hologram; the paper's focal
+ * stacks and time multiplexing, Sec. 5.3, physical configuration): each of the
+ * n_ch x T fields is carried to each of n_planes distances by the ASM of
+ * hpt_asm_propagate (padding, evanescent cut and HPT_ASM_BAND_LIMIT as
+ * there), low-pass filtered by a circular pupil of numerical aperture na
+ * (spatial frequencies with lambda |f| > na removed, na <= 0: no pupil), and
+ * the intensities |u|^2 are averaged over the T frames of each channel:
+ *   out[c][p] = (1/T) sum_t |ASM_{lambda_c, d_p, na}(U[c][t])|^2.
+ *   d_fields: device, complex64 [n_ch][T][height][width]; d_out: device,
+ *     float32 [n_ch][n_planes][height][width]; caller-owned, not aliasing.
+ *   lambdas (n_ch entries), distances (n_planes entries): host arrays,
+ *     metres; lambdas > 0, distances finite; width, height: 1..4096;
+ *     n_ch, T >= 1; 1 <= n_planes <= 64; na finite.
+ * The forward transforms of a chunk of frames are computed once and reused
+ * for every plane. Synchronous. Scratch (three [height][P_x] complex64
+ * buffers per frame of a chunk, at most 1 GiB, and twiddle tables) from the
+ * context's budget for the call. EINVAL on bad arguments, EBUDGET if one
+ * frame's scratch does not fit, EDEVICE on a HIP error. */
+hpt_status hpt_reconstruct(hpt_ctx *ctx, const void *d_fields, uint32_t n_ch, uint32_t T, uint32_t width,
+                           uint32_t height, double pitch, const double *lambdas, uint32_t n_planes,
+                           const double *distances, double na, uint32_t flags, void *d_out);
+
 /* ---------------------------------------------------------------- profiling
  * Level 1: HIP events around every kernel launch on the context stream,
  * summed per kernel kind. Level 2: also counts BVH node visits and primitive

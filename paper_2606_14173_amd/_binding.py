@@ -110,6 +110,8 @@ SIGNATURES = {
     "hpt_profile_reset": (C.c_int, [_vp]),
     "hpt_asm_propagate": (C.c_int, [_vp, _vp, _vp, _u32, _u32, _u32, C.c_double, C.c_double, C.c_double,
                                     _u32]),
+    "hpt_reconstruct": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _u32, C.c_double, C.POINTER(C.c_double), _u32,
+                                  C.POINTER(C.c_double), C.c_double, _u32, _vp]),
 }
 ASM_BAND_LIMIT = 1
 
@@ -313,6 +315,21 @@ class Context:
         pd = dst if isinstance(dst, int) else dst.data_ptr()
         _check(self.lib.hpt_asm_propagate(self.h, ps, pd, n_fields, width, height, float(pitch), float(lam),
                                           float(distance), ASM_BAND_LIMIT if band_limit else 0))
+
+    def reconstruct(self, fields, n_ch, T, width, height, pitch, lambdas, distances, na, out, band_limit=True):
+        """Focal stack: mean over the T frames of the intensity of each of the
+        n_ch x T complex64 [height][width] fields carried to each distance,
+        through a pupil of numerical aperture na (<= 0: none); fields: device
+        [n_ch][T][h][w] complex64, out: device [n_ch][n_planes][h][w] float32
+        (device pointers (int) or torch tensors)."""
+        if len(lambdas) != n_ch:
+            raise ValueError("one wavelength per channel")
+        pf = fields if isinstance(fields, int) else fields.data_ptr()
+        po = out if isinstance(out, int) else out.data_ptr()
+        lam = (C.c_double * len(lambdas))(*[float(x) for x in lambdas])
+        dist = (C.c_double * len(distances))(*[float(x) for x in distances])
+        _check(self.lib.hpt_reconstruct(self.h, pf, n_ch, T, width, height, float(pitch), lam, len(distances),
+                                        dist, float(na), ASM_BAND_LIMIT if band_limit else 0, po))
 
     # profiling
     def profile(self, level):

@@ -13,7 +13,13 @@
 //   k_ifft_rows    inverse FFT of each row, keep [0, w), scale 1/(Px Py)
 // Transfer function H = exp(+i 2 pi z sqrt(1/lambda^2 - f^2)) on propagating
 // frequencies (phase reduced in FP64), optionally band-limited
-// (Matsushima and Shimobaba, 2009), 0 on evanescent ones.
+// (Matsushima and Shimobaba, 2009) and cut by a circular pupil, 0 on
+// evanescent ones.
+//
+// Focal stacks (reconstruction): the row spectra of a set of fields (the
+// first two steps) are kept and reused for every observation plane; per
+// plane the column pass writes to a second buffer and k_ifft_rows_intensity
+// sums |u|^2 over the fields instead of writing the fields.
 //
 // Line FFTs run in LDS, one workgroup per line: radix-4 Stockham stages
 // (Govindaraju et al., SC 2008 formulation), a final radix-2 stage when
@@ -161,9 +167,9 @@ __global__ void __launch_bounds__(256) k_transpose(const float2 *in, float2 *out
 // zero-pad the column to Py, FFT, multiply by H(f_x, f_y), inverse FFT, keep
 // rows [0, h).
 template <int U4>
-__global__ void __launch_bounds__(kFftThreads) k_fft_columns(float2 *B, uint32_t nf, uint32_t h, uint32_t px,
-                                                             uint32_t py, uint32_t lgy, AsmParams P,
-                                                             const float2 *tw) {
+__global__ void __launch_bounds__(kFftThreads) k_fft_columns(const float2 *src, float2 *dst, uint32_t nf,
+                                                             uint32_t h, uint32_t px, uint32_t py, uint32_t lgy,
+                                                             AsmParams P, const float2 *tw) {
   extern __shared__ C2 lds[];
   constexpr int UH = 4 * U4;  // rows per thread (py <= 4 * U4 * kFftThreads)
   const uint32_t kx = blockIdx.x, t = threadIdx.x;
@@ -178,7 +184,8 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_columns(float2 *B, uint32_t
     if (i < py) {
       const double fy = (i < py / 2 ? (double)i : (double)i - (double)py) * P.dfy;
       const double f2 = fx * fx + fy * fy;
-      if (ok_x && (!P.band_limit || fabs(fy) <= P.lim_y) && f2 < P.inv_lam2) {
+      if (ok_x && (!P.band_limit || fabs(fy) <= P.lim_y) && f2 < P.inv_lam2 &&
+          (P.pupil2 <= 0.0 || f2 <= P.pupil2)) {
         // z sqrt(1/lambda^2 - f^2) = z/lambda - z f^2 / (1/lambda + sqrt(1/lambda^2 - f^2)),
         // the first term reduced modulo 1 on the host
         const double rev = P.z_rev_frac - P.z * f2 / (P.inv_lam + sqrt(P.inv_lam2 - f2));
@@ -190,9 +197,10 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_columns(float2 *B, uint32_t
     }
   }
   for (uint32_t f = 0; f < nf; ++f) {
-    float2 *col = B + ((size_t)f * px + kx) * h;
+    const float2 *scol = src + ((size_t)f * px + kx) * h;
+    float2 *col = dst + ((size_t)f * px + kx) * h;
     for (uint32_t i = t; i < py; i += kFftThreads) {
-      float2 v = i < h ? col[i] : make_float2(0.f, 0.f);
+      float2 v = i < h ? scol[i] : make_float2(0.f, 0.f);
       lds[i] = c2(v.x, v.y);
     }
     __syncthreads();
@@ -236,6 +244,46 @@ __global__ void __launch_bounds__(kFftThreads) k_ifft_rows(const float2 *A, floa
   for (uint32_t i = threadIdx.x; i < w; i += kFftThreads) dst[i] = make_float2(lds[i].x * scale, lds[i].y * scale);
 }
 
+// Summed intensity of row y over nf fields: inverse FFT of row (f, y) of
+// A [nf][h][Px] for every f < nf, scaled by 1/(Px Py), |.|^2 of the first w
+// values summed over f, times `weight`; written into (or added to) I [h][w].
+template <int U4>
+__global__ void __launch_bounds__(kFftThreads) k_ifft_rows_intensity(const float2 *A, float *I, uint32_t nf,
+                                                                     uint32_t w, uint32_t h, uint32_t px,
+                                                                     uint32_t lgx, float scale, float weight,
+                                                                     uint32_t accumulate, const float2 *tw) {
+  extern __shared__ C2 lds[];
+  constexpr int UW = 4 * U4;  // values per thread (px <= 4 * U4 * kFftThreads)
+  const uint32_t y = blockIdx.x, t = threadIdx.x;
+  float acc[UW];
+#pragma unroll
+  for (int u = 0; u < UW; ++u) acc[u] = 0.f;
+  for (uint32_t f = 0; f < nf; ++f) {
+    const float2 *src = A + ((size_t)f * h + y) * px;
+    for (uint32_t i = t; i < px; i += kFftThreads) {
+      float2 v = src[i];
+      lds[i] = c2(v.x, v.y);
+    }
+    __syncthreads();
+    lds_fft<U4>(lds, px, lgx, true, tw);
+#pragma unroll
+    for (int u = 0; u < UW; ++u) {
+      const uint32_t i = t + (uint32_t)u * kFftThreads;
+      if (i < w) {
+        const float re = lds[i].x * scale, im = lds[i].y * scale;
+        acc[u] += re * re + im * im;
+      }
+    }
+    __syncthreads();  // before the next field overwrites the buffer
+  }
+  float *dst = I + (size_t)y * w;
+#pragma unroll
+  for (int u = 0; u < UW; ++u) {
+    const uint32_t i = t + (uint32_t)u * kFftThreads;
+    if (i < w) dst[i] = (accumulate ? dst[i] : 0.f) + acc[u] * weight;
+  }
+}
+
 uint32_t log2u(uint32_t n) {
   uint32_t l = 0;
   while ((1u << l) < n) ++l;
@@ -261,17 +309,33 @@ void rows(bool inv, const float2 *in, float2 *out, uint32_t nrows, uint32_t w, u
   else launch_rows<8>(inv, in, out, nrows, w, h, px, lgx, scale, tw, st);
 }
 
-void columns(float2 *B, uint32_t nf, uint32_t h, uint32_t px, uint32_t py, uint32_t lgy, const AsmParams &P,
-             const float2 *tw, hipStream_t st) {
+void columns(const float2 *src, float2 *dst, uint32_t nf, uint32_t h, uint32_t px, uint32_t py, uint32_t lgy,
+             const AsmParams &P, const float2 *tw, hipStream_t st) {
   const size_t sh = py * sizeof(C2);
   if (py <= 4 * kFftThreads)
-    hipLaunchKernelGGL(k_fft_columns<1>, dim3(px), dim3(kFftThreads), sh, st, B, nf, h, px, py, lgy, P, tw);
+    hipLaunchKernelGGL(k_fft_columns<1>, dim3(px), dim3(kFftThreads), sh, st, src, dst, nf, h, px, py, lgy, P, tw);
   else if (py <= 8 * kFftThreads)
-    hipLaunchKernelGGL(k_fft_columns<2>, dim3(px), dim3(kFftThreads), sh, st, B, nf, h, px, py, lgy, P, tw);
+    hipLaunchKernelGGL(k_fft_columns<2>, dim3(px), dim3(kFftThreads), sh, st, src, dst, nf, h, px, py, lgy, P, tw);
   else if (py <= 16 * kFftThreads)
-    hipLaunchKernelGGL(k_fft_columns<4>, dim3(px), dim3(kFftThreads), sh, st, B, nf, h, px, py, lgy, P, tw);
+    hipLaunchKernelGGL(k_fft_columns<4>, dim3(px), dim3(kFftThreads), sh, st, src, dst, nf, h, px, py, lgy, P, tw);
   else
-    hipLaunchKernelGGL(k_fft_columns<8>, dim3(px), dim3(kFftThreads), sh, st, B, nf, h, px, py, lgy, P, tw);
+    hipLaunchKernelGGL(k_fft_columns<8>, dim3(px), dim3(kFftThreads), sh, st, src, dst, nf, h, px, py, lgy, P, tw);
+}
+
+template <int U4>
+void launch_intensity_rows(const float2 *A, float *I, uint32_t nf, uint32_t w, uint32_t h, uint32_t px,
+                           uint32_t lgx, float scale, float weight, bool accumulate, const float2 *tw,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_ifft_rows_intensity<U4>, dim3(h), dim3(kFftThreads), px * sizeof(C2), st, A, I, nf, w, h, px,
+                     lgx, scale, weight, accumulate ? 1u : 0u, tw);
+}
+
+void intensity_rows(const float2 *A, float *I, uint32_t nf, uint32_t w, uint32_t h, uint32_t px, uint32_t lgx,
+                    float scale, float weight, bool accumulate, const float2 *tw, hipStream_t st) {
+  if (px <= 4 * kFftThreads) launch_intensity_rows<1>(A, I, nf, w, h, px, lgx, scale, weight, accumulate, tw, st);
+  else if (px <= 8 * kFftThreads) launch_intensity_rows<2>(A, I, nf, w, h, px, lgx, scale, weight, accumulate, tw, st);
+  else if (px <= 16 * kFftThreads) launch_intensity_rows<4>(A, I, nf, w, h, px, lgx, scale, weight, accumulate, tw, st);
+  else launch_intensity_rows<8>(A, I, nf, w, h, px, lgx, scale, weight, accumulate, tw, st);
 }
 
 }  // namespace
@@ -289,6 +353,26 @@ hipError_t launch_asm_twiddles(float2 *tw, uint32_t w, uint32_t h, hipStream_t s
   return hipGetLastError();
 }
 
+hipError_t launch_asm_spectra(const float2 *in, float2 *A, float2 *B0, const float2 *tw, uint32_t nf, uint32_t w,
+                              uint32_t h, hipStream_t st) {
+  const uint32_t px = asm_padded(w), py = asm_padded(h);
+  if (px > (uint32_t)kFftMax || py > (uint32_t)kFftMax || nf == 0 || w == 0 || h == 0) return hipErrorInvalidValue;
+  rows(false, in, A, nf * h, w, h, px, log2u(px), 1.0f, tw, st);
+  hipLaunchKernelGGL(k_transpose, dim3((px + 31) / 32, (h + 31) / 32, nf), dim3(256), 0, st, A, B0, h, px);
+  return hipGetLastError();
+}
+
+hipError_t launch_asm_intensity(const float2 *B0, float2 *B, float2 *A, const float2 *tw, uint32_t nf, uint32_t w,
+                                uint32_t h, const AsmParams &P, float *I, float weight, bool accumulate,
+                                hipStream_t st) {
+  const uint32_t px = asm_padded(w), py = asm_padded(h);
+  if (px > (uint32_t)kFftMax || py > (uint32_t)kFftMax || nf == 0 || w == 0 || h == 0) return hipErrorInvalidValue;
+  columns(B0, B, nf, h, px, py, log2u(py), P, tw + px, st);
+  hipLaunchKernelGGL(k_transpose, dim3((h + 31) / 32, (px + 31) / 32, nf), dim3(256), 0, st, B, A, px, h);
+  intensity_rows(A, I, nf, w, h, px, log2u(px), 1.0f / ((float)px * (float)py), weight, accumulate, tw, st);
+  return hipGetLastError();
+}
+
 hipError_t launch_asm(const float2 *in, float2 *out, float2 *A, float2 *B, const float2 *tw, uint32_t nf,
                       uint32_t w, uint32_t h, const AsmParams &P, hipStream_t st) {
   const uint32_t px = asm_padded(w), py = asm_padded(h);
@@ -296,7 +380,7 @@ hipError_t launch_asm(const float2 *in, float2 *out, float2 *A, float2 *B, const
   const uint32_t lgx = log2u(px), lgy = log2u(py);
   rows(false, in, A, nf * h, w, h, px, lgx, 1.0f, tw, st);
   hipLaunchKernelGGL(k_transpose, dim3((px + 31) / 32, (h + 31) / 32, nf), dim3(256), 0, st, A, B, h, px);
-  columns(B, nf, h, px, py, lgy, P, tw + px, st);
+  columns(B, B, nf, h, px, py, lgy, P, tw + px, st);
   hipLaunchKernelGGL(k_transpose, dim3((h + 31) / 32, (px + 31) / 32, nf), dim3(256), 0, st, B, A, px, h);
   rows(true, A, out, nf * h, w, h, px, lgx, 1.0f / ((float)px * (float)py), tw, st);
   return hipGetLastError();

@@ -14,6 +14,7 @@ struct AsmParams {
   double inv_lam, inv_lam2;
   double z;
   double z_rev_frac;      // frac(z / lambda)
+  double pupil2;          // squared pupil cutoff (NA / lambda)^2; 0: no pupil
   uint32_t band_limit;
 };
 
@@ -29,5 +30,17 @@ hipError_t launch_asm_twiddles(float2 *tw, uint32_t w, uint32_t h, hipStream_t s
 // hipErrorInvalidValue if a padded axis exceeds 8192 or a size is zero.
 hipError_t launch_asm(const float2 *in, float2 *out, float2 *A, float2 *B, const float2 *tw, uint32_t nf,
                       uint32_t w, uint32_t h, const AsmParams &P, hipStream_t st);
+
+// Focal stacks. Row spectra of nf fields: in [nf][h][w] -> B0 [nf][Px][h]
+// (A: scratch of nf * h * Px complex64).
+hipError_t launch_asm_spectra(const float2 *in, float2 *A, float2 *B0, const float2 *tw, uint32_t nf, uint32_t w,
+                              uint32_t h, hipStream_t st);
+// The nf fields whose row spectra B0 holds, carried by the transfer function
+// of P: weight * sum over the fields of |u|^2 written into (accumulate:
+// added to) I [h][w]. B, A: scratch of nf * h * Px complex64 each; B0 is
+// kept.
+hipError_t launch_asm_intensity(const float2 *B0, float2 *B, float2 *A, const float2 *tw, uint32_t nf, uint32_t w,
+                                uint32_t h, const AsmParams &P, float *I, float weight, bool accumulate,
+                                hipStream_t st);
 
 }  // namespace hpt

@@ -1264,14 +1264,12 @@ hpt_status hpt_grf_read(hpt_ctx *C, uint32_t gw, uint32_t gh, uint32_t T, uint64
   return HPT_OK;
 }
 
-hpt_status hpt_asm_propagate(hpt_ctx *C, const void *d_in, void *d_out, uint32_t n_fields, uint32_t width,
-                             uint32_t height, double pitch, double lambda, double distance, uint32_t flags) {
-  if (!C || !d_in || !d_out) return fail(HPT_EINVAL, "null argument");
-  if (n_fields < 1 || width < 1 || height < 1 || width > 4096 || height > 4096)
-    return fail(HPT_EINVAL, "field size out of range (1..4096 per axis, at least one field)");
-  if (!(pitch > 0) || !std::isfinite(pitch) || !(lambda > 0) || !std::isfinite(lambda) || !std::isfinite(distance))
-    return fail(HPT_EINVAL, "bad pitch, wavelength or distance");
-  if (flags & ~HPT_ASM_BAND_LIMIT) return fail(HPT_EINVAL, "unknown flags");
+}  // extern "C"
+
+namespace {
+// Transfer-function constants of one propagation (na > 0: pupil cutoff NA / lambda).
+AsmParams asm_params(uint32_t width, uint32_t height, double pitch, double lambda, double distance, uint32_t flags,
+                     double na) {
   const uint32_t px = asm_padded(width), py = asm_padded(height);
   AsmParams P;
   P.dfx = 1.0 / (px * pitch);
@@ -1283,7 +1281,24 @@ hpt_status hpt_asm_propagate(hpt_ctx *C, const void *d_in, void *d_out, uint32_t
   P.z = distance;
   const double zr = distance / lambda;
   P.z_rev_frac = zr - std::floor(zr);
+  P.pupil2 = na > 0.0 ? (na / lambda) * (na / lambda) : 0.0;
   P.band_limit = (flags & HPT_ASM_BAND_LIMIT) ? 1u : 0u;
+  return P;
+}
+}  // namespace
+
+extern "C" {
+
+hpt_status hpt_asm_propagate(hpt_ctx *C, const void *d_in, void *d_out, uint32_t n_fields, uint32_t width,
+                             uint32_t height, double pitch, double lambda, double distance, uint32_t flags) {
+  if (!C || !d_in || !d_out) return fail(HPT_EINVAL, "null argument");
+  if (n_fields < 1 || width < 1 || height < 1 || width > 4096 || height > 4096)
+    return fail(HPT_EINVAL, "field size out of range (1..4096 per axis, at least one field)");
+  if (!(pitch > 0) || !std::isfinite(pitch) || !(lambda > 0) || !std::isfinite(lambda) || !std::isfinite(distance))
+    return fail(HPT_EINVAL, "bad pitch, wavelength or distance");
+  if (flags & ~HPT_ASM_BAND_LIMIT) return fail(HPT_EINVAL, "unknown flags");
+  const uint32_t px = asm_padded(width), py = asm_padded(height);
+  const AsmParams P = asm_params(width, height, pitch, lambda, distance, flags, 0.0);
   // scratch for a chunk of fields: two [h][Px] complex64 buffers per field
   const uint64_t per = 2ull * height * px * sizeof(float2);
   float2 *A = nullptr, *B = nullptr, *W = nullptr;
@@ -1317,6 +1332,7 @@ hpt_status hpt_asm_propagate(hpt_ctx *C, const void *d_in, void *d_out, uint32_t
                    P, C->aux);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(C->aux);
+  else (void)hipStreamSynchronize(C->aux);  // launches already queued still use the scratch
   {
     std::lock_guard<std::mutex> g(C->mu);
     const size_t half = (size_t)chunk * height * px * sizeof(float2);
@@ -1325,6 +1341,77 @@ hpt_status hpt_asm_propagate(hpt_ctx *C, const void *d_in, void *d_out, uint32_t
     C->release(W, tw_bytes);
   }
   if (e != hipSuccess) return fail(HPT_EDEVICE, std::string("propagation failed: ") + hipGetErrorString(e));
+  return HPT_OK;
+}
+
+hpt_status hpt_reconstruct(hpt_ctx *C, const void *d_fields, uint32_t n_ch, uint32_t T, uint32_t width,
+                           uint32_t height, double pitch, const double *lambdas, uint32_t n_planes,
+                           const double *distances, double na, uint32_t flags, void *d_out) {
+  if (!C || !d_fields || !d_out || !lambdas || !distances) return fail(HPT_EINVAL, "null argument");
+  if (n_ch < 1 || T < 1 || n_planes < 1 || n_planes > 64)
+    return fail(HPT_EINVAL, "need n_ch >= 1, T >= 1 and 1..64 planes");
+  if (width < 1 || height < 1 || width > 4096 || height > 4096)
+    return fail(HPT_EINVAL, "field size out of range (1..4096 per axis)");
+  if (!(pitch > 0) || !std::isfinite(pitch) || !std::isfinite(na)) return fail(HPT_EINVAL, "bad pitch or aperture");
+  for (uint32_t c = 0; c < n_ch; ++c)
+    if (!(lambdas[c] > 0) || !std::isfinite(lambdas[c])) return fail(HPT_EINVAL, "bad wavelength");
+  for (uint32_t p = 0; p < n_planes; ++p)
+    if (!std::isfinite(distances[p])) return fail(HPT_EINVAL, "bad distance");
+  if (flags & ~HPT_ASM_BAND_LIMIT) return fail(HPT_EINVAL, "unknown flags");
+  const uint32_t px = asm_padded(width), py = asm_padded(height);
+  // scratch per frame of a chunk: row spectra (kept over the planes) and two work buffers
+  const uint64_t per = 3ull * height * px * sizeof(float2);
+  const size_t tw_bytes = (size_t)(px + py) * sizeof(float2);
+  float2 *A = nullptr, *B = nullptr, *B0 = nullptr, *W = nullptr;
+  uint32_t chunk = 0;
+  size_t third = 0;
+  {
+    std::lock_guard<std::mutex> g(C->mu);
+    (void)hipSetDevice(C->device);
+    uint64_t free_b = C->budget > C->used ? C->budget - C->used : 0;
+    if (free_b < per + tw_bytes) evict_grfs(C, per + tw_bytes);
+    free_b = C->budget > C->used ? C->budget - C->used : 0;
+    free_b = free_b > tw_bytes ? free_b - tw_bytes : 0;
+    chunk = (uint32_t)std::min<uint64_t>({(uint64_t)T, free_b / per, std::max<uint64_t>(1, (1ull << 30) / per)});
+    if (chunk == 0) return fail(HPT_EBUDGET, "reconstruction scratch does not fit the budget");
+    third = (size_t)chunk * height * px * sizeof(float2);
+    bool ok = C->alloc((void **)&A, third) == hipSuccess;
+    ok = ok && C->alloc((void **)&B, third) == hipSuccess;
+    ok = ok && C->alloc((void **)&B0, third) == hipSuccess;
+    ok = ok && C->alloc((void **)&W, tw_bytes) == hipSuccess;
+    if (!ok) {
+      if (A) C->release(A, third);
+      if (B) C->release(B, third);
+      if (B0) C->release(B0, third);
+      if (W) C->release(W, tw_bytes);
+      return fail(HPT_ENOMEM, "scratch allocation failed");
+    }
+  }
+  hipError_t e = launch_asm_twiddles(W, width, height, C->aux);
+  const size_t field = (size_t)width * height;
+  const float weight = 1.0f / (float)T;
+  for (uint32_t c = 0; c < n_ch && e == hipSuccess; ++c) {
+    for (uint32_t t0 = 0; t0 < T && e == hipSuccess; t0 += chunk) {
+      const uint32_t nf = std::min(chunk, T - t0);
+      e = launch_asm_spectra((const float2 *)d_fields + ((size_t)c * T + t0) * field, A, B0, W, nf, width, height,
+                             C->aux);
+      for (uint32_t p = 0; p < n_planes && e == hipSuccess; ++p) {
+        const AsmParams P = asm_params(width, height, pitch, lambdas[c], distances[p], flags, na);
+        float *I = (float *)d_out + ((size_t)c * n_planes + p) * field;
+        e = launch_asm_intensity(B0, B, A, W, nf, width, height, P, I, weight, t0 > 0, C->aux);
+      }
+    }
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(C->aux);
+  else (void)hipStreamSynchronize(C->aux);  // launches already queued still use the scratch
+  {
+    std::lock_guard<std::mutex> g(C->mu);
+    C->release(A, third);
+    C->release(B, third);
+    C->release(B0, third);
+    C->release(W, tw_bytes);
+  }
+  if (e != hipSuccess) return fail(HPT_EDEVICE, std::string("reconstruction failed: ") + hipGetErrorString(e));
   return HPT_OK;
 }
 

@@ -1,0 +1,133 @@
+"""Focal-stack reconstruction on the GPU (simulated viewing: ASM to
+observation planes, circular pupil, mean intensity over the T frames;
+Sec. 5.3) against the FP64 oracle through the C ABI: ragged and tiny sizes,
+several channels and planes, pupil and band limit on and off, frames in
+more than one scratch chunk, the 1920 x 1080 size, and traced fields.
+Bar: max |GPU - oracle| <= 1e-4 x mean(oracle intensity) (FP32 transforms
+carry a relative field error of order 1e-6)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import recon as orecon
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+D = 8e-6
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2606_14173_amd as hpt
+    c = hpt.Context(0)
+    yield c
+    c.close()
+
+
+def _fields(shape, seed):
+    """Seeded complex64 fields [..., h, w]: speckle plus a few Gaussian spots."""
+    rng = np.random.default_rng(seed)
+    h, w = shape[-2:]
+    y, x = np.mgrid[0:h, 0:w]
+    out = 0.3 * (rng.normal(size=shape) + 1j * rng.normal(size=shape))
+    flat = out.reshape(-1, h, w)
+    for f in range(flat.shape[0]):
+        for _ in range(3):
+            cy, cx, s = rng.uniform(0, h), rng.uniform(0, w), rng.uniform(1.5, 6.0)
+            flat[f] += np.exp(-((y - cy) ** 2 + (x - cx) ** 2) / (2 * s * s) + 2j * np.pi * rng.uniform())
+    return out.astype(np.complex64)
+
+
+def _gpu(ctx, U, lambdas, dists, na, band_limit=True):
+    import torch
+    n_ch, T, h, w = U.shape
+    src = torch.from_numpy(np.ascontiguousarray(U)).to("cuda:0")
+    out = torch.empty((n_ch, len(dists), h, w), dtype=torch.float32, device="cuda:0")
+    ctx.reconstruct(src, n_ch, T, w, h, D, lambdas, dists, na, out, band_limit)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def _check(got, ref, label):
+    scale = float(ref.mean())
+    err = float(np.abs(got.astype(np.float64) - ref).max() / scale)
+    print("%s: max err / mean = %.2e" % (label, err))
+    sys.stdout.flush()
+    assert err <= TOL, label
+
+
+@pytest.mark.parametrize("h,w", [(1, 1), (37, 29), (64, 64), (5, 257)])
+@pytest.mark.parametrize("na,band_limit", [(0.0, True), (0.02, True), (0.025, False)])
+def test_recon_matches_oracle(ctx, h, w, na, band_limit):
+    U = _fields((2, 3, h, w), seed=h * 100 + w)
+    lambdas, dists = [638e-9, 450e-9], [2e-3, -1e-3, 30e-3]
+    ref = orecon.focal_stack(U.astype(np.complex128), D, lambdas, dists, na=na, band_limit=band_limit)
+    got = _gpu(ctx, U, lambdas, dists, na, band_limit)
+    _check(got, ref, "%dx%d na=%g bl=%d" % (h, w, na, band_limit))
+
+
+def test_recon_frames_in_several_chunks(ctx):
+    """90 frames of 512 x 512: the scratch of one chunk is capped at 1 GiB
+    (85 frames at this size), so the intensities of the later chunk are added
+    to those of the first."""
+    U = _fields((1, 90, 512, 512), seed=7)
+    ref = orecon.focal_stack(U.astype(np.complex128), D, [520e-9], [5e-3, 20e-3], na=0.02)
+    got = _gpu(ctx, U, [520e-9], [5e-3, 20e-3], 0.02)
+    _check(got, ref, "512x512 T=90")
+
+
+def test_recon_full_size(ctx):
+    """1920 x 1080, padded to 4096 x 4096, two frames to 80 and 85 mm."""
+    U = _fields((1, 2, 1080, 1920), seed=11)
+    ref = orecon.focal_stack(U.astype(np.complex128), D, [450e-9], [80e-3, 85e-3], na=0.02)
+    got = _gpu(ctx, U, [450e-9], [80e-3, 85e-3], 0.02)
+    _check(got, ref, "1920x1080")
+
+
+def test_recon_rejects_bad_arguments(ctx):
+    import ctypes as C
+    import torch
+    import paper_2606_14173_amd as hpt
+    f = torch.zeros((1, 1, 8, 8), dtype=torch.complex64, device="cuda:0")
+    o = torch.zeros((1, 1, 8, 8), dtype=torch.float32, device="cuda:0")
+    good = dict(n_ch=1, T=1, w=8, h=8, pitch=D, lam=[520e-9], dist=[1e-3], na=0.0, flags=1)
+    bad = [dict(n_ch=0), dict(T=0), dict(w=4097), dict(h=0), dict(pitch=-1.0), dict(lam=[0.0]),
+           dict(dist=[float("inf")]), dict(na=float("nan")), dict(flags=4), dict(dist=[1e-3] * 65)]
+    for b in bad:
+        a = dict(good)
+        a.update(b)
+        lam = (C.c_double * len(a["lam"]))(*a["lam"])
+        dist = (C.c_double * len(a["dist"]))(*a["dist"])
+        st = ctx.lib.hpt_reconstruct(ctx.h, f.data_ptr(), a["n_ch"], a["T"], a["w"], a["h"], a["pitch"], lam,
+                                     len(a["dist"]), dist, a["na"], a["flags"], o.data_ptr())
+        assert hpt.STATUS[st] == "HPT_EINVAL", b
+
+
+def test_recon_of_traced_fields(ctx):
+    """Traced T = 4 fields of the config-0 scene, viewed 20-30 mm further on
+    through a pupil: the library (tracer + reconstruction) against the oracle
+    (tracer + reconstruction). Paths whose signatures differ are removed from
+    both fields first (the propagation mixes every pixel into every other)."""
+    import scenes
+    from scenes import jobs
+    from parity_util import gpu_run, oracle_run
+    sc = scenes.scene_tiny(0)
+    job = jobs.job_for_config(0, T=4)
+    sid = ctx.upload_scene(sc)
+    Ug, recg, ctg = gpu_run(ctx, sid, job)
+    Uo, reco, cto = oracle_run(sc, job)
+    ctx.release_scene(sid)
+    um = recg["sig"] != reco["sig"]
+    assert um.mean() <= 1e-3
+    Ugm = Ug.astype(np.complex128) - np.einsum("chwst,chws->cthw", ctg.astype(np.complex128), um)
+    Uom = Uo - np.einsum("chwst,chws->cthw", cto, um)
+    lambdas, dists = list(job["lambdas"]), [20e-3, 25e-3, 30e-3]
+    ref = orecon.focal_stack(Uom, job["pitch"], lambdas, dists, na=0.02)
+    import torch
+    n_ch, T, h, w = Ugm.shape
+    src = torch.from_numpy(Ugm.astype(np.complex64)).to("cuda:0")
+    out = torch.empty((n_ch, len(dists), h, w), dtype=torch.float32, device="cuda:0")
+    ctx.reconstruct(src, n_ch, T, w, h, job["pitch"], lambdas, dists, 0.02, out)
+    torch.cuda.synchronize()
+    _check(out.cpu().numpy(), ref, "traced %dx%d T=%d" % (w, h, T))
