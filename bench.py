@@ -360,7 +360,8 @@ def two_stage(hpt, steps, warmup):
     hologram plane by angular-spectrum propagation (4096 x 4096 padded);
     then the viewed focal stack: the hologram fields carried back to five
     planes 80-85 mm from it (1.25 mm apart), through a pupil of NA 0.02,
-    intensities averaged over the 24 frames."""
+    intensities averaged over the 24 frames; then phase-only encoding of the
+    72 hologram fields (20 Adam steps, supervised at 82.5 mm, step 0.05)."""
     import torch
     import scenes
     from scenes import jobs
@@ -377,6 +378,9 @@ def two_stage(hpt, steps, warmup):
     z_asm = 80e-3
     planes = [-(80e-3 + 1.25e-3 * k) for k in range(5)]
     stack = torch.empty((nc, len(planes), H, W), dtype=torch.float32, device="cuda:0")
+    phase = torch.empty((nc, T, H, W), dtype=torch.float32, device="cuda:0")
+    enc_steps, z_sup = 20, -82.5e-3
+    losses = []
 
     def step():
         t0 = time.perf_counter()
@@ -390,17 +394,22 @@ def two_stage(hpt, steps, warmup):
         t2 = time.perf_counter()
         ctx.reconstruct(holo, nc, T, W, H, job["pitch"], job["lambdas"], planes, 0.02, stack)
         torch.cuda.synchronize()
-        return t1 - t0, t2 - t1, time.perf_counter() - t2
+        t3 = time.perf_counter()
+        losses[:] = [ctx.encode_phase(holo[c], phase[c], T, W, H, job["pitch"], job["lambdas"][c], z_sup,
+                                      enc_steps, 0.05) for c in range(nc)]
+        return t1 - t0, t2 - t1, t3 - t2, time.perf_counter() - t3
 
     for _ in range(warmup):
         step()
-    tt = ta = tr = 0.0
+    tt = ta = tr = te = 0.0
     for i in range(steps):
-        a, b, c = step()
+        a, b, c, e = step()
         tt += a
         ta += b
         tr += c
-        log("two-stage step %d: trace %.1f ms, ASM %.1f ms, focal stack %.1f ms" % (i, 1e3 * a, 1e3 * b, 1e3 * c))
+        te += e
+        log("two-stage step %d: trace %.1f ms, ASM %.1f ms, focal stack %.1f ms, encoding %.1f ms"
+            % (i, 1e3 * a, 1e3 * b, 1e3 * c, 1e3 * e))
     assert torch.isfinite(torch.view_as_real(holo)).all().item()
     assert torch.isfinite(stack).all().item()
     n_paths = nc * W * H * job["spp"]
@@ -419,7 +428,11 @@ def two_stage(hpt, steps, warmup):
         # complex64 moved per frame: row spectra once (H W + 3 H Px), then per
         # plane the column pass, the transpose back and the intensity rows (5 H Px)
         "focal_stack_GBps_moved": round(nc * T * 8 * H * (W + 3 * px + 5 * px * len(planes)) * steps / tr / 1e9,
-                                        1)}}
+                                        1),
+        "encoding": "%d Adam steps per field, 72 fields, supervised 82.5 mm behind the hologram" % enc_steps,
+        "ms_encoding": round(1e3 * te / steps, 2),
+        "encoding_ms_per_step": round(1e3 * te / steps / enc_steps, 2),
+        "encoding_final_rel_loss_mean": round(float(np.mean(np.concatenate(losses))), 5)}}
     print(json.dumps(out), flush=True)
     ctx.close()
 

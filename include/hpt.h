@@ -252,6 +252,34 @@ hpt_status hpt_reconstruct(hpt_ctx *ctx, const void *d_fields, uint32_t n_ch, ui
                            uint32_t height, double pitch, const double *lambdas, uint32_t n_planes,
                            const double *distances, double na, uint32_t flags, void *d_out);
 
+/* Phase-only encoding (the paper's hologram encoding: SGD under
+ * complex-amplitude supervision on one plane with a phase-shift-invariant
+ * scale factor; abstract, Sec. 2, Sec. 5.3). For each field U (a rendered
+ * SLM-plane field) the phase phi of a phase-only SLM is optimised so that
+ * its field A = P exp(i phi) at the supervision plane matches the target
+ * V = P U up to one complex factor: loss L = ||A - s V||^2 with the optimal
+ * s = <V, A> / <V, V>; P = the ASM of hpt_asm_propagate over `distance`
+ * (HPT_ASM_BAND_LIMIT as there). Gradient 2 Im(G conj(exp(i phi))) with
+ * G = P^H (A - s V), P^H being the ASM over -distance; Adam (Kingma and Ba
+ * 2015: beta1 0.9, beta2 0.999, eps 1e-8, step `lr`) for `iterations` steps.
+ * Start: phi = arg U (0 where U = 0), or the contents of d_phase with
+ * HPT_ENCODE_WARM_START (Adam's moments start at zero either way).
+ *   d_fields: device complex64 [n_fields][height][width]; d_phase: device
+ *     float32 [n_fields][height][width] (radians, not wrapped), written;
+ *     caller-owned, not aliasing.
+ *   loss_out: host, n_fields doubles (nullable): the final relative loss
+ *     1 - |<V, A>|^2 / (<V, V> <A, A>) in [0, 1].
+ *   width, height 1..4096; pitch, lambda > 0; distance finite;
+ *   iterations 0..100000; lr > 0.
+ * Synchronous. Scratch (five [height][width] buffers and two [height][P_x]
+ * complex64 buffers per field of a chunk, at most 1 GiB) from the
+ * context's budget for the call. EINVAL, EBUDGET, EDEVICE as for
+ * hpt_asm_propagate. */
+#define HPT_ENCODE_WARM_START 2u
+hpt_status hpt_encode_phase(hpt_ctx *ctx, const void *d_fields, uint32_t n_fields, uint32_t width,
+                            uint32_t height, double pitch, double lambda, double distance,
+                            uint32_t iterations, double lr, uint32_t flags, void *d_phase, double *loss_out);
+
 /* ---------------------------------------------------------------- profiling
  * Level 1: HIP events around every kernel launch on the context stream,
  * summed per kernel kind. Level 2: also counts BVH node visits and primitive

@@ -112,8 +112,11 @@ SIGNATURES = {
                                     _u32]),
     "hpt_reconstruct": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _u32, C.c_double, C.POINTER(C.c_double), _u32,
                                   C.POINTER(C.c_double), C.c_double, _u32, _vp]),
+    "hpt_encode_phase": (C.c_int, [_vp, _vp, _u32, _u32, _u32, C.c_double, C.c_double, C.c_double, _u32,
+                                   C.c_double, _u32, _vp, C.POINTER(C.c_double)]),
 }
 ASM_BAND_LIMIT = 1
+ENCODE_WARM_START = 2
 
 _LIB = None
 
@@ -330,6 +333,19 @@ class Context:
         dist = (C.c_double * len(distances))(*[float(x) for x in distances])
         _check(self.lib.hpt_reconstruct(self.h, pf, n_ch, T, width, height, float(pitch), lam, len(distances),
                                         dist, float(na), ASM_BAND_LIMIT if band_limit else 0, po))
+
+    def encode_phase(self, fields, phase, n_fields, width, height, pitch, lam, distance, iterations, lr,
+                     band_limit=True, warm_start=False):
+        """Phase-only encoding of n_fields complex64 [height][width] fields
+        into float32 phases (device pointers (int) or torch tensors); returns
+        the final relative loss of each field."""
+        pf = fields if isinstance(fields, int) else fields.data_ptr()
+        pp = phase if isinstance(phase, int) else phase.data_ptr()
+        loss = (C.c_double * n_fields)()
+        flags = (ASM_BAND_LIMIT if band_limit else 0) | (ENCODE_WARM_START if warm_start else 0)
+        _check(self.lib.hpt_encode_phase(self.h, pf, n_fields, width, height, float(pitch), float(lam),
+                                         float(distance), int(iterations), float(lr), flags, pp, loss))
+        return np.array(loss[:], dtype=np.float64)
 
     # profiling
     def profile(self, level):

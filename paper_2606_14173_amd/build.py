@@ -13,7 +13,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for all device code.
 DEVICE_FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["kernels.hip", "asm.hip", "runtime.cpp", "bvh_build.cpp"]
+SOURCES = ["kernels.hip", "asm.hip", "encode.hip", "runtime.cpp", "bvh_build.cpp"]
 
 
 def build(verbose=False):

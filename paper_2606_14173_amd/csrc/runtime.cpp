@@ -27,6 +27,7 @@
 
 #include "../../include/hpt.h"
 #include "asm.hpp"
+#include "encode.hpp"
 #include "bvh_build.hpp"
 #include "hpt_types.hpp"
 #include "kernels.hpp"
@@ -1341,6 +1342,93 @@ hpt_status hpt_asm_propagate(hpt_ctx *C, const void *d_in, void *d_out, uint32_t
     C->release(W, tw_bytes);
   }
   if (e != hipSuccess) return fail(HPT_EDEVICE, std::string("propagation failed: ") + hipGetErrorString(e));
+  return HPT_OK;
+}
+
+hpt_status hpt_encode_phase(hpt_ctx *C, const void *d_fields, uint32_t n_fields, uint32_t width, uint32_t height,
+                            double pitch, double lambda, double distance, uint32_t iterations, double lr,
+                            uint32_t flags, void *d_phase, double *loss_out) {
+  if (!C || !d_fields || !d_phase) return fail(HPT_EINVAL, "null argument");
+  if (n_fields < 1 || width < 1 || height < 1 || width > 4096 || height > 4096)
+    return fail(HPT_EINVAL, "field size out of range (1..4096 per axis, at least one field)");
+  if (!(pitch > 0) || !std::isfinite(pitch) || !(lambda > 0) || !std::isfinite(lambda) || !std::isfinite(distance))
+    return fail(HPT_EINVAL, "bad pitch, wavelength or distance");
+  if (iterations > 100000 || !(lr > 0) || !std::isfinite(lr)) return fail(HPT_EINVAL, "bad iteration count or step");
+  if (flags & ~(HPT_ASM_BAND_LIMIT | HPT_ENCODE_WARM_START)) return fail(HPT_EINVAL, "unknown flags");
+  const uint32_t px = asm_padded(width), py = asm_padded(height);
+  const uint32_t bl = flags & HPT_ASM_BAND_LIMIT;
+  const AsmParams Pf = asm_params(width, height, pitch, lambda, distance, bl, 0.0);
+  const AsmParams Pb = asm_params(width, height, pitch, lambda, -distance, bl, 0.0);
+  const uint32_t hw = width * height;
+  const uint32_t nb = enc_dot_blocks(hw);
+  // per field: target V, phasor a, work field R (complex64), Adam moments m, v
+  // (float), two ASM buffers [h][Px], dot partials, |V|^2, scale
+  const uint64_t per = 32ull * hw + 16ull * height * px + 24ull * nb + 8 + 16;
+  const size_t tw_bytes = (size_t)(px + py) * sizeof(float2);
+  const size_t rel_bytes = (size_t)n_fields * sizeof(double);
+  std::vector<std::pair<void **, size_t>> bufs;
+  float2 *V = nullptr, *a = nullptr, *R = nullptr, *A = nullptr, *B = nullptr, *W = nullptr;
+  float *m = nullptr, *v = nullptr;
+  double *part = nullptr, *vv = nullptr, *rel = nullptr;
+  double2 *sc = nullptr;
+  uint32_t chunk = 0;
+  {
+    std::lock_guard<std::mutex> g(C->mu);
+    (void)hipSetDevice(C->device);
+    const uint64_t fixed = tw_bytes + rel_bytes;
+    uint64_t free_b = C->budget > C->used ? C->budget - C->used : 0;
+    if (free_b < per + fixed) evict_grfs(C, per + fixed);
+    free_b = C->budget > C->used ? C->budget - C->used : 0;
+    free_b = free_b > fixed ? free_b - fixed : 0;
+    chunk = (uint32_t)std::min<uint64_t>({(uint64_t)n_fields, free_b / per, std::max<uint64_t>(1, (1ull << 30) / per)});
+    if (chunk == 0) return fail(HPT_EBUDGET, "encoding scratch does not fit the budget");
+    const size_t f = (size_t)chunk * hw, ap = (size_t)chunk * height * px;
+    bufs = {{(void **)&V, 8 * f}, {(void **)&a, 8 * f}, {(void **)&R, 8 * f}, {(void **)&m, 4 * f},
+            {(void **)&v, 4 * f}, {(void **)&A, 8 * ap}, {(void **)&B, 8 * ap},
+            {(void **)&part, (size_t)chunk * nb * 3 * sizeof(double)}, {(void **)&vv, chunk * sizeof(double)},
+            {(void **)&sc, chunk * sizeof(double2)}, {(void **)&rel, rel_bytes}, {(void **)&W, tw_bytes}};
+    bool ok = true;
+    for (auto &b : bufs) ok = ok && C->alloc(b.first, b.second) == hipSuccess;
+    if (!ok) {
+      for (auto &b : bufs)
+        if (*b.first) C->release(*b.first, b.second);
+      return fail(HPT_ENOMEM, "scratch allocation failed");
+    }
+  }
+  hipStream_t st = C->aux;
+  hipError_t e = launch_asm_twiddles(W, width, height, st);
+  const bool warm = (flags & HPT_ENCODE_WARM_START) != 0;
+  for (uint32_t f0 = 0; f0 < n_fields && e == hipSuccess; f0 += chunk) {
+    const uint32_t nf = std::min(chunk, n_fields - f0);
+    const size_t n = (size_t)nf * hw;
+    const float2 *U = (const float2 *)d_fields + (size_t)f0 * hw;
+    float *phi = (float *)d_phase + (size_t)f0 * hw;
+    e = launch_asm(U, V, A, B, W, nf, width, height, Pf, st);
+    if (e == hipSuccess) e = launch_enc_norm(V, part, vv, nf, hw, st);
+    if (e == hipSuccess) e = launch_enc_init(U, phi, a, n, warm, st);
+    if (e == hipSuccess) e = hipMemsetAsync(m, 0, 4 * n, st);
+    if (e == hipSuccess) e = hipMemsetAsync(v, 0, 4 * n, st);
+    for (uint32_t k = 1; k <= iterations && e == hipSuccess; ++k) {
+      e = launch_asm(a, R, A, B, W, nf, width, height, Pf, st);
+      if (e == hipSuccess) e = launch_enc_scale(R, V, part, vv, sc, rel + f0, nf, hw, st);
+      if (e == hipSuccess) e = launch_enc_residual(R, V, sc, nf, hw, st);
+      if (e == hipSuccess) e = launch_asm(R, R, A, B, W, nf, width, height, Pb, st);
+      const float bc1 = (float)(1.0 - std::pow(0.9, (double)k)), bc2 = (float)(1.0 - std::pow(0.999, (double)k));
+      if (e == hipSuccess) e = launch_enc_adam(phi, m, v, a, R, n, (float)lr, bc1, bc2, st);
+    }
+    if (e == hipSuccess) e = launch_asm(a, R, A, B, W, nf, width, height, Pf, st);
+    if (e == hipSuccess) e = launch_enc_scale(R, V, part, vv, sc, rel + f0, nf, hw, st);
+  }
+  std::vector<double> rel_h(n_fields, 0.0);
+  if (e == hipSuccess) e = hipMemcpyAsync(rel_h.data(), rel, rel_bytes, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  else (void)hipStreamSynchronize(st);  // launches already queued still use the scratch
+  {
+    std::lock_guard<std::mutex> g(C->mu);
+    for (auto &b : bufs) C->release(*b.first, b.second);
+  }
+  if (e != hipSuccess) return fail(HPT_EDEVICE, std::string("encoding failed: ") + hipGetErrorString(e));
+  if (loss_out) std::copy(rel_h.begin(), rel_h.end(), loss_out);
   return HPT_OK;
 }
 
