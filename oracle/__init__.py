@@ -108,6 +108,7 @@ def make_job(job, grf=None):
     J.seed = job["seed"]
     J.random_phase, J.use_cache, J.cache_depth = (job["random_phase"], job["use_cache"],
                                                   job["cache_depth"])
+    J.nee = int(job.get("nee", 0))
     for i in range(4):
         J.crop[i] = job["crop"][i]
     J.spp_begin, J.spp_end = job["spp_begin"], job["spp_end"]

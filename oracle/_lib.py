@@ -25,7 +25,7 @@ class OJob(C.Structure):
                 ("random_phase", C.c_int32), ("use_cache", C.c_int32), ("cache_depth", C.c_int32),
                 ("crop", C.c_int32 * 4), ("spp_begin", C.c_int32), ("spp_end", C.c_int32),
                 ("holo_from_world", C.c_double * 12),
-                ("grf_w", C.c_int32), ("grf_h", C.c_int32), ("grf", C.c_void_p)]
+                ("grf_w", C.c_int32), ("grf_h", C.c_int32), ("grf", C.c_void_p), ("nee", C.c_int32)]
 
 
 class ORecord(C.Structure):

@@ -128,6 +128,10 @@ struct Node {            // binary BVH node (oracle's own, median split)
   int first, count;      // primitive range (leaf)
 };
 
+// Emitter triangle for next-event estimation (unit normal n along
+// (v1 - v0) x (v2 - v0), the side it emits on).
+struct Light { V3 v0, v1, v2, n; double area; int mat; };
+
 struct Scene {
   int n_sph = 0, n_tri = 0;
   std::vector<V3> sc;            // sphere centres
@@ -139,6 +143,9 @@ struct Scene {
   std::vector<Node> nodes;
   std::vector<int> order;        // primitive ids in leaf order
   Box bounds;
+  std::vector<Light> lights;     // emitter triangles in id order
+  std::vector<double> light_cdf; // running sum of their areas
+  double light_area = 0.0;
 };
 
 struct Hit { double t; int gid; };
@@ -477,7 +484,73 @@ struct TraceCtx {
   int max_bounces;
   int cache_depth;
   double tmin;
+  bool nee = false;       // next-event estimation to the emitter triangles, MIS-weighted
 };
+
+// f cos and sampling pdf (solid angle, of the lobe sample_bsdf draws) of the
+// non-delta lobe of m for the direction wl leaving the surface; d_in: the
+// incoming travel direction, cosines against the normal facing it. GGX:
+// f cos = F D G1(V) G1(L) / (4 V.z), pdf = G1(V) D / (4 V.z), so that
+// f cos / pdf is the sampling weight F G1(L).
+struct Eval { double fcos, pdf; };
+Eval eval_bsdf(const Material &m, int comp, V3 d_in, V3 ng, V3 wl) {
+  V3 nf = dot(d_in, ng) < 0 ? ng : -1.0 * ng;
+  double c = dot(wl, nf);
+  if (c <= 0.0) return {0.0, 0.0};
+  if (m.type == LAMBERT) return {m.rgb[comp] * c / M_PI, c / M_PI};
+  if (m.type != GGX) return {0.0, 0.0};
+  V3 b1, b2;
+  onb(nf, b1, b2);
+  V3 wo = -1.0 * d_in;
+  V3 V = {dot(wo, b1), dot(wo, b2), dot(wo, nf)};
+  V3 L = {dot(wl, b1), dot(wl, b2), c};
+  if (V.z <= 0.0) return {0.0, 0.0};
+  V3 H = normalize(V + L);
+  double a2 = m.rough * m.rough;
+  double k = H.z * H.z * (a2 - 1.0) + 1.0;
+  double D = a2 / (M_PI * k * k);
+  double f0 = m.rgb[comp];
+  double F = f0 + (1.0 - f0) * std::pow(1.0 - std::max(0.0, dot(V, H)), 5.0);
+  double pdf = smith_g1(V, m.rough) * D / (4.0 * V.z);
+  return {pdf * F * smith_g1(L, m.rough), pdf};
+}
+
+// Next-event estimate at the non-delta vertex x (material m, primitive gid,
+// reached along d_in): an emitter triangle chosen with probability
+// proportional to area (u0), a point uniform on it (u1, u2), the
+// unoccluded one-sided emission times f cos over the light pdf
+// dist^2 / (cos_y A_total), weighted by the power heuristic against the
+// lobe's pdf. The light index and visibility enter the signature.
+double next_event(const TraceCtx &X, const Material &m, int comp, V3 x, V3 d_in, V3 ng, int gid,
+                  const double u[3], uint64_t &sig) {
+  const Scene &S = *X.S;
+  int n = (int)S.lights.size();
+  int i = (int)(std::upper_bound(S.light_cdf.begin(), S.light_cdf.end(), u[0] * S.light_area) -
+                S.light_cdf.begin());
+  i = std::min(i, n - 1);
+  const Light &l = S.lights[i];
+  double su = std::sqrt(u[1]);
+  V3 y = (1.0 - su) * l.v0 + (su * (1.0 - u[2])) * l.v1 + (su * u[2]) * l.v2;
+  V3 om = y - x;
+  double dist = std::sqrt(dot(om, om));
+  om = (1.0 / dist) * om;
+  double cos_y = -dot(om, l.n);
+  Eval e = eval_bsdf(m, comp, d_in, ng, om);
+  bool vis = false;
+  double c = 0.0;
+  if (cos_y > 0.0 && e.fcos > 0.0) {
+    int excl = gid >= S.n_sph ? gid : -1;
+    Hit h = closest_hit(S, x, om, X.tmin, excl, false);
+    vis = !(h.gid >= 0 && h.t < dist * (1.0 - 1e-4));
+    if (vis) {
+      double pl = dist * dist / (cos_y * S.light_area);
+      double wl = pl * pl / (pl * pl + e.pdf * e.pdf);
+      c = S.mats[l.mat].emit[comp] * e.fcos * wl / pl;
+    }
+  }
+  sig_add(sig, 0x60000000u | (vis ? 0x800000u : 0u) | (uint32_t)i);
+  return c;
+}
 
 double cache_lookup(Cache &C, int comp, int cell, int bin);
 
@@ -493,12 +566,22 @@ double radiance_tail(const TraceCtx &X, V3 x, V3 d_in, int gid, int b, int bP, i
   const Scene &S = *X.S;
   double L = 0.0, beta = 1.0;
   double eta = 1.0;
+  const bool nee = X.nee && !S.lights.empty();
+  double prev_pdf = 0.0, prev_t = 0.0;   // lobe pdf and length of the segment that led here (0: no MIS)
   for (;;) {
     const Material &m = S.mats[S.prim_mat[gid]];
     V3 ng = geom_normal(S, gid, x);
     if (m.type == EMITTER) {
       sig_add(sig, EV_EMIT);
-      if (dot(d_in, ng) < 0) L += beta * m.emit[comp];
+      double cos_y = -dot(d_in, ng);
+      if (cos_y > 0) {
+        double wb = 1.0;   // power-heuristic weight of a lobe sample that next-event estimation also covers
+        if (nee && prev_pdf > 0.0 && gid >= S.n_sph) {
+          double pl = prev_t * prev_t / (cos_y * S.light_area);
+          wb = prev_pdf * prev_pdf / (prev_pdf * prev_pdf + pl * pl);
+        }
+        L += beta * m.emit[comp] * wb;
+      }
       kind = K_EMITTER;
       return L;
     }
@@ -511,10 +594,20 @@ double radiance_tail(const TraceCtx &X, V3 x, V3 d_in, int gid, int b, int bP, i
     for (int i = 0; i < 4; ++i) U.u[i] = u01(w[i]);
     Sampled s = sample_bsdf(m, comp, d_in, ng, U, eta);
     sig_add(sig, (uint32_t)s.ev);
+    const bool cache_here = X.cache && !s.delta && (b - bP + 1) >= X.cache_depth;
+    const bool nee_here = nee && !s.delta && !cache_here;
+    if (nee_here) {
+      uint32_t c1[4] = {key_a, key_b, ((uint32_t)b << 8) | 1u, stream_word};
+      uint32_t w1[4];
+      philox4x32_10(c1, key, w1);
+      double un[3] = {u01(w1[0]), u01(w1[1]), u01(w1[2])};
+      L += beta * next_event(X, m, comp, x, d_in, ng, gid, un, sig);
+    }
     if (s.w == 0.0) { kind = K_ABSORBED; return L; }
+    prev_pdf = nee_here ? eval_bsdf(m, comp, d_in, ng, s.d).pdf : 0.0;
     beta *= s.w;
     if (s.ev == EV_DIEL_REFR) eta = s.eta_t;
-    if (X.cache && !s.delta && (b - bP + 1) >= X.cache_depth) {
+    if (cache_here) {
       int cell = cell_of(*X.cache, x), bin = oct_bin(s.d, X.cache->P.bins);
       if (cell_out) *cell_out = cell;
       if (bin_out) *bin_out = bin;
@@ -533,6 +626,7 @@ double radiance_tail(const TraceCtx &X, V3 x, V3 d_in, int gid, int b, int bP, i
     x = x + h.t * s.d;
     d_in = s.d;
     gid = h.gid;
+    prev_t = h.t;
   }
 }
 
@@ -606,6 +700,7 @@ struct OJob {
   double holo_from_world[12];
   int32_t grf_w, grf_h;
   const double *grf;        // complex128 [grf_h][grf_w][T] interleaved re, im
+  int32_t nee;              // next-event estimation with MIS in the tail
 };
 
 struct ORecord {           // one per (channel, pixel, sample) path
@@ -636,6 +731,21 @@ void *oracle_scene_create(const OScene *d) {
     S->mats.push_back(m);
   }
   for (int c = 0; c < 3; ++c) S->env[c] = d->env[c];
+  for (int i = 0; i < S->n_tri; ++i) {
+    int mi = S->prim_mat[S->n_sph + i];
+    if (S->mats[mi].type != EMITTER) continue;
+    Light l;
+    l.v0 = S->tv[3 * i]; l.v1 = S->tv[3 * i + 1]; l.v2 = S->tv[3 * i + 2];
+    V3 cr = cross(l.v1 - l.v0, l.v2 - l.v0);
+    double a2 = std::sqrt(dot(cr, cr));
+    if (!(a2 > 0.0)) continue;
+    l.n = (1.0 / a2) * cr;
+    l.area = 0.5 * a2;
+    l.mat = mi;
+    S->light_area += l.area;
+    S->lights.push_back(l);
+    S->light_cdf.push_back(S->light_area);
+  }
   int n = S->n_sph + S->n_tri;
   if (n > 0) {
     std::vector<Box> pb(n);
@@ -831,6 +941,7 @@ int32_t oracle_trace(void *scene, void *cache, const OJob *J, double *field, ORe
   affine_inverse(J->holo_from_world, Tinv);
   const double d = J->pitch;
   TraceCtx X{S, (J->use_cache && C) ? C : nullptr, J->max_bounces, J->cache_depth, 1e-7};
+  X.nee = J->nee != 0;
   std::memset(field, 0, sizeof(double) * 2 * (size_t)J->n_ch * J->T * cw * ch);
   int nt = n_threads > 0 ? n_threads : omp_get_max_threads();
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nt)

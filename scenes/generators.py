@@ -420,6 +420,24 @@ def scene_lambert_plane(z0, rgb, env=1.0, half=5 * MM):
     return b.finish(env=(env,) * 3)
 
 
+def scene_lit_plane(z0, material, light=(1 * MM, 3 * MM, -1 * MM, 1 * MM), h=2 * MM, emit=1.0,
+                    blocker=False, half=5 * MM):
+    """A plane at depth z0 facing the SLM (material: (type, rgb, rough)) lit
+    by a rectangular emitter [x1, x2] x [y1, y2] at depth z0 - h facing the
+    plane (+z), beside the SLM's view of the plane; environment black.
+    blocker: a black Lambert sheet halfway between them over the light's side."""
+    b = _Builder()
+    m = b.material(material[0], rgb=material[1], rough=material[2] if len(material) > 2 else 0.0)
+    b.add_quad((-half, -half, z0), (0, 2 * half, 0), (2 * half, 0, 0), m)
+    x1, x2, y1, y2 = light
+    e = b.material(EMITTER, emit=(emit,) * 3)
+    b.add_quad((x1, y1, z0 - h), (x2 - x1, 0, 0), (0, y2 - y1, 0), e)   # normal +z
+    if blocker:
+        k = b.material(LAMBERT, rgb=(0.0, 0.0, 0.0))
+        b.add_quad((0.3 * MM, y1 - half, z0 - h / 2), (0, y2 - y1 + 2 * half, 0), (x2, 0, 0), k)
+    return b.finish()
+
+
 def scene_single_tri(z0, size=0.2 * MM, env=1.0, albedo=1.0):
     b = _Builder()
     m = b.material(LAMBERT, rgb=(albedo,) * 3)

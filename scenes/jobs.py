@@ -16,7 +16,7 @@ JOB_DEFAULTS = dict(
     spp=16, max_bounces=2, T=1,
     seed=0, grf_seed=0, grf_w=0, grf_h=0,
     phase_mode=PHASE_FP64, random_phase=1,
-    use_cache=0, cache_depth=1,
+    use_cache=0, cache_depth=1, nee=0,
     crop=(0, 0, 0, 0), spp_begin=0, spp_end=0,
     holo_from_world=(1.0, 0.0, 0.0, 0.0,
                      0.0, 1.0, 0.0, 0.0,
