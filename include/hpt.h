@@ -147,6 +147,16 @@ typedef struct {
   double holo_from_world[12];      /* Eq. 3: affine T, row-major 3x4, x_holo = T x_world */
   uint32_t debug;           /* bit 0: per-path records (<= 2^22 paths); bit 1: per-path
                                per-frame contributions; bit 2: per-pixel signature sums */
+  uint32_t nee;             /* 1: next-event estimation in the incoherent tail. At every
+                               non-delta tail vertex that is not ended by the radiance cache
+                               and has interactions left, one emitter triangle is chosen with
+                               probability proportional to area and a point uniform on it;
+                               its unoccluded one-sided emission times f cos / pdf_light is
+                               added with the power-heuristic weight against the lobe pdf,
+                               and emission reached by a lobe sample from such a vertex gets
+                               the complementary weight (Eq. 1 by two combined estimators).
+                               Random numbers: Philox counter (interaction << 8) | 1.
+                               0: BSDF sampling only. */
 } hpt_job_desc;
 
 typedef struct {

@@ -53,7 +53,7 @@ class JobDesc(C.Structure):
                 ("phase_mode", C.c_uint32), ("random_phase", C.c_uint32),
                 ("use_cache", C.c_uint32), ("cache_depth", C.c_uint32),
                 ("crop", C.c_uint32 * 4), ("spp_begin", C.c_uint32), ("spp_end", C.c_uint32),
-                ("holo_from_world", C.c_double * 12), ("debug", C.c_uint32)]
+                ("holo_from_world", C.c_double * 12), ("debug", C.c_uint32), ("nee", C.c_uint32)]
 
 
 class JobStats(C.Structure):
@@ -172,6 +172,7 @@ def job_desc(job):
     for i in range(12):
         d.holo_from_world[i] = job["holo_from_world"][i]
     d.debug = job.get("debug", 0)
+    d.nee = job.get("nee", 0)
     return d
 
 

@@ -419,6 +419,43 @@ __device__ __forceinline__ Lobe sample_lobe(const MaterialDev &m, uint32_t comp,
   return L;
 }
 
+// f cos and the pdf (solid angle) with which sample_lobe draws the direction
+// wl leaving a non-delta surface (cosines against the normal facing the
+// incoming ray d_in). GGX: f cos = F D G1(V) G1(L) / (4 V.z) and
+// pdf = G1(V) D / (4 V.z), whose ratio is the sampling weight F G1(L).
+struct BsdfEval { float fcos, pdf; };
+__device__ __forceinline__ BsdfEval eval_lobe(const MaterialDev &m, uint32_t comp, F3 d_in, F3 ng, F3 wl) {
+  BsdfEval e{0.f, 0.f};
+  F3 nf = dot(d_in, ng) < 0.f ? ng : (-1.0f) * ng;
+  float c = dot(wl, nf);
+  if (c <= 0.f) return e;
+  float rgb = comp == 0 ? m.rgb[0] : (comp == 1 ? m.rgb[1] : m.rgb[2]);
+  const float inv_pi = 0.318309886183790672f;
+  if (m.type == HPT_LAMBERT) {
+    e.fcos = rgb * c * inv_pi;
+    e.pdf = c * inv_pi;
+  } else if (m.type == HPT_GGX) {
+    F3 b1, b2;
+    onb(nf, b1, b2);
+    F3 wo = (-1.0f) * d_in;
+    F3 V = f3(dot(wo, b1), dot(wo, b2), dot(wo, nf));
+    if (V.z <= 0.f) return e;
+    F3 Lw = f3(dot(wl, b1), dot(wl, b2), c);
+    F3 H = normalize(V + Lw);
+    float a = m.rough, a2 = a * a;
+    float k = H.z * H.z * (a2 - 1.0f) + 1.0f;
+    float D = a2 * inv_pi / (k * k);
+    float x = 1.0f - fmaxf(0.f, dot(V, H));
+    float x2 = x * x;
+    float F = rgb + (1.0f - rgb) * (x2 * x2 * x);
+    float g1v = 2.0f * V.z / (V.z + sqrtf(a2 * (V.x * V.x + V.y * V.y) + V.z * V.z));
+    float g1l = 2.0f * Lw.z / (Lw.z + sqrtf(a2 * (Lw.x * Lw.x + Lw.y * Lw.y) + Lw.z * Lw.z));
+    e.pdf = g1v * D / (4.0f * V.z);
+    e.fcos = e.pdf * F * g1l;
+  }
+  return e;
+}
+
 // Octahedral map of a unit direction to a bins x bins grid.
 __device__ __forceinline__ uint32_t oct_bin(F3 w, uint32_t bins) {
   float s = fabsf(w.x) + fabsf(w.y) + fabsf(w.z);

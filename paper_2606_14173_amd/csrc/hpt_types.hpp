@@ -77,6 +77,11 @@ struct SceneDev {
   uint32_t cache_res, cache_bins;
   float cache_lo[3], cache_scale[3];   // cell index = floor((x - lo) * scale)
   double cache_lo_d[3], cache_hi_d[3];
+  // emitter triangles for next-event estimation, in primitive id order
+  const float4 *lights;      // 4 x float4 per light: v0, v1, v2, unit normal (w: material index bits)
+  const double *light_cdf;   // running sum of the light areas
+  uint32_t n_lights, pad2;
+  double light_area;
 };
 
 // Device view of a job (or of a cache build).
@@ -102,7 +107,8 @@ struct JobDev {
   const SceneDev *scene;
   // cache build
   uint16_t *cache_out;       // [3][res^3][bins^2]
-  uint32_t cache_res, cache_bins, cache_spb, pad1;
+  uint32_t cache_res, cache_bins, cache_spb;
+  uint32_t nee;              // next-event estimation with MIS in the tail
 };
 
 // A contiguous block of paths of one job: pixels [p_lo, p_lo + p_n) of the
@@ -128,6 +134,7 @@ struct RayQueue {
   float *bpre;                     // beta_pre: product of the delta weights
   float *wt;                       // medium index in the prefix, then the weight W
   float *beta, *L;                 // tail throughput and radiance
+  float *pdf;                      // lobe pdf of the ray if next-event estimation covers it (MIS), else 0
   double *ox, *oy, *oz, *dx, *dy, *dz, *ell, *al, *be;
   float4 *ray;                     // 2 per entry: (o, tmin), (d, exclude id bits), traversal input
   float *t;                        // hit distance

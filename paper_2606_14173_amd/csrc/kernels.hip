@@ -104,15 +104,18 @@ struct RayState {
   uint32_t slot, unit, meta;
   unsigned long long sig;
   float bpre, wt, beta, L;   // wt: medium index while in the prefix, then the weight W
+  float pdf;                 // lobe pdf of this ray when next-event estimation covers it, else 0
   D3 o, d;                   // FP64 ray of the coherent prefix
   double ell;
 };
 
+template <bool NEE>
 __device__ __forceinline__ void load_state(const RayQueue &Q, uint32_t i, RayState &r) {
   r.i = i;
   r.slot = Q.slot[i]; r.unit = Q.unit[i]; r.meta = Q.meta[i];
   r.sig = Q.sig[i];
   r.bpre = Q.bpre[i]; r.wt = Q.wt[i]; r.beta = Q.beta[i]; r.L = Q.L[i];
+  r.pdf = (NEE && (r.meta & 1u) == STAGE_TAIL) ? Q.pdf[i] : 0.f;
   if ((r.meta & 1u) == STAGE_PREFIX) {
     r.o = D3{Q.ox[i], Q.oy[i], Q.oz[i]};
     r.d = D3{Q.dx[i], Q.dy[i], Q.dz[i]};
@@ -200,6 +203,7 @@ __device__ __forceinline__ void gen_path(const BatchDev &B, uint32_t i, RayState
   st.wt = 1.0f;  // refractive index of the current medium while in the prefix
   st.beta = 1.f;
   st.L = 0.f;
+  st.pdf = 0.f;
   if (U.kind == UNIT_HOLO) {
     uint32_t comp = J.comp[U.ch];
     uint32_t cx, cy;
@@ -266,7 +270,7 @@ __device__ __forceinline__ void load_first(const BatchDev &B, const RayQueue &Q,
   r.i = i;
   r.slot = Q.slot[i]; r.unit = Q.unit[i];
   r.sig = kSigInit;
-  r.bpre = 1.f; r.wt = 1.f; r.beta = 1.f; r.L = 0.f;
+  r.bpre = 1.f; r.wt = 1.f; r.beta = 1.f; r.L = 0.f; r.pdf = 0.f;
   const UnitDev &U = B.units[r.unit];
   if (U.kind == UNIT_HOLO) {
     const JobDev &J = Jl ? *Jl : *U.job;
@@ -416,7 +420,7 @@ struct Emit { bool on; };
 struct StageLds {
   uint32_t i[kBlock], slot[kBlock], unit[kBlock], meta[kBlock];
   unsigned long long sig[kBlock];
-  float bpre[kBlock], wt[kBlock], beta[kBlock], L[kBlock];
+  float bpre[kBlock], wt[kBlock], beta[kBlock], L[kBlock], pdf[kBlock];
   double ox[kBlock], oy[kBlock], oz[kBlock], dx[kBlock], dy[kBlock], dz[kBlock], ell[kBlock];
   float rox[kBlock], roy[kBlock], roz[kBlock], rdx[kBlock], rdy[kBlock], rdz[kBlock];
   int32_t excl[kBlock];
@@ -426,7 +430,7 @@ __device__ __forceinline__ void stage_put(StageLds &G, const RayState &r, F3 o, 
   const uint32_t t = threadIdx.x;
   G.i[t] = r.i; G.slot[t] = r.slot; G.unit[t] = r.unit; G.meta[t] = r.meta;
   G.sig[t] = r.sig;
-  G.bpre[t] = r.bpre; G.wt[t] = r.wt; G.beta[t] = r.beta; G.L[t] = r.L;
+  G.bpre[t] = r.bpre; G.wt[t] = r.wt; G.beta[t] = r.beta; G.L[t] = r.L; G.pdf[t] = r.pdf;
   if ((r.meta & 1u) == STAGE_PREFIX) {
     G.ox[t] = r.o.x; G.oy[t] = r.o.y; G.oz[t] = r.o.z;
     G.dx[t] = r.d.x; G.dy[t] = r.d.y; G.dz[t] = r.d.z;
@@ -440,12 +444,14 @@ __device__ __forceinline__ void stage_put(StageLds &G, const RayState &r, F3 o, 
 
 // Entry k of queue Q from this lane's staged ray; the read-only words come
 // from its entry in the source queue S.
+template <bool NEE>
 __device__ __forceinline__ void stage_store(const StageLds &G, const RayQueue &Q, uint32_t k, const RayQueue &S) {
   const uint32_t t = threadIdx.x, i = G.i[t], meta = G.meta[t];
   Q.slot[k] = G.slot[t]; Q.unit[k] = G.unit[t]; Q.meta[k] = meta;
   Q.ka[k] = S.ka[i]; Q.kb[k] = S.kb[i];
   Q.sig[k] = G.sig[t];
   Q.bpre[k] = G.bpre[t]; Q.wt[k] = G.wt[t]; Q.beta[k] = G.beta[t]; Q.L[k] = G.L[t];
+  if (NEE) Q.pdf[k] = G.pdf[t];
   if ((meta & 1u) == STAGE_PREFIX) {
     Q.ox[k] = G.ox[t]; Q.oy[k] = G.oy[t]; Q.oz[k] = G.oz[t];
     Q.dx[k] = G.dx[t]; Q.dy[k] = G.dy[t]; Q.dz[k] = G.dz[t];
@@ -583,19 +589,78 @@ __device__ __forceinline__ void image_point(const BatchDev &B, const RayQueue &Q
 
 // One interaction of the incoherent tail at x (index b), reached along d_in
 // on primitive gid. Returns a ray to trace in `e`, or finishes the path.
+// Next-event estimate at the non-delta tail vertex x (material m, primitive
+// gid, reached along d_in): an emitter triangle chosen with probability
+// proportional to area, a point uniform on it; its unoccluded one-sided
+// emission times f cos over the light pdf dist^2 / (cos_y A_total), with
+// the power-heuristic weight against the lobe pdf. The occlusion query is a
+// traversal of the whole BVH limited to the segment (stack St). The light
+// index and visibility enter the signature.
+__device__ float next_event(const SceneDev &S, const MaterialDev &m, uint32_t comp, F3 x, F3 d_in, F3 ng,
+                            int32_t gid, U4 w, const Stack &St, unsigned long long &sig) {
+  const double u0 = ud(w.x) * S.light_area;
+  uint32_t lo = 0, hi = S.n_lights;  // first light whose running area exceeds u0
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (S.light_cdf[mid] > u0) hi = mid; else lo = mid + 1;
+  }
+  const uint32_t li = min(lo, S.n_lights - 1u);
+  const float4 *Lp = S.lights + 4 * li;
+  const float4 v0 = Lp[0], v1 = Lp[1], v2 = Lp[2], nn = Lp[3];
+  const float su = sqrtf(uf(w.y)), u2 = uf(w.z);
+  const F3 y = (1.0f - su) * f3(v0.x, v0.y, v0.z) + (su * (1.0f - u2)) * f3(v1.x, v1.y, v1.z) +
+               (su * u2) * f3(v2.x, v2.y, v2.z);
+  F3 om = y - x;
+  const float dist = sqrtf(dot(om, om));
+  om = (1.0f / dist) * om;
+  const float cos_y = -dot(om, f3(nn.x, nn.y, nn.z));
+  const BsdfEval e = eval_lobe(m, comp, d_in, ng, om);
+  bool vis = false;
+  float c = 0.f;
+  if (cos_y > 0.f && e.fcos > 0.f) {
+    Trav T;
+    trav_init(T, x, om, kTmin, gid >= (int32_t)S.n_sph ? gid : -1, S.n_nodes == 0);
+    T.best.t = dist * (1.0f - 1e-4f);
+    const GF4 N = as_global(S.nodes), P = as_global(S.prims);
+    uint32_t nv = 0, nt = 0;
+    while (T.node != kDone && T.best.prim < 0) trav_step<false>(T, N, P, St, nv, nt);
+    vis = T.best.prim < 0;
+    if (vis) {
+      const float pl = dist * dist / (cos_y * (float)S.light_area);
+      const float wl = pl * pl / (pl * pl + e.pdf * e.pdf);
+      const MaterialDev &lm = S.mats[__float_as_uint(nn.w)];
+      const float le = comp == 0 ? lm.emit[0] : (comp == 1 ? lm.emit[1] : lm.emit[2]);
+      c = le * e.fcos * wl / pl;
+    }
+  }
+  sig_add(sig, 0x60000000u | (vis ? 0x800000u : 0u) | li);
+  return c;
+}
+
+template <bool NEE>
 __device__ __forceinline__ void tail_interaction(const BatchDev &B, const RayQueue &Q, StageLds &G,
                                                  const UnitDev &U, const JobDev &J, const SceneDev &S,
                                                  RayState &st, F3 x, F3 d_in,
                                                  const HitRec &H, uint32_t b, uint32_t bP, uint32_t comp,
                                                  uint32_t stream, float beta, float L,
-                                                 unsigned long long sig, Emit &e) {
+                                                 unsigned long long sig, float t_seg, const Stack *St,
+                                                 Emit &e) {
   const int32_t gid = H.gid;
   const MaterialDev m = S.mats[H.mat];
   F3 ng = hit_normal32(S, H, x);
   bool holo = U.kind == UNIT_HOLO;
+  const bool nee = NEE && J.nee && S.n_lights > 0;
   if (m.type == HPT_EMITTER) {
     sig_add(sig, EV_EMIT);
-    if (dot(d_in, ng) < 0.f) L += beta * (comp == 0 ? m.emit[0] : (comp == 1 ? m.emit[1] : m.emit[2]));
+    const float cos_y = -dot(d_in, ng);
+    if (cos_y > 0.f) {
+      float wb = 1.f;  // power-heuristic weight of a lobe sample that next-event estimation also covers
+      if (nee && st.pdf > 0.f && gid >= (int32_t)S.n_sph) {
+        const float pl = t_seg * t_seg / (cos_y * (float)S.light_area);
+        wb = st.pdf * st.pdf / (st.pdf * st.pdf + pl * pl);
+      }
+      L += beta * (comp == 0 ? m.emit[0] : (comp == 1 ? m.emit[1] : m.emit[2])) * wb;
+    }
     finish(B, U, J, st, K_EMITTER, b, L, sig, holo);
     return;
   }
@@ -603,9 +668,16 @@ __device__ __forceinline__ void tail_interaction(const BatchDev &B, const RayQue
   U4 w = philox(Q.ka[st.i], Q.kb[st.i], b << 8, stream, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
   Lobe lb = sample_lobe(m, comp, d_in, ng, uf(w.x), uf(w.y), uf(w.z));
   sig_add(sig, lb.ev);
+  const bool cache_here = holo && J.use_cache && !lb.delta && (b - bP + 1) >= J.cache_depth;
+  const bool nee_here = nee && !lb.delta && !cache_here;
+  if (NEE && nee_here) {
+    U4 wn = philox(Q.ka[st.i], Q.kb[st.i], (b << 8) | 1u, stream, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
+    L += beta * next_event(S, m, comp, x, d_in, ng, gid, wn, *St, sig);
+  }
   if (lb.w == 0.f) { finish(B, U, J, st, K_ABSORBED, b, L, sig, holo); return; }
+  st.pdf = (NEE && nee_here) ? eval_lobe(m, comp, d_in, ng, lb.d).pdf : 0.f;
   beta *= lb.w;
-  if (holo && J.use_cache && !lb.delta && (b - bP + 1) >= J.cache_depth) {
+  if (cache_here) {
     uint32_t res = S.cache_res, nb = S.cache_bins * S.cache_bins;
     int ix = (int)floorf((x.x - S.cache_lo[0]) * S.cache_scale[0]);
     int iy = (int)floorf((x.y - S.cache_lo[1]) * S.cache_scale[1]);
@@ -637,8 +709,9 @@ __device__ __forceinline__ void tail_interaction(const BatchDev &B, const RayQue
 // Shade entry i of queue q, whose state is st; st is updated in place for a
 // path that continues (e.on). Jl: the batch's one job in LDS (its scene and
 // materials too), or null when the batch mixes jobs.
+template <bool NEE>
 __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, RayState &st, StageLds &G,
-                                          const JobDev *Jl, Emit &e) {
+                                          const JobDev *Jl, const Stack *St, Emit &e) {
   const UnitDev &U = B.units[st.unit];
   const JobDev &J = Jl ? *Jl : *U.job;
   const SceneDev &S = *J.scene;
@@ -721,7 +794,8 @@ __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, 
     // first non-delta hit: the real image point P
     sig_add(sig, EV_IMAGE_POINT);
     image_point(B, Q, U, J, st, ell, b);
-    tail_interaction(B, Q, G, U, J, S, st, to_f(x), to_f(d), H, b, b, comp, stream, 1.0f, 0.0f, sig, e);
+    tail_interaction<NEE>(B, Q, G, U, J, S, st, to_f(x), to_f(d), H, b, b, comp, stream, 1.0f, 0.0f, sig, t, St,
+                          e);
     return;
   }
   // incoherent tail (or cache path)
@@ -737,14 +811,19 @@ __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, 
   sig_add(sig, (uint32_t)gid + 1u);
   F3 d_in = f3(r1.x, r1.y, r1.z);
   F3 x = f3(r0.x, r0.y, r0.z) + t * d_in;
-  tail_interaction(B, Q, G, U, J, S, st, x, d_in, H, b, bP, comp, stream, beta, L, sig, e);
+  tail_interaction<NEE>(B, Q, G, U, J, S, st, x, d_in, H, b, bP, comp, stream, beta, L, sig, t, St, e);
 }
 
 constexpr uint32_t kLdsMats = 64;  // materials a workgroup keeps in LDS
 
-template <bool FIRST>
+// NEE: batches with next-event estimation. Shading then runs occlusion
+// queries: the traversal stack takes kStackLds entries per lane in LDS and
+// the lane's column of the traversal spill, so the grid is capped at the
+// spill's columns and walks the queue with a plain grid stride.
+template <bool FIRST, bool NEE>
 __global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
   __shared__ StageLds G;
+  __shared__ int32_t nee_stack[NEE ? kStackLds * kBlock : 1];
   __shared__ JobDev lds_job;
   __shared__ SceneDev lds_scene;
   __shared__ MaterialDev lds_mats[kLdsMats];
@@ -759,9 +838,11 @@ __global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
   // takes one contiguous eighth of the queue.
   const uint32_t nb8 = ((n + blockDim.x - 1) / blockDim.x + 7u) & ~7u;
   const uint32_t b = blockIdx.x;
-  const uint32_t blk = b < nb8 ? (b % 8u) * (nb8 / 8u) + b / 8u : b;
-  const uint32_t stride = max(gridDim.x, nb8) * blockDim.x;
+  const uint32_t blk = NEE ? b : (b < nb8 ? (b % 8u) * (nb8 / 8u) + b / 8u : b);
+  const uint32_t stride = NEE ? gridDim.x * blockDim.x : max(gridDim.x, nb8) * blockDim.x;
   if (blk * blockDim.x >= n) return;  // no entries for this workgroup
+  const Stack St{(LdsI32)(nee_stack + (NEE ? threadIdx.x : 0u)), kBlock,
+                 (GlbI32)(B.stack_spill + blockIdx.x * blockDim.x + threadIdx.x), B.spill_threads};
   // A batch of one job: its job, scene and material descriptors are copied
   // to LDS once per workgroup, so shading reads them without the dependent
   // global loads unit -> job -> scene -> material.
@@ -793,8 +874,8 @@ __global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
     if (live) {
       RayState st;
       if (FIRST) load_first(B, B.Q[q], i, st, Jl);
-      else load_state(B.Q[q], i, st);
-      shade_one(B, q, i, st, G, Jl, e);
+      else load_state<NEE>(B.Q[q], i, st);
+      shade_one<NEE>(B, q, i, st, G, Jl, &St, e);
     }
     // compaction: wave counts from ballots, one atomic per workgroup (all
     // workgroups add to the same counter, so fewer atomics is what matters)
@@ -809,7 +890,7 @@ __global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
     }
     __syncthreads();
     const uint32_t before = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-    if (e.on) stage_store(G, B.Q[qo], wave_base[kBlock / 64] + wave_base[wv] + before, B.Q[q]);
+    if (e.on) stage_store<NEE>(G, B.Q[qo], wave_base[kBlock / 64] + wave_base[wv] + before, B.Q[q]);
   }
 }
 
@@ -1049,11 +1130,19 @@ hipError_t launch_trace(const BatchDev &B, int q, bool count, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_shade(const BatchDev &B, int q, bool first, hipStream_t st) {
-  if (first)
-    hipLaunchKernelGGL(k_shade<true>, dim3(round8(grid_for(B.n_paths))), dim3(kBlock), 0, st, B, q);
-  else
-    hipLaunchKernelGGL(k_shade<false>, dim3(round8(grid_for(B.n_paths))), dim3(kBlock), 0, st, B, q);
+hipError_t launch_shade(const BatchDev &B, int q, bool first, bool nee, hipStream_t st) {
+  const uint32_t g = round8(grid_for(B.n_paths));
+  if (nee) {
+    const uint32_t gn = min(g, B.spill_threads / (uint32_t)kBlock);  // one spill column per lane
+    if (first)
+      hipLaunchKernelGGL((k_shade<true, true>), dim3(gn), dim3(kBlock), 0, st, B, q);
+    else
+      hipLaunchKernelGGL((k_shade<false, true>), dim3(gn), dim3(kBlock), 0, st, B, q);
+  } else if (first) {
+    hipLaunchKernelGGL((k_shade<true, false>), dim3(g), dim3(kBlock), 0, st, B, q);
+  } else {
+    hipLaunchKernelGGL((k_shade<false, false>), dim3(g), dim3(kBlock), 0, st, B, q);
+  }
   return hipGetLastError();
 }
 

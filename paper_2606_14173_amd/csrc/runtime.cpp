@@ -52,7 +52,7 @@ constexpr uint32_t kMaxUnitsPerBatch = 4096;
 // per path, in two sets: final signature, first hit, results; per queue
 // entry (two queues): state (40 B), FP64 prefix ray (72 B), FP32 ray (32 B),
 // hit (8 B)
-constexpr size_t kBytesPerPath = 2 * (8 + 4 + 4 + 8 + 16 + 4 + 4 + 4) + 2 * (40 + 72 + 32 + 8);
+constexpr size_t kBytesPerPath = 2 * (8 + 4 + 4 + 8 + 16 + 4 + 4 + 4) + 2 * (44 + 72 + 32 + 8);
 
 struct Scene {
   uint64_t id = 0;
@@ -171,7 +171,7 @@ struct hpt_ctx {
     unsigned long long *h_work = nullptr; // pinned: node visits, primitive tests
     hipEvent_t ev0 = nullptr, ev_rg = nullptr, ev_shade = nullptr, ev_done = nullptr;
     BatchDev B{};               // the batch's device view (for its accumulation)
-    bool has_f64 = false, has_f32 = false;
+    bool has_f64 = false, has_f32 = false, has_nee = false;
     bool acc_pending = false;   // accumulation not enqueued yet
     hipEvent_t pev[kEvents] = {};
     int ne = 0;
@@ -373,12 +373,24 @@ hpt_status admit(hpt_ctx *C, Job *J) {
   return HPT_OK;
 }
 
-// Fill one batch round-robin over the running jobs.
+// Fill one batch round-robin over the running jobs. A batch holds jobs of
+// one next-event-estimation mode (the shading kernel differs, and a job's
+// results must not depend on what it shares a batch with); the mode is that
+// of the first job with units left, counted from a start that moves with
+// every batch so that neither mode waits for the other to drain.
 std::vector<Picked> pick_batch(hpt_ctx *C) {
   std::vector<Picked> out;
   uint64_t paths = 0;
   std::vector<std::vector<uint32_t>> keys(C->running.size());
   std::vector<bool> blocked(C->running.size(), false);
+  const size_t nr = C->running.size();
+  int mode = -1;
+  for (size_t k = 0; k < nr && mode < 0; ++k) {
+    const Job *J = C->running[(C->batches + k) % nr];
+    if (!J->cancel && J->next < J->units.size()) mode = J->host.nee ? 1 : 0;
+  }
+  for (size_t j = 0; j < nr; ++j)
+    if ((C->running[j]->host.nee ? 1 : 0) != mode) blocked[j] = true;
   bool progress = true;
   while (progress && out.size() < kMaxUnitsPerBatch) {
     progress = false;
@@ -447,7 +459,7 @@ hpt_status launch_batch(hpt_ctx *C, int si, int prev) {
   hpt_ctx::Slot &L = C->slots[si];
   const std::vector<Picked> &P = L.P;
   uint32_t slot = 0, acc = 0, max_b = 0;
-  L.has_holo = L.has_cache = L.has_f64 = L.has_f32 = false;
+  L.has_holo = L.has_cache = L.has_f64 = L.has_f32 = L.has_nee = false;
   for (size_t k = 0; k < P.size(); ++k) {
     const Unit &u = P[k].job->units[P[k].unit];
     UnitDev &d = L.h_units[k];
@@ -460,6 +472,7 @@ hpt_status launch_batch(hpt_ctx *C, int si, int prev) {
     if (u.kind == UNIT_HOLO) {
       L.has_holo = true;
       if (J.phase_mode == HPT_PHASE_FP64) L.has_f64 = true; else L.has_f32 = true;
+      if (J.nee) L.has_nee = true;
     } else {
       L.has_cache = true;
     }
@@ -494,7 +507,7 @@ hpt_status launch_batch(hpt_ctx *C, int si, int prev) {
   for (uint32_t it = 0; it <= max_b; ++it) {
     int q = (int)(it & 1u);
     timed_launch(L, HPT_K_TRACE, S, e, [&] { return launch_trace(B, q, profile >= 2, S); });
-    timed_launch(L, HPT_K_SHADE, S, e, [&] { return launch_shade(B, q, it == 0, S); });
+    timed_launch(L, HPT_K_SHADE, S, e, [&] { return launch_shade(B, q, it == 0, L.has_nee, S); });
   }
   if (e == hipSuccess) e = hipMemcpyAsync(L.h_cnt, B.counters, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, S);
   if (e == hipSuccess && profile >= 2)
@@ -684,7 +697,7 @@ hpt_status alloc_batch(hpt_ctx *C) {
     ok &= A((void **)&Q.slot, 4ull * N) && A((void **)&Q.unit, 4ull * N) && A((void **)&Q.meta, 4ull * N) &&
           A((void **)&Q.ka, 4ull * N) && A((void **)&Q.kb, 4ull * N) && A((void **)&Q.sig, 8ull * N) &&
           A((void **)&Q.bpre, 4ull * N) && A((void **)&Q.wt, 4ull * N) && A((void **)&Q.beta, 4ull * N) &&
-          A((void **)&Q.L, 4ull * N);
+          A((void **)&Q.L, 4ull * N) && A((void **)&Q.pdf, 4ull * N);
     ok &= A((void **)&Q.ox, 8ull * N) && A((void **)&Q.oy, 8ull * N) && A((void **)&Q.oz, 8ull * N) &&
           A((void **)&Q.dx, 8ull * N) && A((void **)&Q.dy, 8ull * N) && A((void **)&Q.dz, 8ull * N) &&
           A((void **)&Q.ell, 8ull * N) && A((void **)&Q.al, 8ull * N) && A((void **)&Q.be, 8ull * N);
@@ -898,10 +911,35 @@ hpt_status hpt_scene_upload(hpt_ctx *C, const hpt_scene_desc *d, uint64_t *out) 
       r.mat = d->tri_mat[g - d->n_sph];
     }
   }
+  // emitter triangles (next-event estimation): vertices, unit normal, area in FP64 from the FP32 input
+  std::vector<float4> lights;
+  std::vector<double> light_cdf;
+  double light_area = 0.0;
+  for (uint32_t i = 0; i < d->n_tri; ++i) {
+    const uint32_t mi = d->tri_mat[i];
+    if (d->mat_type[mi] != HPT_EMITTER) continue;
+    const float *t = d->tri + 9 * (size_t)i;
+    double e1[3], e2[3], cr[3];
+    for (int k = 0; k < 3; ++k) { e1[k] = (double)t[3 + k] - t[k]; e2[k] = (double)t[6 + k] - t[k]; }
+    cr[0] = e1[1] * e2[2] - e1[2] * e2[1];
+    cr[1] = e1[2] * e2[0] - e1[0] * e2[2];
+    cr[2] = e1[0] * e2[1] - e1[1] * e2[0];
+    const double a2 = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+    if (!(a2 > 0.0)) continue;
+    lights.push_back(make_float4(t[0], t[1], t[2], 0.f));
+    lights.push_back(make_float4(t[3], t[4], t[5], 0.f));
+    lights.push_back(make_float4(t[6], t[7], t[8], 0.f));
+    float mbits;
+    std::memcpy(&mbits, &mi, 4);
+    lights.push_back(make_float4((float)(cr[0] / a2), (float)(cr[1] / a2), (float)(cr[2] / a2), mbits));
+    light_area += 0.5 * a2;
+    light_cdf.push_back(light_area);
+  }
   std::lock_guard<std::mutex> g(C->mu);
   (void)hipSetDevice(C->device);
   size_t need = bvh.nodes.size() * 4 + bvh.prims.size() * 4 + sizeof(HitRec) * hits.size() +
-                sizeof(MaterialDev) * mats.size() + sizeof(SceneDev);
+                sizeof(MaterialDev) * mats.size() + sizeof(SceneDev) + sizeof(float4) * lights.size() +
+                sizeof(double) * light_cdf.size();
   if (C->used + need > C->budget) evict_grfs(C, need);
   if (C->used + need > C->budget) return fail(HPT_EBUDGET, "scene does not fit the budget");
   auto put = [&](const void *src, size_t bytes, void **dst) {
@@ -920,6 +958,12 @@ hpt_status hpt_scene_upload(hpt_ctx *C, const hpt_scene_desc *d, uint64_t *out) 
     ok &= put(hits.data(), sizeof(HitRec) * hits.size(), &p); h.hits = (const HitRec *)p;
   }
   ok &= put(mats.data(), sizeof(MaterialDev) * mats.size(), &p); h.mats = (const MaterialDev *)p;
+  if (!light_cdf.empty()) {
+    ok &= put(lights.data(), sizeof(float4) * lights.size(), &p); h.lights = (const float4 *)p;
+    ok &= put(light_cdf.data(), sizeof(double) * light_cdf.size(), &p); h.light_cdf = (const double *)p;
+  }
+  h.n_lights = (uint32_t)light_cdf.size();
+  h.light_area = light_area;
   h.n_sph = d->n_sph; h.n_tri = d->n_tri; h.n_mat = d->n_mat; h.n_nodes = n ? bvh.n_nodes : 0;
   for (int c = 0; c < 3; ++c) h.env[c] = d->env[c];
   ok &= C->alloc((void **)&S->dev, sizeof(SceneDev)) == hipSuccess;
@@ -1088,6 +1132,7 @@ hpt_status hpt_trace_submit(hpt_ctx *C, uint64_t scene, const hpt_job_desc *d, v
   Scene *S = find_scene(C, scene);
   if (!S) return fail(HPT_ENOTFOUND, "unknown scene");
   if (d->use_cache && !S->host.cache) return fail(HPT_EINVAL, "use_cache needs hpt_cache_build first");
+  if (d->nee > 1) return fail(HPT_EINVAL, "nee must be 0 or 1");
   auto J = std::make_unique<Job>();
   J->desc = *d;
   J->scene = S;
@@ -1108,6 +1153,7 @@ hpt_status hpt_trace_submit(hpt_ctx *C, uint64_t scene, const hpt_job_desc *d, v
   jd.spp = d->spp; jd.max_bounces = d->max_bounces; jd.T = d->T; jd.phase_mode = d->phase_mode;
   jd.random_phase = d->random_phase ? 1 : 0;
   jd.use_cache = d->use_cache ? 1 : 0;
+  jd.nee = d->nee ? 1 : 0;
   jd.cache_depth = d->cache_depth;
   jd.debug = d->debug;
   jd.seed = d->seed;
