@@ -37,6 +37,15 @@ constexpr int kFftThreads = 256;
 constexpr int kFftMax = 8192;   // longest line (LDS: 64 KB of complex64)
 
 struct C2 { float x, y; };
+
+// LDS index of element i of a line of up to 4 * U4 * kFftThreads values:
+// one pad slot after every 16 elements, so that the strided writes of the
+// early Stockham stages (4 and 16 elements apart) spread over the banks.
+// Lines of 8192 values (U4 = 8) are not padded: they fill 64 KB of LDS.
+template <int U4>
+__device__ __forceinline__ uint32_t pd(uint32_t i) { return U4 < 8 ? i + (i >> 4) : i; }
+template <int U4>
+constexpr size_t lds_bytes(uint32_t n) { return (U4 < 8 ? n + n / 16 : n) * sizeof(C2); }
 __device__ __forceinline__ C2 c2(float x, float y) { return {x, y}; }
 __device__ __forceinline__ C2 add(C2 a, C2 b) { return {a.x + b.x, a.y + b.y}; }
 __device__ __forceinline__ C2 sub(C2 a, C2 b) { return {a.x - b.x, a.y - b.y}; }
@@ -69,7 +78,7 @@ __device__ void lds_fft(C2 *x, uint32_t n, uint32_t lg, bool inv, const float2 *
       const uint32_t j = tid + (uint32_t)u * kFftThreads;
       if (j < q) {
         const uint32_t k = j % Ns;
-        C2 a0 = x[j], a1 = x[j + q], a2 = x[j + 2 * q], a3 = x[j + 3 * q];
+        C2 a0 = x[pd<U4>(j)], a1 = x[pd<U4>(j + q)], a2 = x[pd<U4>(j + 2 * q)], a3 = x[pd<U4>(j + 3 * q)];
         if (Ns > 1) {  // exp(-+2 pi i e k / (4 Ns)) = tw[e k n / (4 Ns)]
           const uint32_t st = k * (n / (4 * Ns));
           a1 = mul(a1, twiddle(tw, st, inv));
@@ -89,10 +98,10 @@ __device__ void lds_fft(C2 *x, uint32_t n, uint32_t lg, bool inv, const float2 *
       const uint32_t j = tid + (uint32_t)u * kFftThreads;
       if (j < q) {
         const uint32_t d = (j / Ns) * Ns * 4 + j % Ns;
-        x[d] = v[u][0];
-        x[d + Ns] = v[u][1];
-        x[d + 2 * Ns] = v[u][2];
-        x[d + 3 * Ns] = v[u][3];
+        x[pd<U4>(d)] = v[u][0];
+        x[pd<U4>(d + Ns)] = v[u][1];
+        x[pd<U4>(d + 2 * Ns)] = v[u][2];
+        x[pd<U4>(d + 3 * Ns)] = v[u][3];
       }
     }
     __syncthreads();
@@ -105,7 +114,7 @@ __device__ void lds_fft(C2 *x, uint32_t n, uint32_t lg, bool inv, const float2 *
     for (int u = 0; u < U2; ++u) {
       const uint32_t j = tid + (uint32_t)u * kFftThreads;
       if (j < hn) {
-        C2 a0 = x[j], a1 = x[j + hn];
+        C2 a0 = x[pd<U4>(j)], a1 = x[pd<U4>(j + hn)];
         if (Ns > 1) a1 = mul(a1, twiddle(tw, (j % Ns) * (n / (2 * Ns)), inv));
         v[u][0] = add(a0, a1);
         v[u][1] = sub(a0, a1);
@@ -117,8 +126,8 @@ __device__ void lds_fft(C2 *x, uint32_t n, uint32_t lg, bool inv, const float2 *
       const uint32_t j = tid + (uint32_t)u * kFftThreads;
       if (j < hn) {
         const uint32_t d = (j / Ns) * Ns * 2 + j % Ns;
-        x[d] = v[u][0];
-        x[d + Ns] = v[u][1];
+        x[pd<U4>(d)] = v[u][0];
+        x[pd<U4>(d + Ns)] = v[u][1];
       }
     }
     __syncthreads();
@@ -134,12 +143,12 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_rows(const float2 *in, floa
   const float2 *src = in + row * w;
   for (uint32_t i = threadIdx.x; i < px; i += kFftThreads) {
     float2 v = i < w ? src[i] : make_float2(0.f, 0.f);
-    lds[i] = c2(v.x, v.y);
+    lds[pd<U4>(i)] = c2(v.x, v.y);
   }
   __syncthreads();
   lds_fft<U4>(lds, px, lgx, false, tw);
   float2 *dst = A + row * px;
-  for (uint32_t i = threadIdx.x; i < px; i += kFftThreads) dst[i] = make_float2(lds[i].x, lds[i].y);
+  for (uint32_t i = threadIdx.x; i < px; i += kFftThreads) dst[i] = make_float2(lds[pd<U4>(i)].x, lds[pd<U4>(i)].y);
 }
 
 // Transpose of each of nf matrices [rows][cols] -> [cols][rows], 32 x 32 tiles.
@@ -201,18 +210,18 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_columns(const float2 *src, 
     float2 *col = dst + ((size_t)f * px + kx) * h;
     for (uint32_t i = t; i < py; i += kFftThreads) {
       float2 v = i < h ? scol[i] : make_float2(0.f, 0.f);
-      lds[i] = c2(v.x, v.y);
+      lds[pd<U4>(i)] = c2(v.x, v.y);
     }
     __syncthreads();
     lds_fft<U4>(lds, py, lgy, false, tw);
 #pragma unroll
     for (int u = 0; u < UH; ++u) {
       const uint32_t i = t + (uint32_t)u * kFftThreads;
-      if (i < py) lds[i] = mul(lds[i], Hr[u]);
+      if (i < py) lds[pd<U4>(i)] = mul(lds[pd<U4>(i)], Hr[u]);
     }
     __syncthreads();
     lds_fft<U4>(lds, py, lgy, true, tw);
-    for (uint32_t i = t; i < h; i += kFftThreads) col[i] = make_float2(lds[i].x, lds[i].y);
+    for (uint32_t i = t; i < h; i += kFftThreads) col[i] = make_float2(lds[pd<U4>(i)].x, lds[pd<U4>(i)].y);
     __syncthreads();  // before the next field overwrites the buffer
   }
 }
@@ -236,12 +245,12 @@ __global__ void __launch_bounds__(kFftThreads) k_ifft_rows(const float2 *A, floa
   const float2 *src = A + row * px;
   for (uint32_t i = threadIdx.x; i < px; i += kFftThreads) {
     float2 v = src[i];
-    lds[i] = c2(v.x, v.y);
+    lds[pd<U4>(i)] = c2(v.x, v.y);
   }
   __syncthreads();
   lds_fft<U4>(lds, px, lgx, true, tw);
   float2 *dst = out + row * w;
-  for (uint32_t i = threadIdx.x; i < w; i += kFftThreads) dst[i] = make_float2(lds[i].x * scale, lds[i].y * scale);
+  for (uint32_t i = threadIdx.x; i < w; i += kFftThreads) dst[i] = make_float2(lds[pd<U4>(i)].x * scale, lds[pd<U4>(i)].y * scale);
 }
 
 // Summed intensity of row y over nf fields: inverse FFT of row (f, y) of
@@ -262,7 +271,7 @@ __global__ void __launch_bounds__(kFftThreads) k_ifft_rows_intensity(const float
     const float2 *src = A + ((size_t)f * h + y) * px;
     for (uint32_t i = t; i < px; i += kFftThreads) {
       float2 v = src[i];
-      lds[i] = c2(v.x, v.y);
+      lds[pd<U4>(i)] = c2(v.x, v.y);
     }
     __syncthreads();
     lds_fft<U4>(lds, px, lgx, true, tw);
@@ -270,7 +279,7 @@ __global__ void __launch_bounds__(kFftThreads) k_ifft_rows_intensity(const float
     for (int u = 0; u < UW; ++u) {
       const uint32_t i = t + (uint32_t)u * kFftThreads;
       if (i < w) {
-        const float re = lds[i].x * scale, im = lds[i].y * scale;
+        const float re = lds[pd<U4>(i)].x * scale, im = lds[pd<U4>(i)].y * scale;
         acc[u] += re * re + im * im;
       }
     }
@@ -294,10 +303,10 @@ template <int U4>
 void launch_rows(bool inv, const float2 *in, float2 *out, uint32_t nrows, uint32_t w, uint32_t h, uint32_t px,
                  uint32_t lgx, float scale, const float2 *tw, hipStream_t st) {
   if (!inv)
-    hipLaunchKernelGGL(k_fft_rows<U4>, dim3(nrows), dim3(kFftThreads), px * sizeof(C2), st, in, out, w, h, px, lgx,
+    hipLaunchKernelGGL(k_fft_rows<U4>, dim3(nrows), dim3(kFftThreads), lds_bytes<U4>(px), st, in, out, w, h, px, lgx,
                        tw);
   else
-    hipLaunchKernelGGL(k_ifft_rows<U4>, dim3(nrows), dim3(kFftThreads), px * sizeof(C2), st, in, out, w, h, px, lgx,
+    hipLaunchKernelGGL(k_ifft_rows<U4>, dim3(nrows), dim3(kFftThreads), lds_bytes<U4>(px), st, in, out, w, h, px, lgx,
                        scale, tw);
 }
 
@@ -311,22 +320,25 @@ void rows(bool inv, const float2 *in, float2 *out, uint32_t nrows, uint32_t w, u
 
 void columns(const float2 *src, float2 *dst, uint32_t nf, uint32_t h, uint32_t px, uint32_t py, uint32_t lgy,
              const AsmParams &P, const float2 *tw, hipStream_t st) {
-  const size_t sh = py * sizeof(C2);
   if (py <= 4 * kFftThreads)
-    hipLaunchKernelGGL(k_fft_columns<1>, dim3(px), dim3(kFftThreads), sh, st, src, dst, nf, h, px, py, lgy, P, tw);
+    hipLaunchKernelGGL(k_fft_columns<1>, dim3(px), dim3(kFftThreads), lds_bytes<1>(py), st, src, dst, nf, h, px, py,
+                       lgy, P, tw);
   else if (py <= 8 * kFftThreads)
-    hipLaunchKernelGGL(k_fft_columns<2>, dim3(px), dim3(kFftThreads), sh, st, src, dst, nf, h, px, py, lgy, P, tw);
+    hipLaunchKernelGGL(k_fft_columns<2>, dim3(px), dim3(kFftThreads), lds_bytes<2>(py), st, src, dst, nf, h, px, py,
+                       lgy, P, tw);
   else if (py <= 16 * kFftThreads)
-    hipLaunchKernelGGL(k_fft_columns<4>, dim3(px), dim3(kFftThreads), sh, st, src, dst, nf, h, px, py, lgy, P, tw);
+    hipLaunchKernelGGL(k_fft_columns<4>, dim3(px), dim3(kFftThreads), lds_bytes<4>(py), st, src, dst, nf, h, px, py,
+                       lgy, P, tw);
   else
-    hipLaunchKernelGGL(k_fft_columns<8>, dim3(px), dim3(kFftThreads), sh, st, src, dst, nf, h, px, py, lgy, P, tw);
+    hipLaunchKernelGGL(k_fft_columns<8>, dim3(px), dim3(kFftThreads), lds_bytes<8>(py), st, src, dst, nf, h, px, py,
+                       lgy, P, tw);
 }
 
 template <int U4>
 void launch_intensity_rows(const float2 *A, float *I, uint32_t nf, uint32_t w, uint32_t h, uint32_t px,
                            uint32_t lgx, float scale, float weight, bool accumulate, const float2 *tw,
                            hipStream_t st) {
-  hipLaunchKernelGGL(k_ifft_rows_intensity<U4>, dim3(h), dim3(kFftThreads), px * sizeof(C2), st, A, I, nf, w, h, px,
+  hipLaunchKernelGGL(k_ifft_rows_intensity<U4>, dim3(h), dim3(kFftThreads), lds_bytes<U4>(px), st, A, I, nf, w, h, px,
                      lgx, scale, weight, accumulate ? 1u : 0u, tw);
 }
 

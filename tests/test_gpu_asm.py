@@ -54,7 +54,7 @@ def _check(got, ref, label):
     assert err <= TOL, label
 
 
-@pytest.mark.parametrize("h,w", [(1, 1), (37, 29), (64, 64), (100, 30), (5, 257)])
+@pytest.mark.parametrize("h,w", [(1, 1), (37, 29), (64, 64), (100, 30), (5, 257), (2100, 9), (3, 2500)])
 @pytest.mark.parametrize("z,band_limit", [(2e-3, True), (80e-3, True), (80e-3, False), (-5e-3, True)])
 def test_asm_matches_oracle(ctx, h, w, z, band_limit):
     u = _fields(2, h, w, seed=h * 1000 + w)
