@@ -33,12 +33,14 @@ class OracleScene:
                       _c(sc["sph"], np.float32), _c(sc["sph_mat"], np.uint32),
                       _c(sc["mat_type"], np.uint32), _c(sc["mat_rgb"], np.float32),
                       _c(sc["mat_rough"], np.float32), _c(sc["mat_ior"], np.float32),
-                      _c(sc["mat_emit"], np.float32), _c(sc["env"], np.float32)]
+                      _c(sc["mat_emit"], np.float32), _c(sc["env"], np.float32),
+                      _c(sc.get("mat_pbr", np.tile(np.float32([0.0, 0.5, 0.0, 1.0]), (len(sc["mat_type"]), 1))),
+                         np.float32)]
         k = self._keep
         d = _lib.OScene(k[0].ctypes.data, len(k[1]), k[1].ctypes.data,
                         k[2].ctypes.data, len(k[3]), k[3].ctypes.data,
                         len(k[4]), k[4].ctypes.data, k[5].ctypes.data, k[6].ctypes.data,
-                        k[7].ctypes.data, k[8].ctypes.data, k[9].ctypes.data)
+                        k[7].ctypes.data, k[8].ctypes.data, k[9].ctypes.data, k[10].ctypes.data)
         self.h = _lib.lib().oracle_scene_create(C.byref(d))
         self.n_sph = len(k[3])
 
@@ -177,6 +179,26 @@ def sample_vndf(V, alpha, u1, u2):
 
 def smith_g1(w, alpha):
     return _lib.lib().oracle_smith_g1(_c(w, np.float64).ctypes.data, alpha)
+
+
+def principled_eval(params, V, L):
+    """(f cos, pdf) of the principled lobes for local directions V, L;
+    params = (base, roughness, metallic, specular, clearcoat, gloss)."""
+    out = np.zeros(2)
+    _lib.lib().oracle_principled_eval(_c(params, np.float64).ctypes.data, _c(V, np.float64).ctypes.data,
+                                      _c(L, np.float64).ctypes.data, out.ctypes.data)
+    return out[0], out[1]
+
+
+def principled_sample(params, V, u):
+    """(local direction, weight f cos / pdf, lobe index) for uniforms u[0..2]."""
+    L = np.zeros(3)
+    w = np.zeros(1)
+    lobe = np.zeros(1, dtype=np.int32)
+    _lib.lib().oracle_principled_sample(_c(params, np.float64).ctypes.data, _c(V, np.float64).ctypes.data,
+                                        _c(u, np.float64).ctypes.data, L.ctypes.data, w.ctypes.data,
+                                        lobe.ctypes.data)
+    return L, float(w[0]), int(lobe[0])
 
 
 def oct_map(w, bins):

@@ -14,7 +14,7 @@ class OScene(C.Structure):
                 ("sph", C.c_void_p), ("n_sph", C.c_int32), ("sph_mat", C.c_void_p),
                 ("n_mat", C.c_int32), ("mat_type", C.c_void_p), ("mat_rgb", C.c_void_p),
                 ("mat_rough", C.c_void_p), ("mat_ior", C.c_void_p), ("mat_emit", C.c_void_p),
-                ("env", C.c_void_p)]
+                ("env", C.c_void_p), ("mat_pbr", C.c_void_p)]
 
 
 class OJob(C.Structure):
@@ -63,6 +63,8 @@ def lib():
         L.oracle_sample_vndf.argtypes = [vp, dbl, dbl, dbl, vp]
         L.oracle_smith_g1.restype = dbl
         L.oracle_smith_g1.argtypes = [vp, dbl]
+        L.oracle_principled_eval.argtypes = [vp, vp, vp, vp]
+        L.oracle_principled_sample.argtypes = [vp, vp, vp, vp, vp, vp]
         L.oracle_oct.argtypes = [vp, i32, vp, vp]
         L.oracle_oct_decode.argtypes = [dbl, dbl, vp]
         L.oracle_round_fp16.restype = dbl

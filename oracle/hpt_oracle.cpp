@@ -107,17 +107,19 @@ inline void sig_add(uint64_t &h, uint32_t w) { h ^= (uint64_t)w; h *= FNV_PRIME;
 
 // Lobe / event codes recorded in the signature.
 enum { EV_MIRROR = 1, EV_DIEL_REFL = 2, EV_DIEL_REFR = 3, EV_LAMBERT = 4, EV_GGX = 5,
-       EV_ABSORB = 6, EV_EMIT = 7, EV_IMAGE_POINT = 8 };
+       EV_ABSORB = 6, EV_EMIT = 7, EV_IMAGE_POINT = 8, EV_PRIN_DIFFUSE = 9, EV_PRIN_SPECULAR = 10,
+       EV_PRIN_CLEARCOAT = 11 };
 // Termination kinds.
 enum { K_NONE = 0, K_ESCAPE_PREFIX = 1, K_MAXB_PREFIX = 2, K_EMITTER = 3, K_ENV = 4,
        K_MAXB_TAIL = 5, K_CACHE = 6, K_ABSORBED = 7 };
 
-enum { LAMBERT = 0, GGX = 1, MIRROR = 2, DIELECTRIC = 3, EMITTER = 4 };
+enum { LAMBERT = 0, GGX = 1, MIRROR = 2, DIELECTRIC = 3, EMITTER = 4, PRINCIPLED = 5 };
 
 // ------------------------------------------------------------------ scene
 struct Material {
   int type;
   double rgb[3], rough, ior, emit[3];
+  double metallic, specular, clearcoat, clearcoat_gloss;   // PRINCIPLED
 };
 
 struct Box { V3 lo, hi; };
@@ -357,6 +359,74 @@ double smith_g1(V3 w, double alpha) {
   return 2.0 * w.z / (w.z + std::sqrt(alpha * alpha * (w.x * w.x + w.y * w.y) + z2));
 }
 
+// Principled reflectance (Burley, "Physically-Based Shading at Disney",
+// SIGGRAPH 2012 course; its metallic-roughness core): Burley diffuse weighted
+// 1 - metallic; GGX specular, alpha = roughness^2, Schlick F0 =
+// (1 - metallic) 0.08 specular + metallic base, Smith masking G1(V) G1(L);
+// GTR1 clearcoat, alpha = 0.1 (1 - gloss) + 0.001 gloss, F0 = 0.04, Smith
+// masking with alpha 0.25, weighted 0.25 clearcoat. Sampling picks a lobe
+// with probability proportional to (1 - metallic, 1, 0.25 clearcoat) and
+// weights by the full f cos over the combined pdf (one-sample MIS). V, L in
+// the local frame of the facing normal (z up).
+struct PrinLobes { double wd, ws, wc, sum; };
+PrinLobes prin_lobes(const Material &m) {
+  PrinLobes p{1.0 - m.metallic, 1.0, 0.25 * m.clearcoat, 0.0};
+  p.sum = p.wd + p.ws + p.wc;
+  return p;
+}
+
+double gtr1(double cos_h, double a) {
+  double a2 = a * a;
+  return (a2 - 1.0) / (M_PI * std::log(a2) * (1.0 + (a2 - 1.0) * cos_h * cos_h));
+}
+
+struct PrinEval { double fcos, pdf; };
+PrinEval principled_eval(const Material &m, int comp, V3 V, V3 L) {
+  if (L.z <= 0.0 || V.z <= 0.0) return {0.0, 0.0};
+  const double r = m.rough, a = r * r;
+  V3 H = normalize(V + L);
+  double vh = std::max(0.0, dot(V, H));
+  double schlick = std::pow(1.0 - vh, 5.0);
+  double fd90 = 0.5 + 2.0 * r * vh * vh;
+  double fdiff = (1.0 - m.metallic) * m.rgb[comp] / M_PI * (1.0 + (fd90 - 1.0) * std::pow(1.0 - L.z, 5.0)) *
+                 (1.0 + (fd90 - 1.0) * std::pow(1.0 - V.z, 5.0));
+  double f0 = (1.0 - m.metallic) * 0.08 * m.specular + m.metallic * m.rgb[comp];
+  double a2 = a * a, k = H.z * H.z * (a2 - 1.0) + 1.0;
+  double D = a2 / (M_PI * k * k);
+  double g1v = smith_g1(V, a);
+  double fspec = (f0 + (1.0 - f0) * schlick) * D * g1v * smith_g1(L, a) / (4.0 * V.z * L.z);
+  double ac = 0.1 * (1.0 - m.clearcoat_gloss) + 0.001 * m.clearcoat_gloss;
+  double Dc = gtr1(H.z, ac);
+  double fcc = 0.25 * m.clearcoat * (0.04 + 0.96 * schlick) * Dc * smith_g1(V, 0.25) * smith_g1(L, 0.25) /
+               (4.0 * V.z * L.z);
+  PrinLobes p = prin_lobes(m);
+  double pdf = (p.wd * L.z / M_PI + p.ws * g1v * D / (4.0 * V.z) + (vh > 0.0 ? p.wc * Dc * H.z / (4.0 * vh) : 0.0)) /
+               p.sum;
+  return {(fdiff + fspec + fcc) * L.z, pdf};
+}
+
+// Lobe index (0 diffuse, 1 specular, 2 clearcoat) and the local direction
+// drawn from it with u1, u2.
+V3 principled_sample(const Material &m, V3 V, double u0, double u1, double u2, int &lobe) {
+  PrinLobes p = prin_lobes(m);
+  double x = u0 * p.sum;
+  lobe = x < p.wd ? 0 : (x < p.wd + p.ws ? 1 : 2);
+  if (lobe == 0) {
+    double r = std::sqrt(u1), ph = 2.0 * M_PI * u2;
+    return {r * std::cos(ph), r * std::sin(ph), std::sqrt(std::max(0.0, 1.0 - u1))};
+  }
+  V3 H;
+  if (lobe == 1) {
+    H = sample_vndf_local(V, m.rough * m.rough, u1, u2);
+  } else {
+    double ac = 0.1 * (1.0 - m.clearcoat_gloss) + 0.001 * m.clearcoat_gloss, ac2 = ac * ac;
+    double ct = std::sqrt(std::max(0.0, (1.0 - std::pow(ac2, 1.0 - u1)) / (1.0 - ac2)));
+    double st = std::sqrt(std::max(0.0, 1.0 - ct * ct)), ph = 2.0 * M_PI * u2;
+    H = {st * std::cos(ph), st * std::sin(ph), ct};
+  }
+  return (2.0 * dot(V, H)) * H - V;
+}
+
 struct Sampled { V3 d; double w; int ev; bool delta; double eta_t; };
 
 // One BSDF lobe sample at a surface. d_in: travel direction of the incoming
@@ -388,6 +458,18 @@ Sampled sample_bsdf(const Material &m, int comp, V3 d_in, V3 ng, const Uniforms 
       s.d = normalize(s.d);
       s.w = e * e; s.ev = EV_DIEL_REFR; s.eta_t = eta_t;
     }
+  } else if (m.type == PRINCIPLED) {
+    V3 b1, b2;
+    onb(nf, b1, b2);
+    V3 wo = -1.0 * d_in;
+    V3 V = {dot(wo, b1), dot(wo, b2), dot(wo, nf)};
+    int lobe;
+    V3 L = principled_sample(m, V, U.u[0], U.u[1], U.u[2], lobe);
+    s.ev = EV_PRIN_DIFFUSE + lobe;
+    if (L.z <= 0.0 || V.z <= 0.0) { s.w = 0.0; s.ev = EV_ABSORB; return s; }
+    PrinEval e = principled_eval(m, comp, V, L);
+    s.w = e.pdf > 0.0 ? e.fcos / e.pdf : 0.0;
+    s.d = normalize(L.x * b1 + L.y * b2 + L.z * nf);
   } else if (m.type == GGX) {
     V3 b1, b2;
     onb(nf, b1, b2);
@@ -498,6 +580,14 @@ Eval eval_bsdf(const Material &m, int comp, V3 d_in, V3 ng, V3 wl) {
   double c = dot(wl, nf);
   if (c <= 0.0) return {0.0, 0.0};
   if (m.type == LAMBERT) return {m.rgb[comp] * c / M_PI, c / M_PI};
+  if (m.type == PRINCIPLED) {
+    V3 b1, b2;
+    onb(nf, b1, b2);
+    V3 wo = -1.0 * d_in;
+    PrinEval e = principled_eval(m, comp, {dot(wo, b1), dot(wo, b2), dot(wo, nf)},
+                                 {dot(wl, b1), dot(wl, b2), c});
+    return {e.fcos, e.pdf};
+  }
   if (m.type != GGX) return {0.0, 0.0};
   V3 b1, b2;
   onb(nf, b1, b2);
@@ -687,6 +777,7 @@ struct OScene {
   const float *sph; int32_t n_sph; const uint32_t *sph_mat;
   int32_t n_mat; const uint32_t *mat_type; const float *mat_rgb; const float *mat_rough;
   const float *mat_ior; const float *mat_emit; const float *env;
+  const float *mat_pbr;     // [n_mat][4] metallic, specular, clearcoat, clearcoat gloss (nullable)
 };
 
 struct OJob {
@@ -728,6 +819,9 @@ void *oracle_scene_create(const OScene *d) {
     m.type = (int)d->mat_type[i];
     for (int c = 0; c < 3; ++c) { m.rgb[c] = d->mat_rgb[3 * i + c]; m.emit[c] = d->mat_emit[3 * i + c]; }
     m.rough = d->mat_rough[i]; m.ior = d->mat_ior[i];
+    const float *pb = d->mat_pbr ? d->mat_pbr + 4 * i : nullptr;
+    m.metallic = pb ? pb[0] : 0.0; m.specular = pb ? pb[1] : 0.5;
+    m.clearcoat = pb ? pb[2] : 0.0; m.clearcoat_gloss = pb ? pb[3] : 1.0;
     S->mats.push_back(m);
   }
   for (int c = 0; c < 3; ++c) S->env[c] = d->env[c];
@@ -856,6 +950,34 @@ void oracle_sample_vndf(const double *V, double alpha, double u1, double u2, dou
 }
 
 double oracle_smith_g1(const double *w, double alpha) { return smith_g1({w[0], w[1], w[2]}, alpha); }
+
+// Principled lobes of one colour component: p = (base, roughness, metallic,
+// specular, clearcoat, clearcoat gloss); V, L local (z = facing normal).
+static Material principled_of(const double *p) {
+  Material m{};
+  m.type = PRINCIPLED;
+  m.rgb[0] = m.rgb[1] = m.rgb[2] = p[0];
+  m.rough = p[1]; m.metallic = p[2]; m.specular = p[3]; m.clearcoat = p[4]; m.clearcoat_gloss = p[5];
+  return m;
+}
+
+void oracle_principled_eval(const double *p, const double *V, const double *L, double *out) {
+  PrinEval e = principled_eval(principled_of(p), 0, {V[0], V[1], V[2]}, {L[0], L[1], L[2]});
+  out[0] = e.fcos; out[1] = e.pdf;
+}
+
+// Sampled local direction, its weight f cos / pdf (0 below the horizon) and lobe.
+void oracle_principled_sample(const double *p, const double *V, const double *u, double *L_out, double *w,
+                              int32_t *lobe) {
+  Material m = principled_of(p);
+  V3 v = {V[0], V[1], V[2]};
+  int lb;
+  V3 L = principled_sample(m, v, u[0], u[1], u[2], lb);
+  *lobe = lb;
+  L_out[0] = L.x; L_out[1] = L.y; L_out[2] = L.z;
+  PrinEval e = principled_eval(m, 0, v, L);
+  *w = (L.z > 0.0 && e.pdf > 0.0) ? e.fcos / e.pdf : 0.0;
+}
 
 void oracle_oct(const double *w, int32_t bins, double *uv, int32_t *bin) {
   double u, v;

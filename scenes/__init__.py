@@ -6,7 +6,7 @@ intersection, no BSDF, no phase. Both the oracle and the GPU library read
 the arrays it produces.
 """
 from .generators import (  # noqa: F401
-    LAMBERT, GGX, MIRROR, DIELECTRIC, EMITTER,
+    LAMBERT, GGX, MIRROR, DIELECTRIC, EMITTER, PRINCIPLED,
     make_scene, scene_tiny, scene_mid, scene_large, scene_arrays_ok,
     scene_patch, scene_mirror_patch, scene_slab, scene_furnace_sphere,
     scene_lambert_plane, scene_single_tri, scene_translate, empty_scene, scene_lit_plane,

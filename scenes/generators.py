@@ -11,6 +11,7 @@ The scene format is a dict of flat arrays:
   mat_rough float32 [M]      GGX alpha
   mat_ior   float32 [M]      dielectric index
   mat_emit  float32 [M,3]    emitter radiance (one-sided, along the winding normal)
+  mat_pbr   float32 [M,4]    PRINCIPLED: metallic, specular, clearcoat, clearcoat gloss
   env       float32 [3]      radiance of escaped rays
 
 Primitive ids are global: spheres take ids [0, S), triangles [S, S+N).
@@ -25,7 +26,7 @@ Mitsuba scenes that are not available; these generators replace them).
 """
 import numpy as np
 
-LAMBERT, GGX, MIRROR, DIELECTRIC, EMITTER = 0, 1, 2, 3, 4
+LAMBERT, GGX, MIRROR, DIELECTRIC, EMITTER, PRINCIPLED = 0, 1, 2, 3, 4, 5
 MM = 1e-3
 
 
@@ -33,11 +34,11 @@ class _Builder:
     def __init__(self):
         self.tris, self.tri_mats = [], []
         self.sph, self.sph_mats = [], []
-        self.mats = []  # (type, rgb, rough, ior, emit)
+        self.mats = []  # (type, rgb, rough, ior, emit, pbr)
 
-    def material(self, mtype, rgb=(0, 0, 0), rough=0.0, ior=1.0, emit=(0, 0, 0)):
+    def material(self, mtype, rgb=(0, 0, 0), rough=0.0, ior=1.0, emit=(0, 0, 0), pbr=(0.0, 0.5, 0.0, 1.0)):
         self.mats.append((mtype, tuple(map(float, rgb)), float(rough), float(ior),
-                          tuple(map(float, emit))))
+                          tuple(map(float, emit)), tuple(map(float, pbr))))
         return len(self.mats) - 1
 
     def add_tris(self, verts, mat):
@@ -69,6 +70,7 @@ class _Builder:
             mat_rough=np.asarray([x[2] for x in m], dtype=np.float32),
             mat_ior=np.asarray([x[3] for x in m], dtype=np.float32),
             mat_emit=np.asarray([x[4] for x in m], dtype=np.float32).reshape(-1, 3),
+            mat_pbr=np.asarray([x[5] for x in m], dtype=np.float32).reshape(-1, 4),
             env=np.asarray(env, dtype=np.float32),
         )
 
