@@ -70,7 +70,8 @@ const char *hpt_version(void);
  * Primitive ids are global: spheres [0, n_sph), triangles [n_sph, n_sph +
  * n_tri). Light sources are EMITTER triangles; they emit radiance `emit`
  * on the side of their geometric normal and are black otherwise. */
-enum { HPT_LAMBERT = 0, HPT_GGX = 1, HPT_MIRROR = 2, HPT_DIELECTRIC = 3, HPT_EMITTER = 4 };
+enum { HPT_LAMBERT = 0, HPT_GGX = 1, HPT_MIRROR = 2, HPT_DIELECTRIC = 3, HPT_EMITTER = 4,
+       HPT_PRINCIPLED = 5 };
 
 typedef struct {
   const float *tri;        /* host, [n_tri][3][3] vertex positions */
@@ -86,6 +87,17 @@ typedef struct {
   const float *mat_ior;      /* host, [n_mat] dielectric index > 1 */
   const float *mat_emit;     /* host, [n_mat][3] emitter radiance >= 0 */
   const float *env;          /* host, [3] radiance of rays leaving the scene */
+  const float *mat_pbr;      /* host, [n_mat][4] (nullable: 0, 0.5, 0, 1 for every material):
+                                HPT_PRINCIPLED metallic, specular, clearcoat, clearcoat gloss,
+                                each in [0, 1]. A principled material (Burley 2012, metallic-
+                                roughness core) reflects with a Burley diffuse lobe weighted
+                                1 - metallic (albedo mat_rgb), a GGX lobe with alpha =
+                                mat_rough^2 and Schlick F0 = (1 - metallic) 0.08 specular +
+                                metallic mat_rgb, and a GTR1 clearcoat lobe (alpha = 0.1 (1 -
+                                gloss) + 0.001 gloss, F0 0.04, Smith masking alpha 0.25) weighted
+                                0.25 clearcoat; a lobe is sampled with probability proportional
+                                to (1 - metallic, 1, 0.25 clearcoat) and weighted by the full
+                                f cos over the combined pdf. */
 } hpt_scene_desc;
 
 typedef struct {

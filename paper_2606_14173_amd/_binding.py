@@ -30,7 +30,7 @@ class SceneDesc(C.Structure):
                 ("sph", C.c_void_p), ("n_sph", C.c_uint32), ("sph_mat", C.c_void_p),
                 ("n_mat", C.c_uint32), ("mat_type", C.c_void_p), ("mat_rgb", C.c_void_p),
                 ("mat_rough", C.c_void_p), ("mat_ior", C.c_void_p), ("mat_emit", C.c_void_p),
-                ("env", C.c_void_p)]
+                ("env", C.c_void_p), ("mat_pbr", C.c_void_p)]
 
 
 class SceneInfo(C.Structure):
@@ -220,11 +220,13 @@ class Context:
                 _arr(sc["mat_type"], np.uint32), _arr(sc["mat_rgb"], np.float32),
                 _arr(sc["mat_rough"], np.float32), _arr(sc["mat_ior"], np.float32),
                 _arr(sc["mat_emit"], np.float32), _arr(sc["env"], np.float32)]
+        pbr = sc.get("mat_pbr")
+        keep.append(_arr(pbr, np.float32) if pbr is not None else None)
         d = SceneDesc(keep[0].ctypes.data, len(keep[1]), keep[1].ctypes.data,
                       keep[2].ctypes.data, len(keep[3]), keep[3].ctypes.data,
                       len(keep[4]), keep[4].ctypes.data, keep[5].ctypes.data,
                       keep[6].ctypes.data, keep[7].ctypes.data, keep[8].ctypes.data,
-                      keep[9].ctypes.data)
+                      keep[9].ctypes.data, keep[10].ctypes.data if keep[10] is not None else None)
         sid = C.c_uint64()
         _check(self.lib.hpt_scene_upload(self.h, C.byref(d), C.byref(sid)))
         return sid.value

@@ -354,9 +354,89 @@ __device__ __forceinline__ double fresnel64(double cos_i, double eta_i, double e
 
 struct Lobe { F3 d; float w; uint32_t ev; bool delta; };
 
+// GGX visible-normal sample (Heitz, JCGT 2018) in the local frame (z up).
+__device__ __forceinline__ F3 vndf_local(F3 V, float a, float u1, float u2) {
+  F3 Vh = normalize(f3(a * V.x, a * V.y, V.z));
+  float lensq = Vh.x * Vh.x + Vh.y * Vh.y;
+  F3 T1 = lensq > 0.f ? (1.0f / sqrtf(lensq)) * f3(-Vh.y, Vh.x, 0.f) : f3(1.f, 0.f, 0.f);
+  F3 T2 = cross(Vh, T1);
+  float r = sqrtf(u1), s, c;
+  sincospif(2.0f * u2, &s, &c);
+  float t1 = r * c, t2 = r * s;
+  float sh = 0.5f * (1.0f + Vh.z);
+  t2 = (1.0f - sh) * sqrtf(fmaxf(0.f, 1.f - t1 * t1)) + sh * t2;
+  F3 Nh = t1 * T1 + t2 * T2 + sqrtf(fmaxf(0.f, 1.f - t1 * t1 - t2 * t2)) * Vh;
+  return normalize(f3(a * Nh.x, a * Nh.y, fmaxf(0.f, Nh.z)));
+}
+
+__device__ __forceinline__ float smith_g1f(F3 w, float a) {
+  return 2.0f * w.z / (w.z + sqrtf(a * a * (w.x * w.x + w.y * w.y) + w.z * w.z));
+}
+
+// Principled reflectance in FP32 (Burley 2012, metallic-roughness core):
+// Burley diffuse weighted 1 - metallic; GGX specular, alpha = roughness^2,
+// Schlick F0 = (1 - metallic) 0.08 specular + metallic base; GTR1 clearcoat
+// (alpha 0.1 (1 - gloss) + 0.001 gloss, F0 0.04, Smith alpha 0.25) weighted
+// 0.25 clearcoat. Lobes are sampled with probability proportional to
+// (1 - metallic, 1, 0.25 clearcoat); f cos and the combined pdf for local
+// V, L (z = facing normal).
+struct BsdfEval { float fcos, pdf; };
+__device__ __forceinline__ BsdfEval principled_eval(const MaterialDev &m, float base, F3 V, F3 L) {
+  BsdfEval e{0.f, 0.f};
+  if (L.z <= 0.f || V.z <= 0.f) return e;
+  const float inv_pi = 0.318309886183790672f;
+  const float r = m.rough, a = r * r;
+  F3 H = normalize(V + L);
+  const float vh = fmaxf(0.f, dot(V, H));
+  const float x = 1.0f - vh, x2 = x * x, schlick = x2 * x2 * x;
+  const float fd90 = 0.5f + 2.0f * r * vh * vh;
+  const float xl = 1.0f - L.z, xl2 = xl * xl, xv = 1.0f - V.z, xv2 = xv * xv;
+  const float fdiff = (1.0f - m.metallic) * base * inv_pi * (1.0f + (fd90 - 1.0f) * xl2 * xl2 * xl) *
+                      (1.0f + (fd90 - 1.0f) * xv2 * xv2 * xv);
+  const float f0 = (1.0f - m.metallic) * 0.08f * m.specular + m.metallic * base;
+  const float a2 = a * a, k = H.z * H.z * (a2 - 1.0f) + 1.0f;
+  const float D = a2 * inv_pi / (k * k);
+  const float g1v = smith_g1f(V, a);
+  const float fspec = (f0 + (1.0f - f0) * schlick) * D * g1v * smith_g1f(L, a) / (4.0f * V.z * L.z);
+  const float ac = 0.1f * (1.0f - m.clearcoat_gloss) + 0.001f * m.clearcoat_gloss, ac2 = ac * ac;
+  const float Dc = (ac2 - 1.0f) * inv_pi / (logf(ac2) * (1.0f + (ac2 - 1.0f) * H.z * H.z));
+  const float fcc = 0.25f * m.clearcoat * (0.04f + 0.96f * schlick) * Dc * smith_g1f(V, 0.25f) *
+                    smith_g1f(L, 0.25f) / (4.0f * V.z * L.z);
+  const float wd = 1.0f - m.metallic, wc = 0.25f * m.clearcoat, sum = wd + 1.0f + wc;
+  e.pdf = (wd * L.z * inv_pi + g1v * D / (4.0f * V.z) + (vh > 0.f ? wc * Dc * H.z / (4.0f * vh) : 0.f)) / sum;
+  e.fcos = (fdiff + fspec + fcc) * L.z;
+  return e;
+}
+
+__device__ __forceinline__ F3 principled_sample(const MaterialDev &m, F3 V, float u0, float u1, float u2,
+                                                uint32_t &lobe) {
+  const float wd = 1.0f - m.metallic, wc = 0.25f * m.clearcoat, sum = wd + 1.0f + wc;
+  const float xs = u0 * sum;
+  lobe = xs < wd ? 0u : (xs < wd + 1.0f ? 1u : 2u);
+  if (lobe == 0u) {
+    float r = sqrtf(u1), s, c;
+    sincospif(2.0f * u2, &s, &c);
+    return f3(r * c, r * s, sqrtf(fmaxf(0.f, 1.f - u1)));
+  }
+  F3 H;
+  if (lobe == 1u) {
+    H = vndf_local(V, m.rough * m.rough, u1, u2);
+  } else {
+    const float ac = 0.1f * (1.0f - m.clearcoat_gloss) + 0.001f * m.clearcoat_gloss, ac2 = ac * ac;
+    const float ct = sqrtf(fmaxf(0.f, (1.0f - powf(ac2, 1.0f - u1)) / (1.0f - ac2)));
+    const float st = sqrtf(fmaxf(0.f, 1.0f - ct * ct));
+    float s, c;
+    sincospif(2.0f * u2, &s, &c);
+    H = f3(st * c, st * s, ct);
+  }
+  return (2.0f * dot(V, H)) * H - V;
+}
+
 // One lobe sample in FP32 for the incoherent tail (Lambert cosine, GGX
 // visible normals with weight F_schlick * G1(L), mirror, dielectric with
-// Fresnel choice and (eta_i/eta_t)^2 on refraction).
+// Fresnel choice and (eta_i/eta_t)^2 on refraction; with EXT also the
+// principled lobes, kept out of the base shading kernel's registers).
+template <bool EXT>
 __device__ __forceinline__ Lobe sample_lobe(const MaterialDev &m, uint32_t comp, F3 d_in, F3 ng,
                                             float u0, float u1, float u2) {
   Lobe L;
@@ -388,6 +468,18 @@ __device__ __forceinline__ Lobe sample_lobe(const MaterialDev &m, uint32_t comp,
       L.d = normalize(e * d_in + (e * ci - (float)cos_t) * nf);
       L.w = e * e; L.ev = EV_DIEL_REFR;
     }
+  } else if (EXT && m.type == HPT_PRINCIPLED) {
+    F3 b1, b2;
+    onb(nf, b1, b2);
+    F3 wo = (-1.0f) * d_in;
+    F3 V = f3(dot(wo, b1), dot(wo, b2), dot(wo, nf));
+    uint32_t lobe;
+    F3 Lw = principled_sample(m, V, u0, u1, u2, lobe);
+    L.ev = EV_PRIN_DIFFUSE + lobe;
+    if (Lw.z <= 0.f || V.z <= 0.f) { L.w = 0.f; L.ev = EV_ABSORB; return L; }
+    BsdfEval e = principled_eval(m, rgb, V, Lw);
+    L.w = e.pdf > 0.f ? e.fcos / e.pdf : 0.f;
+    L.d = normalize(Lw.x * b1 + Lw.y * b2 + Lw.z * nf);
   } else if (m.type == HPT_GGX) {
     F3 b1, b2;
     onb(nf, b1, b2);
@@ -423,7 +515,7 @@ __device__ __forceinline__ Lobe sample_lobe(const MaterialDev &m, uint32_t comp,
 // wl leaving a non-delta surface (cosines against the normal facing the
 // incoming ray d_in). GGX: f cos = F D G1(V) G1(L) / (4 V.z) and
 // pdf = G1(V) D / (4 V.z), whose ratio is the sampling weight F G1(L).
-struct BsdfEval { float fcos, pdf; };
+template <bool EXT>
 __device__ __forceinline__ BsdfEval eval_lobe(const MaterialDev &m, uint32_t comp, F3 d_in, F3 ng, F3 wl) {
   BsdfEval e{0.f, 0.f};
   F3 nf = dot(d_in, ng) < 0.f ? ng : (-1.0f) * ng;
@@ -434,6 +526,11 @@ __device__ __forceinline__ BsdfEval eval_lobe(const MaterialDev &m, uint32_t com
   if (m.type == HPT_LAMBERT) {
     e.fcos = rgb * c * inv_pi;
     e.pdf = c * inv_pi;
+  } else if (EXT && m.type == HPT_PRINCIPLED) {
+    F3 b1, b2;
+    onb(nf, b1, b2);
+    F3 wo = (-1.0f) * d_in;
+    e = principled_eval(m, rgb, f3(dot(wo, b1), dot(wo, b2), dot(wo, nf)), f3(dot(wl, b1), dot(wl, b2), c));
   } else if (m.type == HPT_GGX) {
     F3 b1, b2;
     onb(nf, b1, b2);

@@ -38,7 +38,8 @@ __host__ __device__ inline uint32_t frame_group(uint32_t T) { return T; }
 
 // Path events hashed into the signature (same codes as the FP64 reference).
 enum : uint32_t { EV_MIRROR = 1, EV_DIEL_REFL = 2, EV_DIEL_REFR = 3, EV_LAMBERT = 4, EV_GGX = 5,
-                  EV_ABSORB = 6, EV_EMIT = 7, EV_IMAGE_POINT = 8 };
+                  EV_ABSORB = 6, EV_EMIT = 7, EV_IMAGE_POINT = 8, EV_PRIN_DIFFUSE = 9,
+                  EV_PRIN_SPECULAR = 10, EV_PRIN_CLEARCOAT = 11 };
 enum : int32_t { K_NONE = 0, K_ESCAPE_PREFIX = 1, K_MAXB_PREFIX = 2, K_EMITTER = 3, K_ENV = 4,
                  K_MAXB_TAIL = 5, K_CACHE = 6, K_ABSORBED = 7 };
 
@@ -47,7 +48,8 @@ struct MaterialDev {
   float rgb[3];
   float rough, ior;
   float emit[3];
-  float pad;
+  float metallic, specular, clearcoat, clearcoat_gloss;  // HPT_PRINCIPLED
+  float pad[3];
 };
 
 // What shading needs of a hit primitive, one record per primitive in leaf

@@ -109,13 +109,13 @@ struct RayState {
   double ell;
 };
 
-template <bool NEE>
+template <bool EXT>
 __device__ __forceinline__ void load_state(const RayQueue &Q, uint32_t i, RayState &r) {
   r.i = i;
   r.slot = Q.slot[i]; r.unit = Q.unit[i]; r.meta = Q.meta[i];
   r.sig = Q.sig[i];
   r.bpre = Q.bpre[i]; r.wt = Q.wt[i]; r.beta = Q.beta[i]; r.L = Q.L[i];
-  r.pdf = (NEE && (r.meta & 1u) == STAGE_TAIL) ? Q.pdf[i] : 0.f;
+  r.pdf = (EXT && (r.meta & 1u) == STAGE_TAIL) ? Q.pdf[i] : 0.f;
   if ((r.meta & 1u) == STAGE_PREFIX) {
     r.o = D3{Q.ox[i], Q.oy[i], Q.oz[i]};
     r.d = D3{Q.dx[i], Q.dy[i], Q.dz[i]};
@@ -444,14 +444,14 @@ __device__ __forceinline__ void stage_put(StageLds &G, const RayState &r, F3 o, 
 
 // Entry k of queue Q from this lane's staged ray; the read-only words come
 // from its entry in the source queue S.
-template <bool NEE>
+template <bool EXT>
 __device__ __forceinline__ void stage_store(const StageLds &G, const RayQueue &Q, uint32_t k, const RayQueue &S) {
   const uint32_t t = threadIdx.x, i = G.i[t], meta = G.meta[t];
   Q.slot[k] = G.slot[t]; Q.unit[k] = G.unit[t]; Q.meta[k] = meta;
   Q.ka[k] = S.ka[i]; Q.kb[k] = S.kb[i];
   Q.sig[k] = G.sig[t];
   Q.bpre[k] = G.bpre[t]; Q.wt[k] = G.wt[t]; Q.beta[k] = G.beta[t]; Q.L[k] = G.L[t];
-  if (NEE) Q.pdf[k] = G.pdf[t];
+  if (EXT) Q.pdf[k] = G.pdf[t];
   if ((meta & 1u) == STAGE_PREFIX) {
     Q.ox[k] = G.ox[t]; Q.oy[k] = G.oy[t]; Q.oz[k] = G.oz[t];
     Q.dx[k] = G.dx[t]; Q.dy[k] = G.dy[t]; Q.dz[k] = G.dz[t];
@@ -614,7 +614,7 @@ __device__ float next_event(const SceneDev &S, const MaterialDev &m, uint32_t co
   const float dist = sqrtf(dot(om, om));
   om = (1.0f / dist) * om;
   const float cos_y = -dot(om, f3(nn.x, nn.y, nn.z));
-  const BsdfEval e = eval_lobe(m, comp, d_in, ng, om);
+  const BsdfEval e = eval_lobe<true>(m, comp, d_in, ng, om);
   bool vis = false;
   float c = 0.f;
   if (cos_y > 0.f && e.fcos > 0.f) {
@@ -637,7 +637,7 @@ __device__ float next_event(const SceneDev &S, const MaterialDev &m, uint32_t co
   return c;
 }
 
-template <bool NEE>
+template <bool EXT>
 __device__ __forceinline__ void tail_interaction(const BatchDev &B, const RayQueue &Q, StageLds &G,
                                                  const UnitDev &U, const JobDev &J, const SceneDev &S,
                                                  RayState &st, F3 x, F3 d_in,
@@ -646,10 +646,10 @@ __device__ __forceinline__ void tail_interaction(const BatchDev &B, const RayQue
                                                  unsigned long long sig, float t_seg, const Stack *St,
                                                  Emit &e) {
   const int32_t gid = H.gid;
-  const MaterialDev m = S.mats[H.mat];
+  const MaterialDev &m = S.mats[H.mat];
   F3 ng = hit_normal32(S, H, x);
   bool holo = U.kind == UNIT_HOLO;
-  const bool nee = NEE && J.nee && S.n_lights > 0;
+  const bool nee = EXT && J.nee && S.n_lights > 0;
   if (m.type == HPT_EMITTER) {
     sig_add(sig, EV_EMIT);
     const float cos_y = -dot(d_in, ng);
@@ -666,16 +666,16 @@ __device__ __forceinline__ void tail_interaction(const BatchDev &B, const RayQue
   }
   if (b >= J.max_bounces) { finish(B, U, J, st, K_MAXB_TAIL, b, L, sig, holo); return; }
   U4 w = philox(Q.ka[st.i], Q.kb[st.i], b << 8, stream, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
-  Lobe lb = sample_lobe(m, comp, d_in, ng, uf(w.x), uf(w.y), uf(w.z));
+  Lobe lb = sample_lobe<EXT>(m, comp, d_in, ng, uf(w.x), uf(w.y), uf(w.z));
   sig_add(sig, lb.ev);
   const bool cache_here = holo && J.use_cache && !lb.delta && (b - bP + 1) >= J.cache_depth;
   const bool nee_here = nee && !lb.delta && !cache_here;
-  if (NEE && nee_here) {
+  if (EXT && nee_here) {
     U4 wn = philox(Q.ka[st.i], Q.kb[st.i], (b << 8) | 1u, stream, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
     L += beta * next_event(S, m, comp, x, d_in, ng, gid, wn, *St, sig);
   }
   if (lb.w == 0.f) { finish(B, U, J, st, K_ABSORBED, b, L, sig, holo); return; }
-  st.pdf = (NEE && nee_here) ? eval_lobe(m, comp, d_in, ng, lb.d).pdf : 0.f;
+  st.pdf = (EXT && nee_here) ? eval_lobe<EXT>(m, comp, d_in, ng, lb.d).pdf : 0.f;
   beta *= lb.w;
   if (cache_here) {
     uint32_t res = S.cache_res, nb = S.cache_bins * S.cache_bins;
@@ -709,7 +709,7 @@ __device__ __forceinline__ void tail_interaction(const BatchDev &B, const RayQue
 // Shade entry i of queue q, whose state is st; st is updated in place for a
 // path that continues (e.on). Jl: the batch's one job in LDS (its scene and
 // materials too), or null when the batch mixes jobs.
-template <bool NEE>
+template <bool EXT>
 __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, RayState &st, StageLds &G,
                                           const JobDev *Jl, const Stack *St, Emit &e) {
   const UnitDev &U = B.units[st.unit];
@@ -741,7 +741,7 @@ __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, 
     double ell = st.ell;
     float ncur = st.wt;
     bool tri = gid >= (int32_t)S.n_sph;
-    const MaterialDev m = S.mats[H.mat];
+    const MaterialDev &m = S.mats[H.mat];
     bool delta = m.type == HPT_MIRROR || m.type == HPT_DIELECTRIC;
     double t64;
     const double4 pl = make_double4(H.g[0], H.g[1], H.g[2], H.g[3]);  // plane, or centre and radius
@@ -794,7 +794,7 @@ __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, 
     // first non-delta hit: the real image point P
     sig_add(sig, EV_IMAGE_POINT);
     image_point(B, Q, U, J, st, ell, b);
-    tail_interaction<NEE>(B, Q, G, U, J, S, st, to_f(x), to_f(d), H, b, b, comp, stream, 1.0f, 0.0f, sig, t, St,
+    tail_interaction<EXT>(B, Q, G, U, J, S, st, to_f(x), to_f(d), H, b, b, comp, stream, 1.0f, 0.0f, sig, t, St,
                           e);
     return;
   }
@@ -811,19 +811,20 @@ __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, 
   sig_add(sig, (uint32_t)gid + 1u);
   F3 d_in = f3(r1.x, r1.y, r1.z);
   F3 x = f3(r0.x, r0.y, r0.z) + t * d_in;
-  tail_interaction<NEE>(B, Q, G, U, J, S, st, x, d_in, H, b, bP, comp, stream, beta, L, sig, t, St, e);
+  tail_interaction<EXT>(B, Q, G, U, J, S, st, x, d_in, H, b, bP, comp, stream, beta, L, sig, t, St, e);
 }
 
 constexpr uint32_t kLdsMats = 64;  // materials a workgroup keeps in LDS
 
-// NEE: batches with next-event estimation. Shading then runs occlusion
-// queries: the traversal stack takes kStackLds entries per lane in LDS and
-// the lane's column of the traversal spill, so the grid is capped at the
-// spill's columns and walks the queue with a plain grid stride.
-template <bool FIRST, bool NEE>
+// EXT: batches that use next-event estimation or principled materials (the
+// base kernel leaves both out to keep its registers). Shading then may run
+// occlusion queries: the traversal stack takes kStackLds entries per lane in
+// LDS and the lane's column of the traversal spill, so the grid is capped at
+// the spill's columns and walks the queue with a plain grid stride.
+template <bool FIRST, bool EXT>
 __global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
   __shared__ StageLds G;
-  __shared__ int32_t nee_stack[NEE ? kStackLds * kBlock : 1];
+  __shared__ int32_t nee_stack[EXT ? kStackLds * kBlock : 1];
   __shared__ JobDev lds_job;
   __shared__ SceneDev lds_scene;
   __shared__ MaterialDev lds_mats[kLdsMats];
@@ -838,10 +839,10 @@ __global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
   // takes one contiguous eighth of the queue.
   const uint32_t nb8 = ((n + blockDim.x - 1) / blockDim.x + 7u) & ~7u;
   const uint32_t b = blockIdx.x;
-  const uint32_t blk = NEE ? b : (b < nb8 ? (b % 8u) * (nb8 / 8u) + b / 8u : b);
-  const uint32_t stride = NEE ? gridDim.x * blockDim.x : max(gridDim.x, nb8) * blockDim.x;
+  const uint32_t blk = EXT ? b : (b < nb8 ? (b % 8u) * (nb8 / 8u) + b / 8u : b);
+  const uint32_t stride = EXT ? gridDim.x * blockDim.x : max(gridDim.x, nb8) * blockDim.x;
   if (blk * blockDim.x >= n) return;  // no entries for this workgroup
-  const Stack St{(LdsI32)(nee_stack + (NEE ? threadIdx.x : 0u)), kBlock,
+  const Stack St{(LdsI32)(nee_stack + (EXT ? threadIdx.x : 0u)), kBlock,
                  (GlbI32)(B.stack_spill + blockIdx.x * blockDim.x + threadIdx.x), B.spill_threads};
   // A batch of one job: its job, scene and material descriptors are copied
   // to LDS once per workgroup, so shading reads them without the dependent
@@ -874,8 +875,8 @@ __global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
     if (live) {
       RayState st;
       if (FIRST) load_first(B, B.Q[q], i, st, Jl);
-      else load_state<NEE>(B.Q[q], i, st);
-      shade_one<NEE>(B, q, i, st, G, Jl, &St, e);
+      else load_state<EXT>(B.Q[q], i, st);
+      shade_one<EXT>(B, q, i, st, G, Jl, &St, e);
     }
     // compaction: wave counts from ballots, one atomic per workgroup (all
     // workgroups add to the same counter, so fewer atomics is what matters)
@@ -890,7 +891,7 @@ __global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
     }
     __syncthreads();
     const uint32_t before = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-    if (e.on) stage_store<NEE>(G, B.Q[qo], wave_base[kBlock / 64] + wave_base[wv] + before, B.Q[q]);
+    if (e.on) stage_store<EXT>(G, B.Q[qo], wave_base[kBlock / 64] + wave_base[wv] + before, B.Q[q]);
   }
 }
 
@@ -1130,9 +1131,9 @@ hipError_t launch_trace(const BatchDev &B, int q, bool count, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_shade(const BatchDev &B, int q, bool first, bool nee, hipStream_t st) {
+hipError_t launch_shade(const BatchDev &B, int q, bool first, bool ext, hipStream_t st) {
   const uint32_t g = round8(grid_for(B.n_paths));
-  if (nee) {
+  if (ext) {
     const uint32_t gn = min(g, B.spill_threads / (uint32_t)kBlock);  // one spill column per lane
     if (first)
       hipLaunchKernelGGL((k_shade<true, true>), dim3(gn), dim3(kBlock), 0, st, B, q);

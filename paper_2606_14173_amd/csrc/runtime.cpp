@@ -66,6 +66,7 @@ struct Scene {
   size_t cache_bytes = 0;
   hpt_cache_desc cache_desc{};
   int users = 0;
+  bool principled = false;   // some material is HPT_PRINCIPLED
 };
 
 struct Grf {
@@ -88,6 +89,7 @@ struct Job {
   Scene *scene = nullptr;
   Grf *grf = nullptr;
   bool cache_build = false;
+  bool ext = false;       // needs the extended shading kernel: next-event estimation or principled materials
   JobDev host{};
   JobDev *dev = nullptr;
   float2 *field = nullptr;
@@ -171,7 +173,7 @@ struct hpt_ctx {
     unsigned long long *h_work = nullptr; // pinned: node visits, primitive tests
     hipEvent_t ev0 = nullptr, ev_rg = nullptr, ev_shade = nullptr, ev_done = nullptr;
     BatchDev B{};               // the batch's device view (for its accumulation)
-    bool has_f64 = false, has_f32 = false, has_nee = false;
+    bool has_f64 = false, has_f32 = false, has_ext = false;
     bool acc_pending = false;   // accumulation not enqueued yet
     hipEvent_t pev[kEvents] = {};
     int ne = 0;
@@ -387,10 +389,10 @@ std::vector<Picked> pick_batch(hpt_ctx *C) {
   int mode = -1;
   for (size_t k = 0; k < nr && mode < 0; ++k) {
     const Job *J = C->running[(C->batches + k) % nr];
-    if (!J->cancel && J->next < J->units.size()) mode = J->host.nee ? 1 : 0;
+    if (!J->cancel && J->next < J->units.size()) mode = J->ext ? 1 : 0;
   }
   for (size_t j = 0; j < nr; ++j)
-    if ((C->running[j]->host.nee ? 1 : 0) != mode) blocked[j] = true;
+    if ((C->running[j]->ext ? 1 : 0) != mode) blocked[j] = true;
   bool progress = true;
   while (progress && out.size() < kMaxUnitsPerBatch) {
     progress = false;
@@ -459,7 +461,7 @@ hpt_status launch_batch(hpt_ctx *C, int si, int prev) {
   hpt_ctx::Slot &L = C->slots[si];
   const std::vector<Picked> &P = L.P;
   uint32_t slot = 0, acc = 0, max_b = 0;
-  L.has_holo = L.has_cache = L.has_f64 = L.has_f32 = L.has_nee = false;
+  L.has_holo = L.has_cache = L.has_f64 = L.has_f32 = L.has_ext = false;
   for (size_t k = 0; k < P.size(); ++k) {
     const Unit &u = P[k].job->units[P[k].unit];
     UnitDev &d = L.h_units[k];
@@ -469,10 +471,10 @@ hpt_status launch_batch(hpt_ctx *C, int si, int prev) {
     slot += u.p_n * u.s_n;
     acc += u.kind == UNIT_HOLO ? u.p_n * frame_group(J.T) : u.p_n;
     max_b = std::max(max_b, J.max_bounces);
+    if (P[k].job->ext) L.has_ext = true;
     if (u.kind == UNIT_HOLO) {
       L.has_holo = true;
       if (J.phase_mode == HPT_PHASE_FP64) L.has_f64 = true; else L.has_f32 = true;
-      if (J.nee) L.has_nee = true;
     } else {
       L.has_cache = true;
     }
@@ -507,7 +509,7 @@ hpt_status launch_batch(hpt_ctx *C, int si, int prev) {
   for (uint32_t it = 0; it <= max_b; ++it) {
     int q = (int)(it & 1u);
     timed_launch(L, HPT_K_TRACE, S, e, [&] { return launch_trace(B, q, profile >= 2, S); });
-    timed_launch(L, HPT_K_SHADE, S, e, [&] { return launch_shade(B, q, it == 0, L.has_nee, S); });
+    timed_launch(L, HPT_K_SHADE, S, e, [&] { return launch_shade(B, q, it == 0, L.has_ext, S); });
   }
   if (e == hipSuccess) e = hipMemcpyAsync(L.h_cnt, B.counters, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, S);
   if (e == hipSuccess && profile >= 2)
@@ -841,9 +843,14 @@ hpt_status hpt_scene_upload(hpt_ctx *C, const hpt_scene_desc *d, uint64_t *out) 
     return fail(HPT_EINVAL, "missing material arrays");
   if ((uint64_t)d->n_tri + d->n_sph >= (1ull << 27)) return fail(HPT_EINVAL, "too many primitives");
   for (uint32_t i = 0; i < d->n_mat; ++i) {
-    if (d->mat_type[i] > HPT_EMITTER) return fail(HPT_EINVAL, "unknown material type");
-    if (d->mat_type[i] == HPT_GGX && !(d->mat_rough[i] > 0.f && d->mat_rough[i] <= 1.f))
-      return fail(HPT_EINVAL, "GGX roughness must be in (0, 1]");
+    if (d->mat_type[i] > HPT_PRINCIPLED) return fail(HPT_EINVAL, "unknown material type");
+    if ((d->mat_type[i] == HPT_GGX || d->mat_type[i] == HPT_PRINCIPLED) &&
+        !(d->mat_rough[i] > 0.f && d->mat_rough[i] <= 1.f))
+      return fail(HPT_EINVAL, "GGX and principled roughness must be in (0, 1]");
+    if (d->mat_type[i] == HPT_PRINCIPLED && d->mat_pbr)
+      for (int k = 0; k < 4; ++k)
+        if (!(d->mat_pbr[4 * i + k] >= 0.f && d->mat_pbr[4 * i + k] <= 1.f))
+          return fail(HPT_EINVAL, "principled parameters must be in [0, 1]");
     if (d->mat_type[i] == HPT_DIELECTRIC && !(d->mat_ior[i] > 1.f && std::isfinite(d->mat_ior[i])))
       return fail(HPT_EINVAL, "dielectric index must be > 1");
     if (!finite3(d->mat_rgb + 3 * i) || !finite3(d->mat_emit + 3 * i)) return fail(HPT_EINVAL, "non-finite material");
@@ -884,7 +891,11 @@ hpt_status hpt_scene_upload(hpt_ctx *C, const hpt_scene_desc *d, uint64_t *out) 
     MaterialDev &m = mats[i];
     m.type = d->mat_type[i];
     for (int c = 0; c < 3; ++c) { m.rgb[c] = d->mat_rgb[3 * i + c]; m.emit[c] = d->mat_emit[3 * i + c]; }
-    m.rough = d->mat_rough[i]; m.ior = d->mat_ior[i]; m.pad = 0.f;
+    m.rough = d->mat_rough[i]; m.ior = d->mat_ior[i];
+    const float *pb = d->mat_pbr ? d->mat_pbr + 4 * i : nullptr;
+    m.metallic = pb ? pb[0] : 0.f; m.specular = pb ? pb[1] : 0.5f;
+    m.clearcoat = pb ? pb[2] : 0.f; m.clearcoat_gloss = pb ? pb[3] : 1.f;
+    m.pad[0] = m.pad[1] = m.pad[2] = 0.f;
   }
   // one shading record per primitive in leaf order: FP64 plane of a triangle
   // (the coherent-prefix refinement and the hit normal) or the sphere itself
@@ -964,6 +975,8 @@ hpt_status hpt_scene_upload(hpt_ctx *C, const hpt_scene_desc *d, uint64_t *out) 
   }
   h.n_lights = (uint32_t)light_cdf.size();
   h.light_area = light_area;
+  for (uint32_t i = 0; i < d->n_mat; ++i)
+    if (d->mat_type[i] == HPT_PRINCIPLED) S->principled = true;
   h.n_sph = d->n_sph; h.n_tri = d->n_tri; h.n_mat = d->n_mat; h.n_nodes = n ? bvh.n_nodes : 0;
   for (int c = 0; c < 3; ++c) h.env[c] = d->env[c];
   ok &= C->alloc((void **)&S->dev, sizeof(SceneDev)) == hipSuccess;
@@ -1053,6 +1066,7 @@ hpt_status hpt_cache_build(hpt_ctx *C, uint64_t scene, const hpt_cache_desc *cd)
     J->id = id = C->next_id++;
     J->scene = S;
     J->cache_build = true;
+    J->ext = S->principled;
     JobDev &jd = J->host;
     std::memset(&jd, 0, sizeof(jd));
     jd.max_bounces = cd->max_bounces;
@@ -1136,6 +1150,7 @@ hpt_status hpt_trace_submit(hpt_ctx *C, uint64_t scene, const hpt_job_desc *d, v
   auto J = std::make_unique<Job>();
   J->desc = *d;
   J->scene = S;
+  J->ext = S->principled || d->nee != 0;
   JobDev &jd = J->host;
   std::memset(&jd, 0, sizeof(jd));
   jd.width = d->width; jd.height = d->height; jd.pitch = d->pitch;
