@@ -114,6 +114,9 @@ def main():
                          "point, then angular-spectrum propagation 80 mm to the hologram plane")
     ap.add_argument("--serving", action="store_true",
                     help="continuous batching: Poisson arrivals over four resident scenes")
+    ap.add_argument("--estimators", action="store_true",
+                    help="tail estimators on the 512^2 RGB T=8 mixed-material workload: BSDF sampling "
+                         "against next-event estimation with MIS (time and Monte Carlo noise)")
     ap.add_argument("--requests", type=int, default=96)
     ap.add_argument("--load", type=float, default=0.8)
     args = ap.parse_args()
@@ -136,6 +139,8 @@ def main():
         return precision_sweep(hpt)
     if args.serving:
         return serving(hpt, args.requests, args.load)
+    if args.estimators:
+        return estimators(hpt, args.steps, args.warmup)
     if args.two_stage:
         return two_stage(hpt, args.steps, args.warmup)
 
@@ -434,6 +439,44 @@ def two_stage(hpt, steps, warmup):
         "encoding_ms_per_step": round(1e3 * te / steps / enc_steps, 2),
         "encoding_final_rel_loss_mean": round(float(np.mean(np.concatenate(losses))), 5)}}
     print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+def estimators(hpt, steps, warmup):
+    """The 512 x 512 RGB, 64 spp, 4-bounce, T = 8 job on the ~58k-triangle
+    mixed-material scene with its quad light, traced with BSDF sampling only
+    and with next-event estimation (MIS): ms per hologram, and the noise of
+    the amplitude estimate on a central 64 x 64 crop: per pixel and channel
+    the variance over the 64 samples of A^2 = beta_pre L (what the amplitude
+    sqrt(beta_pre L) carries), averaged, over the squared mean of A^2 (the
+    hologram field itself is a random-phase sum whose sample-to-sample
+    spread is set by the phases, not by the radiance estimator)."""
+    import scenes
+    from scenes import jobs
+    sc = scenes.scene_mid(1)
+    ctx = hpt.Context(0)
+    sid = ctx.upload_scene(sc)
+    out = {}
+    for nee in (0, 1):
+        job = jobs.job_for_config(1, nee=nee)
+        for _ in range(warmup):
+            ctx.trace(sid, job)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ua = ctx.trace(sid, dict(job, seed=11))
+        dt = (time.perf_counter() - t0) / steps
+        rec = ctx.trace(sid, dict(job, crop=(224, 224, 64, 64)), records=True)[1]
+        a2 = rec["A"].astype(np.float64) ** 2          # [ch, h, w, spp]
+        noise = float(np.mean(a2.var(axis=-1)) / max(np.mean(a2) ** 2, 1e-300))
+        n_paths = len(job["lambdas"]) * job["width"] * job["height"] * job["spp"]
+        out["nee" if nee else "bsdf"] = {"ms_per_hologram": round(1e3 * dt, 2),
+                                         "path_samples_per_s": round(n_paths / dt, 1),
+                                         "amplitude_sq_relative_variance": round(noise, 5)}
+        log("estimator %s: %.1f ms, noise %.4f" % ("nee" if nee else "bsdf", 1e3 * dt, noise))
+    out["workload"] = "512x512 RGB T=8, ~58k-triangle mixed-material scene with a quad light, 64 spp, 4 bounces"
+    out["variance_ratio_nee_over_bsdf"] = round(out["nee"]["amplitude_sq_relative_variance"] /
+                                                out["bsdf"]["amplitude_sq_relative_variance"], 4)
+    print(json.dumps({"estimators": out}), flush=True)
     ctx.close()
 
 
