@@ -21,10 +21,11 @@
 // plane the column pass writes to a second buffer and k_ifft_rows_intensity
 // sums |u|^2 over the fields instead of writing the fields.
 //
-// Line FFTs run in LDS, one workgroup per line: radix-4 Stockham stages
-// (Govindaraju et al., SC 2008 formulation), a final radix-2 stage when
-// log2(n) is odd; each stage reads its operands into registers, synchronises,
-// and writes the results back in place. Twiddles come from a table of
+// Line FFTs run in LDS, one workgroup per line: Stockham stages
+// (Govindaraju et al., SC 2008 formulation) of radix 16 while they fit, then
+// radix 4, then a radix-2 stage for an odd remainder; each stage reads its
+// operands into registers, synchronises, and writes the results back in
+// place. Twiddles come from a table of
 // exp(-2 pi i m / n), m < n, per transform length, built once per call in FP64.
 #include <hip/hip_runtime.h>
 
@@ -60,18 +61,90 @@ __device__ __forceinline__ C2 twiddle(const float2 *tw, uint32_t m, bool inv) {
   return c2(v.x, inv ? -v.y : v.y);
 }
 
+// Radix-4 DFT of a[0..3] in place (forward: exp(-2 pi i), inverse: +).
+__device__ __forceinline__ void dft4(C2 &a0, C2 &a1, C2 &a2, C2 &a3, bool inv) {
+  C2 b0 = add(a0, a2), b1 = sub(a0, a2), b2 = add(a1, a3), b3 = rot(sub(a1, a3), inv);
+  a0 = add(b0, b2);
+  a1 = add(b1, b3);
+  a2 = sub(b0, b2);
+  a3 = sub(b1, b3);
+}
+
+// Radix-16 DFT of a[0..15] in place, as 4 x 4: DFT-4 over n1 of a[4 n1 + n2]
+// for each n2, twiddles exp(-+2 pi i n2 k1 / 16), DFT-4 over n2; output k =
+// k1 + 4 k2 lands in a[k].
+__device__ __forceinline__ void dft16(C2 (&a)[16], bool inv) {
+  // exp(-2 pi i m / 16), m = 0..9
+  constexpr float c1 = 0.923879532511286756f, s1 = 0.382683432365089772f, h = 0.707106781186547524f;
+  const float cs[10][2] = {{1.f, 0.f}, {c1, -s1}, {h, -h}, {s1, -c1}, {0.f, -1.f},
+                           {-s1, -c1}, {-h, -h}, {-c1, -s1}, {-1.f, 0.f}, {-c1, s1}};
+  C2 t[16];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+    C2 b0 = a[n2], b1 = a[n2 + 4], b2 = a[n2 + 8], b3 = a[n2 + 12];
+    dft4(b0, b1, b2, b3, inv);
+    t[4 * n2 + 0] = b0; t[4 * n2 + 1] = b1; t[4 * n2 + 2] = b2; t[4 * n2 + 3] = b3;   // t[n2][k1]
+  }
+#pragma unroll
+  for (int n2 = 1; n2 < 4; ++n2)
+#pragma unroll
+    for (int k1 = 1; k1 < 4; ++k1) {
+      const int m = n2 * k1;
+      t[4 * n2 + k1] = mul(t[4 * n2 + k1], c2(cs[m][0], inv ? -cs[m][1] : cs[m][1]));
+    }
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    C2 b0 = t[k1], b1 = t[4 + k1], b2 = t[8 + k1], b3 = t[12 + k1];
+    dft4(b0, b1, b2, b3, inv);
+    a[k1] = b0; a[k1 + 4] = b1; a[k1 + 8] = b2; a[k1 + 12] = b3;
+  }
+}
+
 // In-place FFT of the n = 2^lg values in LDS buffer x (all threads of the
-// block take part; returns synchronised). Each thread handles butterflies
-// j = tid + u * kFftThreads; the per-thread operands stay in registers
-// (static indices), written back after the whole stage has been read.
-// U4: butterflies per thread and radix-4 stage (n <= 4 * U4 * kFftThreads).
+// block take part; returns synchronised): Stockham radix-16 stages while
+// they fit, then radix-4, then a radix-2 stage for odd remainders. Each
+// thread handles butterflies j = tid + u * kFftThreads; the per-thread
+// operands stay in registers (static indices), written back after the whole
+// stage has been read. U4: n <= 4 * U4 * kFftThreads.
 template <int U4>
 __device__ void lds_fft(C2 *x, uint32_t n, uint32_t lg, bool inv, const float2 *tw) {
   constexpr int U2 = 2 * U4;
+  constexpr int U16 = (U4 + 3) / 4;
   const uint32_t tid = threadIdx.x;
   uint32_t Ns = 1;
+  const uint32_t q16 = n / 16;
+  for (uint32_t s = 0; s < lg / 4; ++s) {
+    C2 v[U16][16];
+#pragma unroll
+    for (int u = 0; u < U16; ++u) {
+      const uint32_t j = tid + (uint32_t)u * kFftThreads;
+      if (j < q16) {
+        const uint32_t k = j % Ns;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) v[u][r] = x[pd<U4>(j + (uint32_t)r * q16)];
+        if (Ns > 1) {  // exp(-+2 pi i r k / (16 Ns)) = tw[r k n / (16 Ns)]
+          const uint32_t st = k * (n / (16 * Ns));
+#pragma unroll
+          for (int r = 1; r < 16; ++r) v[u][r] = mul(v[u][r], twiddle(tw, (uint32_t)r * st, inv));
+        }
+        dft16(v[u], inv);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U16; ++u) {
+      const uint32_t j = tid + (uint32_t)u * kFftThreads;
+      if (j < q16) {
+        const uint32_t d = (j / Ns) * Ns * 16 + j % Ns;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) x[pd<U4>(d + (uint32_t)r * Ns)] = v[u][r];
+      }
+    }
+    __syncthreads();
+    Ns *= 16;
+  }
   const uint32_t q = n / 4;
-  for (uint32_t s = 0; s < lg / 2; ++s) {
+  for (uint32_t s = 0; s < (lg % 4) / 2; ++s) {
     C2 v[U4][4];
 #pragma unroll
     for (int u = 0; u < U4; ++u) {
