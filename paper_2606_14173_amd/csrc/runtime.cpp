@@ -1328,6 +1328,10 @@ hpt_status hpt_grf_read(hpt_ctx *C, uint32_t gw, uint32_t gh, uint32_t T, uint64
 
 }  // extern "C"
 
+// Fields per launch of the FFT passes: their grids index fields in a
+// dimension limited to 65535 blocks.
+constexpr uint32_t kMaxFieldsPerLaunch = 65535;
+
 namespace {
 // Transfer-function constants of one propagation (na > 0: pupil cutoff NA / lambda).
 AsmParams asm_params(uint32_t width, uint32_t height, double pitch, double lambda, double distance, uint32_t flags,
@@ -1372,7 +1376,8 @@ hpt_status hpt_asm_propagate(hpt_ctx *C, const void *d_in, void *d_out, uint32_t
     uint64_t free_b = C->budget > C->used ? C->budget - C->used : 0;
     if (free_b < per) evict_grfs(C, per);
     free_b = C->budget > C->used ? C->budget - C->used : 0;
-    chunk = (uint32_t)std::min<uint64_t>({(uint64_t)n_fields, free_b / per, std::max<uint64_t>(1, (1ull << 30) / per)});
+    chunk = (uint32_t)std::min<uint64_t>({(uint64_t)n_fields, free_b / per, std::max<uint64_t>(1, (1ull << 30) / per),
+                                           (uint64_t)kMaxFieldsPerLaunch});
     if (chunk == 0) return fail(HPT_EBUDGET, "propagation scratch does not fit the budget");
     const size_t half = (size_t)chunk * height * px * sizeof(float2);
     if (C->alloc((void **)&A, half) != hipSuccess) return fail(HPT_ENOMEM, "scratch allocation failed");
@@ -1441,7 +1446,8 @@ hpt_status hpt_encode_phase(hpt_ctx *C, const void *d_fields, uint32_t n_fields,
     if (free_b < per + fixed) evict_grfs(C, per + fixed);
     free_b = C->budget > C->used ? C->budget - C->used : 0;
     free_b = free_b > fixed ? free_b - fixed : 0;
-    chunk = (uint32_t)std::min<uint64_t>({(uint64_t)n_fields, free_b / per, std::max<uint64_t>(1, (1ull << 30) / per)});
+    chunk = (uint32_t)std::min<uint64_t>({(uint64_t)n_fields, free_b / per, std::max<uint64_t>(1, (1ull << 30) / per),
+                                           (uint64_t)kMaxFieldsPerLaunch});
     if (chunk == 0) return fail(HPT_EBUDGET, "encoding scratch does not fit the budget");
     const size_t f = (size_t)chunk * hw, ap = (size_t)chunk * height * px;
     bufs = {{(void **)&V, 8 * f}, {(void **)&a, 8 * f}, {(void **)&R, 8 * f}, {(void **)&m, 4 * f},
@@ -1521,7 +1527,8 @@ hpt_status hpt_reconstruct(hpt_ctx *C, const void *d_fields, uint32_t n_ch, uint
     if (free_b < per + tw_bytes) evict_grfs(C, per + tw_bytes);
     free_b = C->budget > C->used ? C->budget - C->used : 0;
     free_b = free_b > tw_bytes ? free_b - tw_bytes : 0;
-    chunk = (uint32_t)std::min<uint64_t>({(uint64_t)T, free_b / per, std::max<uint64_t>(1, (1ull << 30) / per)});
+    chunk = (uint32_t)std::min<uint64_t>({(uint64_t)T, free_b / per, std::max<uint64_t>(1, (1ull << 30) / per),
+                                           (uint64_t)kMaxFieldsPerLaunch});
     if (chunk == 0) return fail(HPT_EBUDGET, "reconstruction scratch does not fit the budget");
     third = (size_t)chunk * height * px * sizeof(float2);
     bool ok = C->alloc((void **)&A, third) == hipSuccess;

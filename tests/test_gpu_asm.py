@@ -119,3 +119,12 @@ def test_two_stage_pipeline(ctx):
     ref = oasm.propagate(Uom[0], job["pitch"], lam, 30e-3)
     got = _gpu(ctx, Ugm[0].astype(np.complex64), job["pitch"], lam, 30e-3, True)
     _check(got, ref, "two-stage %dx%d T=%d" % (w, h, T))
+
+
+def test_asm_more_fields_than_one_launch_holds(ctx):
+    """70000 fields of 2 x 3: more than the 65535 fields one launch's grid
+    indexes, so the call runs in two chunks."""
+    u = (np.random.default_rng(3).normal(size=(70000, 2, 3)) * (1 + 1j)).astype(np.complex64)
+    ref = oasm.propagate(u.astype(np.complex128), 8e-6, 520e-9, 1e-3)
+    got = _gpu(ctx, u, 8e-6, 520e-9, 1e-3, True)
+    _check(got, ref, "70000 fields")
