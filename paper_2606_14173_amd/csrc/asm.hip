@@ -100,20 +100,16 @@ __device__ __forceinline__ void dft16(C2 (&a)[16], bool inv) {
   }
 }
 
-// In-place FFT of the n = 2^lg values in LDS buffer x (all threads of the
-// block take part; returns synchronised): Stockham radix-16 stages while
-// they fit, then radix-4, then a radix-2 stage for odd remainders. Each
-// thread handles butterflies j = tid + u * kFftThreads; the per-thread
-// operands stay in registers (static indices), written back after the whole
-// stage has been read. U4: n <= 4 * U4 * kFftThreads.
+// One Stockham radix-16 stage of an n-point FFT in LDS (all threads take
+// part; reads, synchronises, writes, synchronises): butterfly j takes
+// x[j + r n/16], r < 16, twiddled by exp(-+2 pi i r k / (16 Ns)), k = j mod
+// Ns, and writes its 16-point DFT to x[(j / Ns) 16 Ns + k + r Ns].
 template <int U4>
-__device__ void lds_fft(C2 *x, uint32_t n, uint32_t lg, bool inv, const float2 *tw) {
-  constexpr int U2 = 2 * U4;
+__device__ __forceinline__ void stage16(C2 *x, uint32_t n, uint32_t Ns, bool inv, const float2 *tw) {
   constexpr int U16 = (U4 + 3) / 4;
   const uint32_t tid = threadIdx.x;
-  uint32_t Ns = 1;
   const uint32_t q16 = n / 16;
-  for (uint32_t s = 0; s < lg / 4; ++s) {
+  {
     C2 v[U16][16];
 #pragma unroll
     for (int u = 0; u < U16; ++u) {
@@ -141,6 +137,22 @@ __device__ void lds_fft(C2 *x, uint32_t n, uint32_t lg, bool inv, const float2 *
       }
     }
     __syncthreads();
+  }
+}
+
+// In-place FFT of the n = 2^lg values in LDS buffer x (all threads of the
+// block take part; returns synchronised): Stockham radix-16 stages while
+// they fit, then radix-4, then a radix-2 stage for odd remainders. Each
+// thread handles butterflies j = tid + u * kFftThreads; the per-thread
+// operands stay in registers (static indices), written back after the whole
+// stage has been read. U4: n <= 4 * U4 * kFftThreads.
+template <int U4>
+__device__ void lds_fft(C2 *x, uint32_t n, uint32_t lg, bool inv, const float2 *tw) {
+  constexpr int U2 = 2 * U4;
+  const uint32_t tid = threadIdx.x;
+  uint32_t Ns = 1;
+  for (uint32_t s = 0; s < lg / 4; ++s) {
+    stage16<U4>(x, n, Ns, inv, tw);
     Ns *= 16;
   }
   const uint32_t q = n / 4;
@@ -277,6 +289,55 @@ __global__ void __launch_bounds__(kFftThreads) k_fft_columns(const float2 *src, 
         Hr[u] = c2((float)cs, (float)sn);
       }
     }
+  }
+  if constexpr (U4 == 4) {
+    // 4096-point columns: the three radix-16 stages of each transform map
+    // thread t to elements t + 256 r at both ends, so the first forward stage
+    // reads the column from global memory, the last forward stage, the
+    // transfer function and the first inverse stage stay in registers, and
+    // the last inverse stage writes rows [0, h) to global memory: 4 LDS
+    // passes per field instead of 8 plus the multiply pass.
+    for (uint32_t f = 0; f < nf; ++f) {
+      const float2 *scol = src + ((size_t)f * px + kx) * h;
+      float2 *col = dst + ((size_t)f * px + kx) * h;
+      C2 v[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const uint32_t i = t + (uint32_t)r * kFftThreads;
+        const float2 g = i < h ? scol[i] : make_float2(0.f, 0.f);
+        v[r] = c2(g.x, g.y);
+      }
+      dft16(v, false);                                   // forward stage, Ns = 1
+      __syncthreads();                                   // the previous field's last reads are done
+#pragma unroll
+      for (int r = 0; r < 16; ++r) lds[pd<U4>(16 * t + (uint32_t)r)] = v[r];
+      __syncthreads();
+      stage16<U4>(lds, py, 16, false, tw);               // forward stage, Ns = 16
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = lds[pd<U4>(t + (uint32_t)r * kFftThreads)];
+#pragma unroll
+      for (int r = 1; r < 16; ++r) v[r] = mul(v[r], twiddle(tw, (uint32_t)r * t, false));
+      dft16(v, false);                                   // forward stage, Ns = 256: v[r] = X[t + 256 r]
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = mul(v[r], Hr[r]);
+      dft16(v, true);                                    // inverse stage, Ns = 1
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 16; ++r) lds[pd<U4>(16 * t + (uint32_t)r)] = v[r];
+      __syncthreads();
+      stage16<U4>(lds, py, 16, true, tw);                // inverse stage, Ns = 16
+#pragma unroll
+      for (int r = 0; r < 16; ++r) v[r] = lds[pd<U4>(t + (uint32_t)r * kFftThreads)];
+#pragma unroll
+      for (int r = 1; r < 16; ++r) v[r] = mul(v[r], twiddle(tw, (uint32_t)r * t, true));
+      dft16(v, true);                                    // inverse stage, Ns = 256
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const uint32_t i = t + (uint32_t)r * kFftThreads;
+        if (i < h) col[i] = make_float2(v[r].x, v[r].y);
+      }
+    }
+    return;
   }
   for (uint32_t f = 0; f < nf; ++f) {
     const float2 *scol = src + ((size_t)f * px + kx) * h;
