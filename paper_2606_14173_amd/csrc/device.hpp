@@ -76,6 +76,24 @@ __device__ __forceinline__ float4 ld4(GF4 p) {
   v4f v = *p;
   return make_float4(v.x, v.y, v.z, v.w);
 }
+// The same for a pointer of any type that is known to address global memory
+// (a pointer read from a descriptor in LDS would otherwise be taken as flat).
+// The host pass, which only parses device code, sees plain pointers.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using GPtr = T __attribute__((address_space(1))) *;
+#else
+template <class T>
+using GPtr = T *;
+#endif
+template <class T>
+__device__ __forceinline__ GPtr<T> glb(T *p) {
+  return (GPtr<T>)(void *)p;
+}
+template <class T>
+__device__ __forceinline__ GPtr<const T> glb(const T *p) {
+  return (GPtr<const T>)(const void *)p;
+}
 
 // Watertight ray/triangle test (Woop, Benthin, Wald, JCGT 2013) in FP32 with
 // per-ray shear constants; returns t in (tmin, tbest] or leaves best alone.

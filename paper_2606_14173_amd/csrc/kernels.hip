@@ -96,12 +96,13 @@ __device__ __forceinline__ uint32_t morton8(float u, float v) {
 }
 
 // State of one live ray that shading changes, loaded from entry i of queue
-// q; the read-only words (Philox keys, direction cosines) stay in the source
-// entry, are read where they are used, and are copied to the ray's next
-// entry when the path continues.
+// q; the Philox key words are read with it, the direction cosines stay in the
+// source entry, are read where they are used, and are copied to the ray's
+// next entry when the path continues.
 struct RayState {
   uint32_t i;                // entry in the source queue
   uint32_t slot, unit, meta;
+  uint32_t ka, kb;           // Philox key words of the path
   unsigned long long sig;
   float bpre, wt, beta, L;   // wt: medium index while in the prefix, then the weight W
   float pdf;                 // lobe pdf of this ray when next-event estimation covers it, else 0
@@ -112,7 +113,8 @@ struct RayState {
 template <bool EXT>
 __device__ __forceinline__ void load_state(const RayQueue &Q, uint32_t i, RayState &r) {
   r.i = i;
-  r.slot = Q.slot[i]; r.unit = Q.unit[i]; r.meta = Q.meta[i];
+  r.slot = Q.slot[i]; r.meta = Q.meta[i];
+  r.ka = Q.ka[i]; r.kb = Q.kb[i];
   r.sig = Q.sig[i];
   r.bpre = Q.bpre[i]; r.wt = Q.wt[i]; r.beta = Q.beta[i]; r.L = Q.L[i];
   r.pdf = (EXT && (r.meta & 1u) == STAGE_TAIL) ? Q.pdf[i] : 0.f;
@@ -265,18 +267,19 @@ __device__ __forceinline__ void gen_path(const BatchDev &B, uint32_t i, RayState
 }
 
 // State of entry i of the first queue, as gen_path made it (store_first).
-__device__ __forceinline__ void load_first(const BatchDev &B, const RayQueue &Q, uint32_t i, RayState &r,
-                                           const JobDev *Jl) {
+// The cone direction is read for every entry (a cache path's entry holds
+// stale words there, unused), so that all loads are in flight together.
+__device__ __forceinline__ void load_first(const RayQueue &Q, uint32_t i, RayState &r, const UnitDev &U,
+                                           const JobDev &J) {
   r.i = i;
-  r.slot = Q.slot[i]; r.unit = Q.unit[i];
+  r.slot = Q.slot[i];
+  r.ka = Q.ka[i]; r.kb = Q.kb[i];
+  const double al = Q.al[i], be = Q.be[i];
   r.sig = kSigInit;
   r.bpre = 1.f; r.wt = 1.f; r.beta = 1.f; r.L = 0.f; r.pdf = 0.f;
-  const UnitDev &U = B.units[r.unit];
   if (U.kind == UNIT_HOLO) {
-    const JobDev &J = Jl ? *Jl : *U.job;
-    const uint32_t gpix = Q.ka[i];
     r.meta = STAGE_PREFIX;
-    primary_ray(J, gpix % J.width, gpix / J.width, Q.al[i], Q.be[i], r.o, r.d);
+    primary_ray(J, r.ka % J.width, r.ka / J.width, al, be, r.o, r.d);
     r.ell = 0.0;
   } else {
     r.meta = STAGE_TAIL;
@@ -418,7 +421,7 @@ struct Emit { bool on; };
 // finalises them until the compaction has given them their entry in the next
 // queue; this keeps the new state out of registers for the rest of the pass.
 struct StageLds {
-  uint32_t i[kBlock], slot[kBlock], unit[kBlock], meta[kBlock];
+  uint32_t i[kBlock], slot[kBlock], unit[kBlock], meta[kBlock], ka[kBlock], kb[kBlock];
   unsigned long long sig[kBlock];
   float bpre[kBlock], wt[kBlock], beta[kBlock], L[kBlock], pdf[kBlock];
   double ox[kBlock], oy[kBlock], oz[kBlock], dx[kBlock], dy[kBlock], dz[kBlock], ell[kBlock];
@@ -429,6 +432,7 @@ struct StageLds {
 __device__ __forceinline__ void stage_put(StageLds &G, const RayState &r, F3 o, F3 d, int32_t excl, Emit &e) {
   const uint32_t t = threadIdx.x;
   G.i[t] = r.i; G.slot[t] = r.slot; G.unit[t] = r.unit; G.meta[t] = r.meta;
+  G.ka[t] = r.ka; G.kb[t] = r.kb;
   G.sig[t] = r.sig;
   G.bpre[t] = r.bpre; G.wt[t] = r.wt; G.beta[t] = r.beta; G.L[t] = r.L; G.pdf[t] = r.pdf;
   if ((r.meta & 1u) == STAGE_PREFIX) {
@@ -442,13 +446,13 @@ __device__ __forceinline__ void stage_put(StageLds &G, const RayState &r, F3 o, 
   e.on = true;
 }
 
-// Entry k of queue Q from this lane's staged ray; the read-only words come
+// Entry k of queue Q from this lane's staged ray; the direction cosines come
 // from its entry in the source queue S.
 template <bool EXT>
 __device__ __forceinline__ void stage_store(const StageLds &G, const RayQueue &Q, uint32_t k, const RayQueue &S) {
   const uint32_t t = threadIdx.x, i = G.i[t], meta = G.meta[t];
   Q.slot[k] = G.slot[t]; Q.unit[k] = G.unit[t]; Q.meta[k] = meta;
-  Q.ka[k] = S.ka[i]; Q.kb[k] = S.kb[i];
+  Q.ka[k] = G.ka[t]; Q.kb[k] = G.kb[t];
   Q.sig[k] = G.sig[t];
   Q.bpre[k] = G.bpre[t]; Q.wt[k] = G.wt[t]; Q.beta[k] = G.beta[t]; Q.L[k] = G.L[t];
   if (EXT) Q.pdf[k] = G.pdf[t];
@@ -466,7 +470,7 @@ __device__ __forceinline__ void write_rec_tail(const JobDev &J, const UnitDev &U
                                                float amp, unsigned long long sig) {
   uint32_t p_local, s_local;
   slot_decode(U, slot, p_local, s_local);
-  hpt_path_record *R = J.rec + rec_index(J, U, p_local, s_local);
+  auto R = glb(J.rec) + rec_index(J, U, p_local, s_local);
   R->sig = sig; R->kind = kind; R->n_hits = (int32_t)b; R->A = A; R->amp = amp;
   R->first_gid = B.s_first[slot];
   if (kind != K_CACHE) { R->cache_cell = -1; R->cache_bin = -1; }
@@ -496,7 +500,7 @@ __device__ __forceinline__ void finish(const BatchDev &B, const UnitDev &U, cons
 __device__ __forceinline__ void image_point(const BatchDev &B, const RayQueue &Q, const UnitDev &U,
                                             const JobDev &J, RayState &st, double ell, uint32_t bP) {
   const uint32_t slot = st.slot;
-  uint32_t gpix = Q.ka[st.i];
+  uint32_t gpix = st.ka;
   uint32_t px = gpix % J.width, py = gpix / J.width;
   double al = Q.al[st.i], be = Q.be[st.i];
   double s = J.s_cone[U.ch];
@@ -582,7 +586,7 @@ __device__ __forceinline__ void image_point(const BatchDev &B, const RayQueue &Q
   if (J.debug & 1u) {
     uint32_t p_local, s_local;
     slot_decode(U, slot, p_local, s_local);
-    hpt_path_record *R = J.rec + rec_index(J, U, p_local, s_local);
+    auto R = glb(J.rec) + rec_index(J, U, p_local, s_local);
     R->bP = (int32_t)bP; R->ell = ell; R->r = r; R->W = W; R->qx = qx; R->qy = qy; R->rev = rev;
   }
 }
@@ -596,17 +600,18 @@ __device__ __forceinline__ void image_point(const BatchDev &B, const RayQueue &Q
 // the power-heuristic weight against the lobe pdf. The occlusion query is a
 // traversal of the whole BVH limited to the segment (stack St). The light
 // index and visibility enter the signature.
-__device__ float next_event(const SceneDev &S, const MaterialDev &m, uint32_t comp, F3 x, F3 d_in, F3 ng,
-                            int32_t gid, U4 w, const Stack &St, unsigned long long &sig) {
+__device__ float next_event(const SceneDev &S, const MaterialDev *M, const MaterialDev &m, uint32_t comp, F3 x,
+                            F3 d_in, F3 ng, int32_t gid, U4 w, const Stack &St, unsigned long long &sig) {
+  const auto cdf = glb(S.light_cdf);
   const double u0 = ud(w.x) * S.light_area;
   uint32_t lo = 0, hi = S.n_lights;  // first light whose running area exceeds u0
   while (lo < hi) {
     const uint32_t mid = (lo + hi) >> 1;
-    if (S.light_cdf[mid] > u0) hi = mid; else lo = mid + 1;
+    if (cdf[mid] > u0) hi = mid; else lo = mid + 1;
   }
   const uint32_t li = min(lo, S.n_lights - 1u);
-  const float4 *Lp = S.lights + 4 * li;
-  const float4 v0 = Lp[0], v1 = Lp[1], v2 = Lp[2], nn = Lp[3];
+  const GF4 Lp = as_global(S.lights + 4 * li);
+  const float4 v0 = ld4(Lp), v1 = ld4(Lp + 1), v2 = ld4(Lp + 2), nn = ld4(Lp + 3);
   const float su = sqrtf(uf(w.y)), u2 = uf(w.z);
   const F3 y = (1.0f - su) * f3(v0.x, v0.y, v0.z) + (su * (1.0f - u2)) * f3(v1.x, v1.y, v1.z) +
                (su * u2) * f3(v2.x, v2.y, v2.z);
@@ -628,7 +633,7 @@ __device__ float next_event(const SceneDev &S, const MaterialDev &m, uint32_t co
     if (vis) {
       const float pl = dist * dist / (cos_y * (float)S.light_area);
       const float wl = pl * pl / (pl * pl + e.pdf * e.pdf);
-      const MaterialDev &lm = S.mats[__float_as_uint(nn.w)];
+      const MaterialDev &lm = M[__float_as_uint(nn.w)];
       const float le = comp == 0 ? lm.emit[0] : (comp == 1 ? lm.emit[1] : lm.emit[2]);
       c = le * e.fcos * wl / pl;
     }
@@ -640,13 +645,13 @@ __device__ float next_event(const SceneDev &S, const MaterialDev &m, uint32_t co
 template <bool EXT>
 __device__ __forceinline__ void tail_interaction(const BatchDev &B, const RayQueue &Q, StageLds &G,
                                                  const UnitDev &U, const JobDev &J, const SceneDev &S,
-                                                 RayState &st, F3 x, F3 d_in,
+                                                 const MaterialDev *M, RayState &st, F3 x, F3 d_in,
                                                  const HitRec &H, uint32_t b, uint32_t bP, uint32_t comp,
                                                  uint32_t stream, float beta, float L,
                                                  unsigned long long sig, float t_seg, const Stack *St,
                                                  Emit &e) {
   const int32_t gid = H.gid;
-  const MaterialDev &m = S.mats[H.mat];
+  const MaterialDev &m = M[H.mat];
   F3 ng = hit_normal32(S, H, x);
   bool holo = U.kind == UNIT_HOLO;
   const bool nee = EXT && J.nee && S.n_lights > 0;
@@ -665,14 +670,14 @@ __device__ __forceinline__ void tail_interaction(const BatchDev &B, const RayQue
     return;
   }
   if (b >= J.max_bounces) { finish(B, U, J, st, K_MAXB_TAIL, b, L, sig, holo); return; }
-  U4 w = philox(Q.ka[st.i], Q.kb[st.i], b << 8, stream, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
+  U4 w = philox(st.ka, st.kb, b << 8, stream, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
   Lobe lb = sample_lobe<EXT>(m, comp, d_in, ng, uf(w.x), uf(w.y), uf(w.z));
   sig_add(sig, lb.ev);
   const bool cache_here = holo && J.use_cache && !lb.delta && (b - bP + 1) >= J.cache_depth;
   const bool nee_here = nee && !lb.delta && !cache_here;
   if (EXT && nee_here) {
-    U4 wn = philox(Q.ka[st.i], Q.kb[st.i], (b << 8) | 1u, stream, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
-    L += beta * next_event(S, m, comp, x, d_in, ng, gid, wn, *St, sig);
+    U4 wn = philox(st.ka, st.kb, (b << 8) | 1u, stream, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
+    L += beta * next_event(S, M, m, comp, x, d_in, ng, gid, wn, *St, sig);
   }
   if (lb.w == 0.f) { finish(B, U, J, st, K_ABSORBED, b, L, sig, holo); return; }
   st.pdf = (EXT && nee_here) ? eval_lobe<EXT>(m, comp, d_in, ng, lb.d).pdf : 0.f;
@@ -690,12 +695,12 @@ __device__ __forceinline__ void tail_interaction(const BatchDev &B, const RayQue
     if (J.debug & 1u) {
       uint32_t p_local, s_local;
       slot_decode(U, st.slot, p_local, s_local);
-      hpt_path_record *R = J.rec + rec_index(J, U, p_local, s_local);
+      auto R = glb(J.rec) + rec_index(J, U, p_local, s_local);
       R->cache_cell = (int32_t)cell;
       R->cache_bin = (int32_t)bin;
     }
     size_t ce = (size_t)comp * res * res * res * nb + (size_t)cell * nb + bin;
-    L += beta * __half2float(__ushort_as_half(S.cache[ce]));
+    L += beta * __half2float(__ushort_as_half(glb(S.cache)[ce]));
     finish(B, U, J, st, K_CACHE, b, L, sig, true);
     return;
   }
@@ -707,25 +712,21 @@ __device__ __forceinline__ void tail_interaction(const BatchDev &B, const RayQue
 }
 
 // Shade entry i of queue q, whose state is st; st is updated in place for a
-// path that continues (e.on). Jl: the batch's one job in LDS (its scene and
-// materials too), or null when the batch mixes jobs.
+// path that continues (e.on). U, J, S, M: its unit, job, scene and the
+// scene's materials; t, hp: the hit the traversal reported, H its record
+// (read when hp >= 0).
 template <bool EXT>
 __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, RayState &st, StageLds &G,
-                                          const JobDev *Jl, const Stack *St, Emit &e) {
-  const UnitDev &U = B.units[st.unit];
-  const JobDev &J = Jl ? *Jl : *U.job;
-  const SceneDev &S = *J.scene;
+                                          const UnitDev &U, const JobDev &J, const SceneDev &S,
+                                          const MaterialDev *M, float t, int32_t hp, const HitRec &H,
+                                          const Stack *St, Emit &e) {
   const RayQueue &Q = B.Q[q];
   uint32_t meta = st.meta;
   uint32_t stage = meta & 1u, b = (meta >> 1) & 63u, bP = (meta >> 7) & 63u;
-  float t = Q.t[i];
-  int32_t hp = Q.prim[i];
   unsigned long long sig = st.sig;
   bool holo = U.kind == UNIT_HOLO;
   uint32_t comp = holo ? J.comp[U.ch] : U.ch;
   uint32_t stream = (comp << 16) | (holo ? 0u : 2u);
-  HitRec H;
-  if (hp >= 0) H = S.hits[hp];
   const int32_t gid = hp >= 0 ? H.gid : -1;
   if (stage == STAGE_PREFIX) {
     if (gid < 0) {
@@ -741,7 +742,7 @@ __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, 
     double ell = st.ell;
     float ncur = st.wt;
     bool tri = gid >= (int32_t)S.n_sph;
-    const MaterialDev &m = S.mats[H.mat];
+    const MaterialDev &m = M[H.mat];
     bool delta = m.type == HPT_MIRROR || m.type == HPT_DIELECTRIC;
     double t64;
     const double4 pl = make_double4(H.g[0], H.g[1], H.g[2], H.g[3]);  // plane, or centre and radius
@@ -755,7 +756,7 @@ __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, 
     D3 x = o + t64 * d;
     if (J.phase_mode == HPT_PHASE_FP32) x = to_d(to_f(o) + t * to_f(d));
     if (delta) {
-      U4 w = philox(Q.ka[i], Q.kb[i], b << 8, stream, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
+      U4 w = philox(st.ka, st.kb, b << 8, stream, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
       D3 ng;
       if (tri) ng = D3{pl.x, pl.y, pl.z};
       else ng = (1.0 / pl.w) * (x - D3{pl.x, pl.y, pl.z});
@@ -794,8 +795,8 @@ __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, 
     // first non-delta hit: the real image point P
     sig_add(sig, EV_IMAGE_POINT);
     image_point(B, Q, U, J, st, ell, b);
-    tail_interaction<EXT>(B, Q, G, U, J, S, st, to_f(x), to_f(d), H, b, b, comp, stream, 1.0f, 0.0f, sig, t, St,
-                          e);
+    tail_interaction<EXT>(B, Q, G, U, J, S, M, st, to_f(x), to_f(d), H, b, b, comp, stream, 1.0f, 0.0f, sig, t,
+                          St, e);
     return;
   }
   // incoherent tail (or cache path)
@@ -811,23 +812,31 @@ __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, 
   sig_add(sig, (uint32_t)gid + 1u);
   F3 d_in = f3(r1.x, r1.y, r1.z);
   F3 x = f3(r0.x, r0.y, r0.z) + t * d_in;
-  tail_interaction<EXT>(B, Q, G, U, J, S, st, x, d_in, H, b, bP, comp, stream, beta, L, sig, t, St, e);
+  tail_interaction<EXT>(B, Q, G, U, J, S, M, st, x, d_in, H, b, bP, comp, stream, beta, L, sig, t, St, e);
 }
 
-constexpr uint32_t kLdsMats = 64;  // materials a workgroup keeps in LDS
+constexpr uint32_t kLdsMats = 64;    // materials a workgroup keeps in LDS
+constexpr uint32_t kLdsUnits = 128;  // units a workgroup keeps in LDS
 
 // EXT: batches that use next-event estimation or principled materials (the
 // base kernel leaves both out to keep its registers). Shading then may run
 // occlusion queries: the traversal stack takes kStackLds entries per lane in
 // LDS and the lane's column of the traversal spill, so the grid is capped at
 // the spill's columns and walks the queue with a plain grid stride.
-template <bool FIRST, bool EXT>
-__global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
+// UNI: a batch of one job whose scene has at most kLdsMats materials and
+// which has at most kLdsUnits units. Its job, scene, material and unit
+// descriptors are copied to LDS once per workgroup and read from there with
+// LDS instructions; otherwise they are read from global memory. (Reached
+// through a pointer that may address either, they would be read with flat
+// instructions, each of which waits for every load in flight.)
+template <bool FIRST, bool EXT, bool UNI>
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EXT ? 2 : 3))) k_shade(BatchDev B, int q) {
   __shared__ StageLds G;
   __shared__ int32_t nee_stack[EXT ? kStackLds * kBlock : 1];
-  __shared__ JobDev lds_job;
-  __shared__ SceneDev lds_scene;
-  __shared__ MaterialDev lds_mats[kLdsMats];
+  __shared__ JobDev lds_job[1];
+  __shared__ SceneDev lds_scene[1];
+  __shared__ MaterialDev lds_mats[UNI ? kLdsMats : 1];
+  __shared__ UnitDev lds_units[UNI ? kLdsUnits : 1];
   __shared__ uint32_t wave_cnt[kBlock / 64], wave_base[kBlock / 64 + 1];
   uint32_t n = B.counters[q];
   int qo = q ^ 1;
@@ -844,28 +853,19 @@ __global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
   if (blk * blockDim.x >= n) return;  // no entries for this workgroup
   const Stack St{(LdsI32)(nee_stack + (EXT ? threadIdx.x : 0u)), kBlock,
                  (GlbI32)(B.stack_spill + blockIdx.x * blockDim.x + threadIdx.x), B.spill_threads};
-  // A batch of one job: its job, scene and material descriptors are copied
-  // to LDS once per workgroup, so shading reads them without the dependent
-  // global loads unit -> job -> scene -> material.
-  const JobDev *Jl = nullptr;
-  if (B.job_uniform && B.scene_uniform) {
+  if (UNI) {
     const uint32_t t = threadIdx.x;
     const uint32_t *jsrc = (const uint32_t *)B.job_uniform, *ssrc = (const uint32_t *)B.scene_uniform;
-    for (uint32_t k = t; k < sizeof(JobDev) / 4; k += blockDim.x) ((uint32_t *)&lds_job)[k] = jsrc[k];
-    for (uint32_t k = t; k < sizeof(SceneDev) / 4; k += blockDim.x) ((uint32_t *)&lds_scene)[k] = ssrc[k];
+    for (uint32_t k = t; k < sizeof(JobDev) / 4; k += blockDim.x) ((uint32_t *)lds_job)[k] = jsrc[k];
+    for (uint32_t k = t; k < sizeof(SceneDev) / 4; k += blockDim.x) ((uint32_t *)lds_scene)[k] = ssrc[k];
     const uint32_t nm = B.scene_uniform->n_mat;
-    if (nm <= kLdsMats) {
-      const uint32_t *msrc = (const uint32_t *)B.scene_uniform->mats;
-      for (uint32_t k = t; k < nm * (uint32_t)(sizeof(MaterialDev) / 4); k += blockDim.x)
-        ((uint32_t *)lds_mats)[k] = msrc[k];
-    }
+    const uint32_t *msrc = (const uint32_t *)B.scene_uniform->mats;
+    for (uint32_t k = t; k < nm * (uint32_t)(sizeof(MaterialDev) / 4); k += blockDim.x)
+      ((uint32_t *)lds_mats)[k] = msrc[k];
+    const uint32_t *usrc = (const uint32_t *)B.units;
+    for (uint32_t k = t; k < B.n_units * (uint32_t)(sizeof(UnitDev) / 4); k += blockDim.x)
+      ((uint32_t *)lds_units)[k] = usrc[k];
     __syncthreads();
-    if (t == 0) {
-      lds_job.scene = &lds_scene;
-      if (nm <= kLdsMats) lds_scene.mats = lds_mats;
-    }
-    __syncthreads();
-    Jl = &lds_job;
   }
   for (uint32_t base = blk * blockDim.x; base < n; base += stride) {
     const uint32_t i = base + threadIdx.x;
@@ -873,10 +873,24 @@ __global__ void __launch_bounds__(kBlock) k_shade(BatchDev B, int q) {
     Emit e;
     e.on = false;
     if (live) {
+      // the hit record is requested first: it is the longest chain
+      // (entry -> primitive -> record); the rest of the state is loaded
+      // while it is in flight
+      const RayQueue &Qc = B.Q[q];
+      const int32_t hp = Qc.prim[i];
+      const uint32_t unit = Qc.unit[i];
+      const float t = Qc.t[i];
+      const UnitDev &U = UNI ? lds_units[unit] : B.units[unit];
+      const JobDev &J = UNI ? lds_job[0] : *U.job;
+      const SceneDev &S = UNI ? lds_scene[0] : *J.scene;
+      const MaterialDev *M = UNI ? lds_mats : S.mats;
+      HitRec H;
+      if (hp >= 0) H = glb(S.hits)[hp];
       RayState st;
-      if (FIRST) load_first(B, B.Q[q], i, st, Jl);
-      else load_state<EXT>(B.Q[q], i, st);
-      shade_one<EXT>(B, q, i, st, G, Jl, &St, e);
+      st.unit = unit;
+      if (FIRST) load_first(Qc, i, st, U, J);
+      else load_state<EXT>(Qc, i, st);
+      shade_one<EXT>(B, q, i, st, G, U, J, S, M, t, hp, H, &St, e);
     }
     // compaction: wave counts from ballots, one atomic per workgroup (all
     // workgroups add to the same counter, so fewer atomics is what matters)
@@ -922,7 +936,7 @@ __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
   crop_xy(J, U.p_lo + p_local, cx, cy);
   using R = typename std::conditional<F64, double, float>::type;
   const uint32_t gw = J.grf_w, gh = J.grf_h;
-  const float2 *G2 = J.grf + t;
+  const auto G2 = glb(J.grf) + t;
   const size_t plane = (size_t)J.crop_h * J.crop_w;
   R ar = 0, ai = 0;
   unsigned long long sigsum = 0;
@@ -993,7 +1007,7 @@ __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
       if (dbg_c) J.contrib[rec_index(J, U, p_local, s) * T + t] = make_float2((float)cr, (float)ci);
     }
   }
-  float2 *F = J.field + ((size_t)U.ch * T + t) * plane + (size_t)cy * J.crop_w + cx;
+  const auto F = glb(J.field) + ((size_t)U.ch * T + t) * plane + (size_t)cy * J.crop_w + cx;
   float2 v = *F;
   v.x += (float)ar; v.y += (float)ai;
   *F = v;
@@ -1131,19 +1145,17 @@ hipError_t launch_trace(const BatchDev &B, int q, bool count, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_shade(const BatchDev &B, int q, bool first, bool ext, hipStream_t st) {
+uint32_t shade_lds_mats() { return kLdsMats; }
+uint32_t shade_lds_units() { return kLdsUnits; }
+
+hipError_t launch_shade(const BatchDev &B, int q, bool first, bool ext, bool uni, hipStream_t st) {
   const uint32_t g = round8(grid_for(B.n_paths));
-  if (ext) {
-    const uint32_t gn = min(g, B.spill_threads / (uint32_t)kBlock);  // one spill column per lane
-    if (first)
-      hipLaunchKernelGGL((k_shade<true, true>), dim3(gn), dim3(kBlock), 0, st, B, q);
-    else
-      hipLaunchKernelGGL((k_shade<false, true>), dim3(gn), dim3(kBlock), 0, st, B, q);
-  } else if (first) {
-    hipLaunchKernelGGL((k_shade<true, false>), dim3(g), dim3(kBlock), 0, st, B, q);
-  } else {
-    hipLaunchKernelGGL((k_shade<false, false>), dim3(g), dim3(kBlock), 0, st, B, q);
-  }
+  const uint32_t gn = ext ? min(g, B.spill_threads / (uint32_t)kBlock) : g;  // one spill column per lane
+  auto k = ext ? (first ? (uni ? k_shade<true, true, true> : k_shade<true, true, false>)
+                        : (uni ? k_shade<false, true, true> : k_shade<false, true, false>))
+               : (first ? (uni ? k_shade<true, false, true> : k_shade<true, false, false>)
+                        : (uni ? k_shade<false, false, true> : k_shade<false, false, false>));
+  hipLaunchKernelGGL(k, dim3(gn), dim3(kBlock), 0, st, B, q);
   return hipGetLastError();
 }
 

@@ -16,8 +16,11 @@ hipError_t launch_trace(const BatchDev &B, int q, bool count, hipStream_t st);
 uint32_t trace_grid(uint32_t n_paths);
 uint32_t trace_block();
 // first: queue from k_raygen; ext: the batch's jobs use next-event estimation
-// or principled materials (extended shading kernel)
-hipError_t launch_shade(const BatchDev &B, int q, bool first, bool ext, hipStream_t st);
+// or principled materials (extended shading kernel); uni: the batch has one
+// job, at most shade_lds_mats() materials and at most shade_lds_units() units
+hipError_t launch_shade(const BatchDev &B, int q, bool first, bool ext, bool uni, hipStream_t st);
+uint32_t shade_lds_mats();
+uint32_t shade_lds_units();
 hipError_t launch_accumulate(const BatchDev &B, bool has_f64, bool has_f32, hipStream_t st);
 hipError_t launch_cache_reduce(const BatchDev &B, hipStream_t st);
 hipError_t launch_grf(double2 *spec, double2 *rows, float2 *table, uint32_t gw, uint32_t gh, uint32_t T,

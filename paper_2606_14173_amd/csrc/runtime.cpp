@@ -506,10 +506,13 @@ hpt_status launch_batch(hpt_ctx *C, int si, int prev) {
   timed_launch(L, HPT_K_RAYGEN, S, e, [&] { return launch_raygen(B, S); });
   if (e == hipSuccess) e = hipEventRecord(L.ev_rg, S);
   if (e == hipSuccess && prev >= 0 && C->slots[prev].acc_pending) e = launch_accumulation(C, prev, L.ev_rg);
+  // shading copies the descriptors of a one-job batch to LDS when they fit
+  const bool uni = B.job_uniform && B.scene_uniform && P[0].job->scene->host.n_mat <= shade_lds_mats() &&
+                   B.n_units <= shade_lds_units();
   for (uint32_t it = 0; it <= max_b; ++it) {
     int q = (int)(it & 1u);
     timed_launch(L, HPT_K_TRACE, S, e, [&] { return launch_trace(B, q, profile >= 2, S); });
-    timed_launch(L, HPT_K_SHADE, S, e, [&] { return launch_shade(B, q, it == 0, L.has_ext, S); });
+    timed_launch(L, HPT_K_SHADE, S, e, [&] { return launch_shade(B, q, it == 0, L.has_ext, uni, S); });
   }
   if (e == hipSuccess) e = hipMemcpyAsync(L.h_cnt, B.counters, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, S);
   if (e == hipSuccess && profile >= 2)
