@@ -147,6 +147,15 @@ __device__ __forceinline__ void store_first(const RayQueue &Q, uint32_t k, const
 // the traversal's coherence: every path keeps its slot.
 constexpr int kRaygenBlock = 1024;
 
+// A batch of one job with at most kLdsUnits units (and, for shading, a scene
+// of at most kLdsMats materials) has its descriptors copied to LDS once per
+// workgroup and read from there with LDS instructions; otherwise they are
+// read from global memory. (Reached through a pointer that may address
+// either, they would be read with flat instructions, each of which waits for
+// every load in flight.)
+constexpr uint32_t kLdsMats = 64;
+constexpr uint32_t kLdsUnits = 128;
+
 // s1-s2: the primary ray of SLM pixel (px, py) with cone direction cosines
 // (al, be): origin at the pixel, direction (al, be, sqrt(1 - al^2 - be^2)),
 // both carried into world space by the inverse of T (Eq. 3). FP32 phase
@@ -187,14 +196,42 @@ __device__ __forceinline__ void primary_ray(const JobDev &J, uint32_t px, uint32
   }
 }
 
-// s1-s2 for path slot i (or a cache path): its state, read-only key words,
-// FP32 ray and direction-sort key.
-__device__ __forceinline__ void gen_path(const BatchDev &B, uint32_t i, RayState &st, uint32_t &ska,
-                                         uint32_t &skb, double &sal, double &sbe, F3 &ro, F3 &rd,
-                                         uint32_t &key) {
-  uint32_t u = find_unit(B.units, B.n_units, i, false);
-  const UnitDev U = B.units[u];
-  const JobDev &J = *U.job;
+// A radiance-cache path: a point uniform in the cell, a direction uniform in
+// the bin's octahedral square.
+__device__ __forceinline__ void gen_cache_path(const UnitDev &U, const JobDev &J, uint32_t p_local,
+                                               uint32_t s_local, RayState &st, uint32_t &ska, uint32_t &skb,
+                                               F3 &ro, F3 &rd, uint32_t &key) {
+  const SceneDev &S = *J.scene;
+  uint32_t comp = U.ch;
+  uint32_t e = U.p_lo + p_local, j = U.s_lo + s_local;
+  uint32_t nb = J.cache_bins * J.cache_bins;
+  uint32_t cell = e / nb, bin = e - cell * nb;
+  uint32_t res = J.cache_res;
+  uint32_t ix = cell % res, iy = (cell / res) % res, iz = cell / (res * res);
+  uint32_t bu = bin % J.cache_bins, bv = bin / J.cache_bins;
+  uint32_t ka = cell, kb = (bin << 16) | j;
+  uint32_t sw = (comp << 16) | 2u;
+  U4 w0 = philox(ka, kb, 0u, sw, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
+  U4 w1 = philox(ka, kb, 1u, sw, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
+  D3 lo = {S.cache_lo_d[0], S.cache_lo_d[1], S.cache_lo_d[2]};
+  D3 ext = {S.cache_hi_d[0] - lo.x, S.cache_hi_d[1] - lo.y, S.cache_hi_d[2] - lo.z};
+  D3 x = {lo.x + (ix + ud(w0.x)) / res * ext.x, lo.y + (iy + ud(w0.y)) / res * ext.y,
+          lo.z + (iz + ud(w0.z)) / res * ext.z};
+  double pu = -1.0 + 2.0 * (bu + ud(w0.w)) / J.cache_bins;
+  double pv = -1.0 + 2.0 * (bv + ud(w1.x)) / J.cache_bins;
+  D3 d = oct_decode64(pu, pv);
+  ska = ka;
+  skb = kb;
+  st.meta = STAGE_TAIL;  // b = 0, bP = 0
+  ro = to_f(x); rd = to_f(d);
+  key = morton8((float)pu, (float)pv);
+}
+
+// s1-s2 for path slot i (or a cache path) of unit u of the batch: its
+// state, read-only key words, FP32 ray and direction-sort key.
+__device__ __forceinline__ void gen_path(const UnitDev &U, const JobDev &J, uint32_t u, uint32_t i,
+                                         RayState &st, uint32_t &ska, uint32_t &skb, double &sal, double &sbe,
+                                         F3 &ro, F3 &rd, uint32_t &key) {
   uint32_t p_local, s_local;
   slot_decode(U, i, p_local, s_local);
   st.i = i;
@@ -239,32 +276,10 @@ __device__ __forceinline__ void gen_path(const BatchDev &B, uint32_t i, RayState
   } else {
     // radiance-cache path: a point uniform in the cell, a direction uniform
     // in the bin's octahedral square
-    const SceneDev &S = *J.scene;
-    uint32_t comp = U.ch;
-    uint32_t e = U.p_lo + p_local, j = U.s_lo + s_local;
-    uint32_t nb = J.cache_bins * J.cache_bins;
-    uint32_t cell = e / nb, bin = e - cell * nb;
-    uint32_t res = J.cache_res;
-    uint32_t ix = cell % res, iy = (cell / res) % res, iz = cell / (res * res);
-    uint32_t bu = bin % J.cache_bins, bv = bin / J.cache_bins;
-    uint32_t ka = cell, kb = (bin << 16) | j;
-    uint32_t sw = (comp << 16) | 2u;
-    U4 w0 = philox(ka, kb, 0u, sw, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
-    U4 w1 = philox(ka, kb, 1u, sw, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
-    D3 lo = {S.cache_lo_d[0], S.cache_lo_d[1], S.cache_lo_d[2]};
-    D3 ext = {S.cache_hi_d[0] - lo.x, S.cache_hi_d[1] - lo.y, S.cache_hi_d[2] - lo.z};
-    D3 x = {lo.x + (ix + ud(w0.x)) / res * ext.x, lo.y + (iy + ud(w0.y)) / res * ext.y,
-            lo.z + (iz + ud(w0.z)) / res * ext.z};
-    double pu = -1.0 + 2.0 * (bu + ud(w0.w)) / J.cache_bins;
-    double pv = -1.0 + 2.0 * (bv + ud(w1.x)) / J.cache_bins;
-    D3 d = oct_decode64(pu, pv);
-    ska = ka;
-    skb = kb;
-    st.meta = STAGE_TAIL;  // b = 0, bP = 0
-    ro = to_f(x); rd = to_f(d);
-    key = morton8((float)pu, (float)pv);
+    gen_cache_path(U, J, p_local, s_local, st, ska, skb, ro, rd, key);
   }
 }
+
 
 // State of entry i of the first queue, as gen_path made it (store_first).
 // The cone direction is read for every entry (a cache path's entry holds
@@ -286,24 +301,57 @@ __device__ __forceinline__ void load_first(const RayQueue &Q, uint32_t i, RaySta
   }
 }
 
+// Direction-sort key of path slot i of unit u: for a hologram path the
+// 8x8 Morton cell of its cone direction cosines over s (from the same
+// uniforms as gen_path, in FP32: the key only orders the queue); for a
+// cache path the one gen_path gives.
+__device__ __forceinline__ uint32_t sort_key(const UnitDev &U, const JobDev &J, uint32_t u, uint32_t i) {
+  uint32_t p_local, s_local;
+  slot_decode(U, i, p_local, s_local);
+  if (U.kind == UNIT_HOLO) {
+    uint32_t cx, cy;
+    crop_xy(J, U.p_lo + p_local, cx, cy);
+    const uint32_t gpix = (J.crop_y0 + cy) * J.width + J.crop_x0 + cx;
+    const U4 w = philox(gpix, U.s_lo + s_local, 0u, J.comp[U.ch] << 16, (uint32_t)J.seed,
+                        (uint32_t)(J.seed >> 32));
+    const float rad = sqrtf(uf(w.x));
+    float sn, cs;
+    sincospif(2.0f * uf(w.y), &sn, &cs);
+    return morton8(rad * cs, rad * sn);
+  }
+  RayState st;
+  uint32_t ska, skb, key;
+  F3 ro, rd;
+  gen_cache_path(U, J, p_local, s_local, st, ska, skb, ro, rd, key);
+  return key;
+}
+
+template <bool UNI>
 __global__ void __launch_bounds__(kRaygenBlock) k_raygen(BatchDev B) {
   __shared__ uint32_t hist[64], base[64];
   __shared__ uint16_t perm[kRaygenBlock];
+  __shared__ JobDev lds_job[1];
+  __shared__ UnitDev lds_units[UNI ? kLdsUnits : 1];
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t g0 = blockIdx.x * blockDim.x;
   if (i == 0) { B.counters[0] = B.n_paths; B.counters[1] = 0; }
   if (threadIdx.x < 64) hist[threadIdx.x] = 0;
+  if (UNI) {
+    const uint32_t t = threadIdx.x;
+    const uint32_t *jsrc = (const uint32_t *)B.job_uniform, *usrc = (const uint32_t *)B.units;
+    for (uint32_t k = t; k < sizeof(JobDev) / 4; k += blockDim.x) ((uint32_t *)lds_job)[k] = jsrc[k];
+    for (uint32_t k = t; k < B.n_units * (uint32_t)(sizeof(UnitDev) / 4); k += blockDim.x)
+      ((uint32_t *)lds_units)[k] = usrc[k];
+  }
   __syncthreads();
+  const UnitDev *Us = UNI ? lds_units : B.units;
   const bool valid = i < B.n_paths;
   uint32_t key = 0;
-  RayState st;
-  uint32_t ska = 0, skb = 0;
-  double sal = 0.0, sbe = 0.0;
-  F3 ro = f3(0.f, 0.f, 0.f), rd = f3(0.f, 0.f, 1.f);
   if (valid) {
     B.s_first[i] = -1;
     B.r_amp[i] = 0.f;
-    gen_path(B, i, st, ska, skb, sal, sbe, ro, rd, key);  // the sort key only
+    const uint32_t u = find_unit(Us, B.n_units, i, false);
+    key = sort_key(Us[u], UNI ? lds_job[0] : *Us[u].job, u, i);
   }
   uint32_t rank = valid ? atomicAdd(&hist[key], 1u) : 0u;
   __syncthreads();
@@ -319,7 +367,13 @@ __global__ void __launch_bounds__(kRaygenBlock) k_raygen(BatchDev B) {
   // the queue entries are written in order
   const uint32_t nv = min((uint32_t)blockDim.x, B.n_paths - g0);
   if (threadIdx.x < nv) {
-    gen_path(B, g0 + perm[threadIdx.x], st, ska, skb, sal, sbe, ro, rd, key);
+    const uint32_t k = g0 + perm[threadIdx.x];
+    const uint32_t u = find_unit(Us, B.n_units, k, false);
+    RayState st;
+    uint32_t ska = 0, skb = 0;
+    double sal = 0.0, sbe = 0.0;
+    F3 ro, rd;
+    gen_path(Us[u], UNI ? lds_job[0] : *Us[u].job, u, k, st, ska, skb, sal, sbe, ro, rd, key);
     store_first(B.Q[0], g0 + threadIdx.x, st, ska, skb, sal, sbe, ro, rd);
   }
 }
@@ -815,20 +869,14 @@ __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, 
   tail_interaction<EXT>(B, Q, G, U, J, S, M, st, x, d_in, H, b, bP, comp, stream, beta, L, sig, t, St, e);
 }
 
-constexpr uint32_t kLdsMats = 64;    // materials a workgroup keeps in LDS
-constexpr uint32_t kLdsUnits = 128;  // units a workgroup keeps in LDS
-
 // EXT: batches that use next-event estimation or principled materials (the
 // base kernel leaves both out to keep its registers). Shading then may run
 // occlusion queries: the traversal stack takes kStackLds entries per lane in
 // LDS and the lane's column of the traversal spill, so the grid is capped at
 // the spill's columns and walks the queue with a plain grid stride.
 // UNI: a batch of one job whose scene has at most kLdsMats materials and
-// which has at most kLdsUnits units. Its job, scene, material and unit
-// descriptors are copied to LDS once per workgroup and read from there with
-// LDS instructions; otherwise they are read from global memory. (Reached
-// through a pointer that may address either, they would be read with flat
-// instructions, each of which waits for every load in flight.)
+// which has at most kLdsUnits units; its job, scene, material and unit
+// descriptors are read from LDS.
 template <bool FIRST, bool EXT, bool UNI>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EXT ? 2 : 3))) k_shade(BatchDev B, int q) {
   __shared__ StageLds G;
@@ -1120,9 +1168,12 @@ __global__ void k_grf_cols(const double2 *rows, float2 *table, uint32_t gw, uint
 static inline uint32_t grid_for(uint64_t n) { return (uint32_t)((n + kBlock - 1) / kBlock); }
 static inline uint32_t round8(uint32_t g) { return (g + 7u) & ~7u; }
 
-hipError_t launch_raygen(const BatchDev &B, hipStream_t st) {
+hipError_t launch_raygen(const BatchDev &B, bool uni, hipStream_t st) {
   uint32_t g = (uint32_t)(((uint64_t)B.n_paths + kRaygenBlock - 1) / kRaygenBlock);
-  hipLaunchKernelGGL(k_raygen, dim3(g), dim3(kRaygenBlock), 0, st, B);
+  if (uni)
+    hipLaunchKernelGGL(k_raygen<true>, dim3(g), dim3(kRaygenBlock), 0, st, B);
+  else
+    hipLaunchKernelGGL(k_raygen<false>, dim3(g), dim3(kRaygenBlock), 0, st, B);
   return hipGetLastError();
 }
 

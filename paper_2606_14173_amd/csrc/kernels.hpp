@@ -6,7 +6,8 @@
 
 namespace hpt {
 
-hipError_t launch_raygen(const BatchDev &B, hipStream_t st);
+// uni: the batch has one job and at most shade_lds_units() units
+hipError_t launch_raygen(const BatchDev &B, bool uni, hipStream_t st);
 // One interaction for every ray in queue q: closest hit (trace), then
 // shading that compacts continuing rays into queue q^1 (shade).
 // Fails (hipErrorInvalidValue) if the batch's stack spill is too small.

@@ -503,7 +503,8 @@ hpt_status launch_batch(hpt_ctx *C, int si, int prev) {
   if (e == hipSuccess) e = hipMemsetAsync(B.claims, 0, 2 * kClaimClasses * kClaimStride * sizeof(uint32_t), S);
   if (e == hipSuccess && profile >= 2) e = hipMemsetAsync(B.work, 0, 2 * sizeof(unsigned long long), S);
   if (e == hipSuccess) e = hipEventRecord(L.ev0, S);
-  timed_launch(L, HPT_K_RAYGEN, S, e, [&] { return launch_raygen(B, S); });
+  timed_launch(L, HPT_K_RAYGEN, S, e,
+               [&] { return launch_raygen(B, B.job_uniform && B.n_units <= shade_lds_units(), S); });
   if (e == hipSuccess) e = hipEventRecord(L.ev_rg, S);
   if (e == hipSuccess && prev >= 0 && C->slots[prev].acc_pending) e = launch_accumulation(C, prev, L.ev_rg);
   // shading copies the descriptors of a one-job batch to LDS when they fit
