@@ -155,6 +155,9 @@ constexpr int kRaygenBlock = 1024;
 // every load in flight.)
 constexpr uint32_t kLdsMats = 64;
 constexpr uint32_t kLdsUnits = 128;
+// Workgroups of a shading launch at most (a multiple of 8): each copies the
+// descriptors once and then walks its chunks of the queue.
+constexpr uint32_t kShadeGridMax = 32768;
 
 // s1-s2: the primary ray of SLM pixel (px, py) with cone direction cosines
 // (al, be): origin at the pixel, direction (al, be, sqrt(1 - al^2 - be^2)),
@@ -890,15 +893,17 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EXT
   int qo = q ^ 1;
   if (blockIdx.x == 0 && threadIdx.x < kClaimClasses)  // traversal claims of queue q
     B.claims[((uint32_t)q * kClaimClasses + threadIdx.x) * kClaimStride] = 0;
-  // Neighbouring queue entries touch the same slot windows: the blocks that
-  // have entries (the first ceil(n / blockDim) of the grid, which the
-  // hardware deals to the 8 XCDs in turn) are remapped so that each XCD
-  // takes one contiguous eighth of the queue.
+  // The queue is cut into chunks of blockDim entries. Neighbouring entries
+  // touch the same slot windows, so each XCD (the hardware deals workgroups
+  // to the 8 XCDs in turn; the grid is a multiple of 8) takes one contiguous
+  // eighth of the chunks, which its workgroups walk with a stride of their
+  // number; the extended kernel walks all chunks with a plain grid stride.
   const uint32_t nb8 = ((n + blockDim.x - 1) / blockDim.x + 7u) & ~7u;
-  const uint32_t b = blockIdx.x;
-  const uint32_t blk = EXT ? b : (b < nb8 ? (b % 8u) * (nb8 / 8u) + b / 8u : b);
-  const uint32_t stride = EXT ? gridDim.x * blockDim.x : max(gridDim.x, nb8) * blockDim.x;
-  if (blk * blockDim.x >= n) return;  // no entries for this workgroup
+  const uint32_t b = blockIdx.x, per = nb8 / 8u;
+  const uint32_t c0 = EXT ? b : (b % 8u) * per + b / 8u;
+  const uint32_t cstep = EXT ? gridDim.x : gridDim.x / 8u;
+  const uint32_t cend = EXT ? nb8 : (b % 8u + 1u) * per;
+  if (c0 >= cend || c0 * blockDim.x >= n) return;  // no entries for this workgroup
   const Stack St{(LdsI32)(nee_stack + (EXT ? threadIdx.x : 0u)), kBlock,
                  (GlbI32)(B.stack_spill + blockIdx.x * blockDim.x + threadIdx.x), B.spill_threads};
   if (UNI) {
@@ -915,8 +920,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EXT
       ((uint32_t *)lds_units)[k] = usrc[k];
     __syncthreads();
   }
-  for (uint32_t base = blk * blockDim.x; base < n; base += stride) {
-    const uint32_t i = base + threadIdx.x;
+  for (uint32_t c = c0; c < cend && c * blockDim.x < n; c += cstep) {
+    const uint32_t i = c * blockDim.x + threadIdx.x;
     const bool live = i < n;
     Emit e;
     e.on = false;
@@ -1200,7 +1205,7 @@ uint32_t shade_lds_mats() { return kLdsMats; }
 uint32_t shade_lds_units() { return kLdsUnits; }
 
 hipError_t launch_shade(const BatchDev &B, int q, bool first, bool ext, bool uni, hipStream_t st) {
-  const uint32_t g = round8(grid_for(B.n_paths));
+  const uint32_t g = min(round8(grid_for(B.n_paths)), kShadeGridMax);
   const uint32_t gn = ext ? min(g, B.spill_threads / (uint32_t)kBlock) : g;  // one spill column per lane
   auto k = ext ? (first ? (uni ? k_shade<true, true, true> : k_shade<true, true, false>)
                         : (uni ? k_shade<false, true, true> : k_shade<false, true, false>))
