@@ -19,7 +19,7 @@ constexpr int kStackSpill = kStackMax - kStackLds;  // further entries per lane 
 #endif
 constexpr int kTraceChunk = HPT_TRACE_CHUNK;  // queue entries a traversal wave claims at a time
 constexpr uint32_t kTraceGridMax = 2048;      // traversal workgroups per launch (8 per CU)
-constexpr int kTraceStragglers = 16;          // lanes a wave's descent stops waiting for
+constexpr int kTraceStragglers = 24;          // lanes a wave's descent stops waiting for
 #ifndef HPT_CLAIM_CLASSES
 #define HPT_CLAIM_CLASSES 8
 #endif
