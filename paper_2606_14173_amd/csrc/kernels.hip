@@ -86,12 +86,17 @@ __device__ __forceinline__ size_t rec_index(const JobDev &J, const UnitDev &U, u
          (U.s_lo + s_local - J.spp_lo);
 }
 
-// Morton index of a point of [-1,1]^2 on an 8x8 grid (ray-sorting key).
-__device__ __forceinline__ uint32_t morton8(float u, float v) {
-  int a = min(max((int)floorf((u + 1.f) * 4.f), 0), 7);
-  int b = min(max((int)floorf((v + 1.f) * 4.f), 0), 7);
+// Morton index of a point of [-1,1]^2 on a grid of 2^kSortBits cells a side
+// (ray-sorting key).
+constexpr int kSortBits = 5;  // 3 and 4 order the first bounce less coherently
+constexpr uint32_t kSortBins = 1u << (2 * kSortBits);
+__device__ __forceinline__ uint32_t morton_key(float u, float v) {
+  constexpr int n = 1 << kSortBits;
+  const int a = min(max((int)floorf((u + 1.f) * (0.5f * n)), 0), n - 1);
+  const int b = min(max((int)floorf((v + 1.f) * (0.5f * n)), 0), n - 1);
   uint32_t k = 0;
-  for (int i = 0; i < 3; ++i) k |= (((uint32_t)a >> i) & 1u) << (2 * i) | (((uint32_t)b >> i) & 1u) << (2 * i + 1);
+  for (int i = 0; i < kSortBits; ++i)
+    k |= (((uint32_t)a >> i) & 1u) << (2 * i) | (((uint32_t)b >> i) & 1u) << (2 * i + 1);
   return k;
 }
 
@@ -141,7 +146,7 @@ __device__ __forceinline__ void store_first(const RayQueue &Q, uint32_t k, const
 // ------------------------------------------------------------------ raygen
 // One thread per slot. A block of kRaygenBlock consecutive slots (a few
 // neighbouring pixels x their samples; slots are pixel-major) counting-sorts its rays by
-// direction (8x8 Morton bins over the cone, or over the octahedral square
+// direction (32x32 Morton bins over the cone, or over the octahedral square
 // for cache paths) before writing the first queue, so that each wave traces
 // rays of similar origin and direction. The queue order changes nothing but
 // the traversal's coherence: every path keeps its slot.
@@ -227,7 +232,7 @@ __device__ __forceinline__ void gen_cache_path(const UnitDev &U, const JobDev &J
   skb = kb;
   st.meta = STAGE_TAIL;  // b = 0, bP = 0
   ro = to_f(x); rd = to_f(d);
-  key = morton8((float)pu, (float)pv);
+  key = morton_key((float)pu, (float)pv);
 }
 
 // s1-s2 for path slot i (or a cache path) of unit u of the batch: its
@@ -275,7 +280,7 @@ __device__ __forceinline__ void gen_path(const UnitDev &U, const JobDev &J, uint
     st.ell = 0.0;
     st.meta = STAGE_PREFIX;
     ro = to_f(O); rd = to_f(d);
-    key = morton8((float)(al / J.s_cone[U.ch]), (float)(be / J.s_cone[U.ch]));
+    key = morton_key((float)(al / J.s_cone[U.ch]), (float)(be / J.s_cone[U.ch]));
   } else {
     // radiance-cache path: a point uniform in the cell, a direction uniform
     // in the bin's octahedral square
@@ -305,7 +310,7 @@ __device__ __forceinline__ void load_first(const RayQueue &Q, uint32_t i, RaySta
 }
 
 // Direction-sort key of path slot i of unit u: for a hologram path the
-// 8x8 Morton cell of its cone direction cosines over s (from the same
+// 32x32 Morton cell of its cone direction cosines over s (from the same
 // uniforms as gen_path, in FP32: the key only orders the queue); for a
 // cache path the one gen_path gives.
 __device__ __forceinline__ uint32_t sort_key(const UnitDev &U, const JobDev &J, uint32_t u, uint32_t i) {
@@ -320,7 +325,7 @@ __device__ __forceinline__ uint32_t sort_key(const UnitDev &U, const JobDev &J, 
     const float rad = sqrtf(uf(w.x));
     float sn, cs;
     sincospif(2.0f * uf(w.y), &sn, &cs);
-    return morton8(rad * cs, rad * sn);
+    return morton_key(rad * cs, rad * sn);
   }
   RayState st;
   uint32_t ska, skb, key;
@@ -331,14 +336,15 @@ __device__ __forceinline__ uint32_t sort_key(const UnitDev &U, const JobDev &J, 
 
 template <bool UNI>
 __global__ void __launch_bounds__(kRaygenBlock) k_raygen(BatchDev B) {
-  __shared__ uint32_t hist[64], base[64];
+  static_assert(kSortBins <= kRaygenBlock, "one thread per sort bin");
+  __shared__ uint32_t hist[kSortBins], wsum[kRaygenBlock / 64];
   __shared__ uint16_t perm[kRaygenBlock];
   __shared__ JobDev lds_job[1];
   __shared__ UnitDev lds_units[UNI ? kLdsUnits : 1];
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t g0 = blockIdx.x * blockDim.x;
   if (i == 0) { B.counters[0] = B.n_paths; B.counters[1] = 0; }
-  if (threadIdx.x < 64) hist[threadIdx.x] = 0;
+  if (threadIdx.x < kSortBins) hist[threadIdx.x] = 0;
   if (UNI) {
     const uint32_t t = threadIdx.x;
     const uint32_t *jsrc = (const uint32_t *)B.job_uniform, *usrc = (const uint32_t *)B.units;
@@ -358,12 +364,23 @@ __global__ void __launch_bounds__(kRaygenBlock) k_raygen(BatchDev B) {
   }
   uint32_t rank = valid ? atomicAdd(&hist[key], 1u) : 0u;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t acc = 0;
-    for (int k = 0; k < 64; ++k) { base[k] = acc; acc += hist[k]; }
+  // exclusive prefix sum of the bin counts (thread k owns bin k): within
+  // each wave by shuffles, then over the waves' totals
+  const uint32_t lane = __lane_id(), wv = threadIdx.x / 64u;
+  const uint32_t own = threadIdx.x < kSortBins ? hist[threadIdx.x] : 0u;
+  uint32_t inc = own;
+  for (uint32_t off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(inc, off);
+    if (lane >= off) inc += y;
   }
+  if (lane == 63) wsum[wv] = inc;
   __syncthreads();
-  if (valid) perm[base[key] + rank] = (uint16_t)threadIdx.x;
+  uint32_t before = 0;
+  for (uint32_t k = 0; k < wv; ++k) before += wsum[k];
+  __syncthreads();
+  if (threadIdx.x < kSortBins) hist[threadIdx.x] = before + inc - own;  // the bin's first sorted position
+  __syncthreads();
+  if (valid) perm[hist[key] + rank] = (uint16_t)threadIdx.x;
   __syncthreads();
   // entry g0 + t of the first queue: the path at sorted position t,
   // generated again (its random numbers are a function of the path), so that
