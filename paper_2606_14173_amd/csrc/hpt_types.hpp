@@ -143,16 +143,26 @@ struct RayQueue {
   int32_t *prim;                   // leaf-order primitive index of the hit, -1: none
 };
 
+// What the accumulation reads of a path: one 32-byte record per path slot,
+// written where the path finds its image point and where it ends, so that
+// the scattered writes of a shading pass touch one cache line per path.
+struct alignas(32) PathRes {
+  uint32_t tex;   // random-field texel of the image point: i0 | j0 << 16
+  float fx, fy;   // position of the image point in the texel
+  float amp;      // hologram path: amplitude weight A W / spp; cache path: radiance (0: none)
+  float2 cs;      // unit phasor exp(i k r) (FP32 and split phase)
+  float pad[2];
+};
+static_assert(sizeof(PathRes) == 32, "PathRes is one 32-byte record");
+
 struct BatchDev {
   const UnitDev *units;
   uint32_t n_units, n_paths, n_acc, lds_unused;
   // per path slot
   unsigned long long *s_sig;  // final signature (debug records and signature sums only)
   int32_t *s_first;           // first hit (debug records only)
-  float *r_amp, *r_fx, *r_fy;   // results consumed by the accumulation
-  float2 *r_cs;                 // unit phasor exp(i k r) (FP32 and split phase)
-  double2 *r_cs64;              // the same in FP64 (FP64 phase)
-  uint32_t *r_tex;
+  PathRes *res;                 // results consumed by the accumulation
+  double2 *r_cs64;              // unit phasor exp(i k r) in FP64 (FP64 phase)
   RayQueue Q[2];
   uint32_t *counters;        // [0], [1]: queue lengths; [2]: rays traced
   uint32_t *claims;          // traversal claim counters: queue q, class c at [(8 q + c) * kClaimStride]

@@ -358,7 +358,7 @@ __global__ void __launch_bounds__(kRaygenBlock) k_raygen(BatchDev B) {
   uint32_t key = 0;
   if (valid) {
     B.s_first[i] = -1;
-    B.r_amp[i] = 0.f;
+    B.res[i] = PathRes{};  // whole records: coalesced writes
     const uint32_t u = find_unit(Us, B.n_units, i, false);
     key = sort_key(Us[u], UNI ? lds_job[0] : *Us[u].job, u, i);
   }
@@ -557,13 +557,13 @@ __device__ __forceinline__ void finish(const BatchDev &B, const UnitDev &U, cons
   const uint32_t slot = r.slot;
   sig_add(sig, 0x100u | (uint32_t)kind);
   if (J.debug & 5u) B.s_sig[slot] = sig;  // records and signature sums
-  if (U.kind == UNIT_CACHE) { B.r_amp[slot] = L; return; }
+  if (U.kind == UNIT_CACHE) { B.res[slot].amp = L; return; }
   float A = 0.f, amp = 0.f;
   if (has_image) {
     A = sqrtf(r.bpre * L);
     amp = A * r.wt / (float)J.spp;
   }
-  B.r_amp[slot] = amp;
+  B.res[slot].amp = amp;
   if (J.debug & 1u) write_rec_tail(J, U, B, slot, kind, b, A, amp, sig);
 }
 
@@ -642,9 +642,10 @@ __device__ __forceinline__ void image_point(const BatchDev &B, const RayQueue &Q
   int64_t i0 = (int64_t)fu % (int64_t)J.grf_w, j0 = (int64_t)fv % (int64_t)J.grf_h;
   if (i0 < 0) i0 += J.grf_w;
   if (j0 < 0) j0 += J.grf_h;
-  B.r_tex[slot] = (uint32_t)i0 | ((uint32_t)j0 << 16);
-  B.r_fx[slot] = (float)(u - fu);
-  B.r_fy[slot] = (float)(v - fv);
+  PathRes &res = B.res[slot];
+  res.tex = (uint32_t)i0 | ((uint32_t)j0 << 16);
+  res.fx = (float)(u - fu);
+  res.fy = (float)(v - fv);
   // unit phasor exp(i k r) of the path (the same for all T frames), in the
   // precision the accumulation of this mode sums in
   if (J.phase_mode == HPT_PHASE_FP64) {
@@ -654,7 +655,7 @@ __device__ __forceinline__ void image_point(const BatchDev &B, const RayQueue &Q
   } else {
     float sn, cs;
     sincospif(2.0f * (float)rev, &sn, &cs);
-    B.r_cs[slot] = make_float2(cs, sn);
+    res.cs = make_float2(cs, sn);
   }
   st.wt = W;
   if (J.debug & 1u) {
@@ -1026,17 +1027,18 @@ __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
     for (uint32_t u = 0; u < kAccBatch; ++u) {
       const bool v = k0 + u < n;
       const uint32_t slot = slot0 + k0 + u;
-      amp[u] = v ? B.r_amp[slot] : 0.f;
+      PathRes pr{};
+      if (v) pr = B.res[slot];
+      amp[u] = pr.amp;
       if (F64) {
         const double2 cs = v ? B.r_cs64[slot] : make_double2(0.0, 0.0);
         csr[u] = (R)cs.x; csi[u] = (R)cs.y;
       } else {
-        const float2 cs = v ? B.r_cs[slot] : make_float2(0.f, 0.f);
-        csr[u] = (R)cs.x; csi[u] = (R)cs.y;
+        csr[u] = (R)pr.cs.x; csi[u] = (R)pr.cs.y;
       }
-      tex[u] = v && rp ? B.r_tex[slot] : 0u;
-      fx[u] = v && rp ? B.r_fx[slot] : 0.f;
-      fy[u] = v && rp ? B.r_fy[slot] : 0.f;
+      tex[u] = rp ? pr.tex : 0u;
+      fx[u] = rp ? pr.fx : 0.f;
+      fy[u] = rp ? pr.fy : 0.f;
     }
 #pragma unroll
     for (uint32_t u = 0; u < kAccBatch; ++u) {
@@ -1094,7 +1096,7 @@ __global__ void __launch_bounds__(kBlock) k_cache_reduce(BatchDev B) {
   const JobDev &J = *U.job;
   uint32_t e_local = idx - U.acc_base;
   float sum = 0.f;
-  for (uint32_t s = 0; s < U.s_n; ++s) sum += B.r_amp[U.slot_base + e_local * U.s_n + s];
+  for (uint32_t s = 0; s < U.s_n; ++s) sum += B.res[U.slot_base + e_local * U.s_n + s].amp;
   float mean = sum / (float)J.cache_spb;
   size_t n_entries = (size_t)J.cache_res * J.cache_res * J.cache_res * J.cache_bins * J.cache_bins;
   J.cache_out[(size_t)U.ch * n_entries + U.p_lo + e_local] = __half_as_ushort(__float2half_rn(mean));

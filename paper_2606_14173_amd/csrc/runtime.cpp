@@ -52,7 +52,7 @@ constexpr uint32_t kMaxUnitsPerBatch = 4096;
 // per path, in two sets: final signature, first hit, results; per queue
 // entry (two queues): state (40 B), FP64 prefix ray (72 B), FP32 ray (32 B),
 // hit (8 B)
-constexpr size_t kBytesPerPath = 2 * (8 + 4 + 4 + 8 + 16 + 4 + 4 + 4) + 2 * (44 + 72 + 32 + 8);
+constexpr size_t kBytesPerPath = 2 * (8 + 4 + 32 + 16) + 2 * (44 + 72 + 32 + 8);
 
 struct Scene {
   uint64_t id = 0;
@@ -164,10 +164,8 @@ struct hpt_ctx {
   struct Slot {
     unsigned long long *s_sig = nullptr;
     int32_t *s_first = nullptr;
-    float *r_amp = nullptr, *r_fx = nullptr, *r_fy = nullptr;
-    float2 *r_cs = nullptr;
+    PathRes *res = nullptr;
     double2 *r_cs64 = nullptr;
-    uint32_t *r_tex = nullptr;
     UnitDev *d_units = nullptr, *h_units = nullptr;
     uint32_t *h_cnt = nullptr;            // pinned: the batch's counters after its last shading pass
     unsigned long long *h_work = nullptr; // pinned: node visits, primitive tests
@@ -483,7 +481,7 @@ hpt_status launch_batch(hpt_ctx *C, int si, int prev) {
   BatchDev &B = L.B;
   B = C->batch;
   B.s_sig = L.s_sig; B.s_first = L.s_first;
-  B.r_amp = L.r_amp; B.r_fx = L.r_fx; B.r_fy = L.r_fy; B.r_cs = L.r_cs; B.r_cs64 = L.r_cs64; B.r_tex = L.r_tex;
+  B.res = L.res; B.r_cs64 = L.r_cs64;
   B.scene_uniform = P.empty() ? nullptr : P[0].job->scene->dev;
   B.job_uniform = P.empty() ? nullptr : P[0].job->dev;
   for (auto &p : P) {
@@ -694,8 +692,7 @@ hpt_status alloc_batch(hpt_ctx *C) {
   bool ok = true;
   for (auto &L : C->slots) {
     ok &= A((void **)&L.s_sig, 8ull * N) && A((void **)&L.s_first, 4ull * N);
-    ok &= A((void **)&L.r_amp, 4ull * N) && A((void **)&L.r_cs, 8ull * N) && A((void **)&L.r_cs64, 16ull * N) &&
-          A((void **)&L.r_fx, 4ull * N) && A((void **)&L.r_fy, 4ull * N) && A((void **)&L.r_tex, 4ull * N);
+    ok &= A((void **)&L.res, sizeof(PathRes) * (size_t)N) && A((void **)&L.r_cs64, 16ull * N);
     ok &= A((void **)&L.d_units, kMaxUnitsPerBatch * sizeof(UnitDev));
   }
   for (int q = 0; q < 2 && ok; ++q) {
