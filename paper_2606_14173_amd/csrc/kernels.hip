@@ -144,13 +144,16 @@ __device__ __forceinline__ void store_first(const RayQueue &Q, uint32_t k, const
 }
 
 // ------------------------------------------------------------------ raygen
-// One thread per slot. A block of kRaygenBlock consecutive slots (a few
-// neighbouring pixels x their samples; slots are pixel-major) counting-sorts its rays by
-// direction (32x32 Morton bins over the cone, or over the octahedral square
-// for cache paths) before writing the first queue, so that each wave traces
-// rays of similar origin and direction. The queue order changes nothing but
-// the traversal's coherence: every path keeps its slot.
+// A block of kRaygenBlock threads takes kRaygenWindow consecutive slots
+// (kRaygenSlots per thread: 32 neighbouring pixels x their 256 samples;
+// slots are pixel-major) and counting-sorts their rays by direction (32x32
+// Morton bins over the cone, or over the octahedral square for cache paths)
+// before writing the first queue, so that each wave traces rays of similar
+// origin and direction. The queue order changes nothing but the traversal's
+// coherence: every path keeps its slot.
 constexpr int kRaygenBlock = 1024;
+constexpr uint32_t kRaygenSlots = 8;                              // 2 and 4 sort less coherently
+constexpr uint32_t kRaygenWindow = kRaygenSlots * kRaygenBlock;  // slots a block sorts
 
 // A batch of one job with at most kLdsUnits units (and, for shading, a scene
 // of at most kLdsMats materials) has its descriptors copied to LDS once per
@@ -338,12 +341,12 @@ template <bool UNI>
 __global__ void __launch_bounds__(kRaygenBlock) k_raygen(BatchDev B) {
   static_assert(kSortBins <= kRaygenBlock, "one thread per sort bin");
   __shared__ uint32_t hist[kSortBins], wsum[kRaygenBlock / 64];
-  __shared__ uint16_t perm[kRaygenBlock];
+  __shared__ uint16_t perm[kRaygenWindow];
   __shared__ JobDev lds_job[1];
   __shared__ UnitDev lds_units[UNI ? kLdsUnits : 1];
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t g0 = blockIdx.x * blockDim.x;
-  if (i == 0) { B.counters[0] = B.n_paths; B.counters[1] = 0; }
+  static_assert(kRaygenWindow <= 65536, "sorted positions fit 16 bits");
+  const uint32_t g0 = blockIdx.x * kRaygenWindow;
+  if (blockIdx.x == 0 && threadIdx.x == 0) { B.counters[0] = B.n_paths; B.counters[1] = 0; }
   if (threadIdx.x < kSortBins) hist[threadIdx.x] = 0;
   if (UNI) {
     const uint32_t t = threadIdx.x;
@@ -354,15 +357,21 @@ __global__ void __launch_bounds__(kRaygenBlock) k_raygen(BatchDev B) {
   }
   __syncthreads();
   const UnitDev *Us = UNI ? lds_units : B.units;
-  const bool valid = i < B.n_paths;
-  uint32_t key = 0;
-  if (valid) {
-    B.s_first[i] = -1;
-    B.res[i] = PathRes{};  // whole records: coalesced writes
-    const uint32_t u = find_unit(Us, B.n_units, i, false);
-    key = sort_key(Us[u], UNI ? lds_job[0] : *Us[u].job, u, i);
+  const uint32_t nv = min(kRaygenWindow, B.n_paths - g0);  // slots of this block
+  uint32_t key[kRaygenSlots], rank[kRaygenSlots];
+#pragma unroll
+  for (uint32_t r = 0; r < kRaygenSlots; ++r) {
+    const uint32_t w = r * blockDim.x + threadIdx.x, i = g0 + w;
+    key[r] = 0;
+    rank[r] = 0;
+    if (w < nv) {
+      B.s_first[i] = -1;
+      B.res[i] = PathRes{};  // whole records: coalesced writes
+      const uint32_t u = find_unit(Us, B.n_units, i, false);
+      key[r] = sort_key(Us[u], UNI ? lds_job[0] : *Us[u].job, u, i);
+      rank[r] = atomicAdd(&hist[key[r]], 1u);
+    }
   }
-  uint32_t rank = valid ? atomicAdd(&hist[key], 1u) : 0u;
   __syncthreads();
   // exclusive prefix sum of the bin counts (thread k owns bin k): within
   // each wave by shuffles, then over the waves' totals
@@ -380,21 +389,26 @@ __global__ void __launch_bounds__(kRaygenBlock) k_raygen(BatchDev B) {
   __syncthreads();
   if (threadIdx.x < kSortBins) hist[threadIdx.x] = before + inc - own;  // the bin's first sorted position
   __syncthreads();
-  if (valid) perm[hist[key] + rank] = (uint16_t)threadIdx.x;
+#pragma unroll
+  for (uint32_t r = 0; r < kRaygenSlots; ++r) {
+    const uint32_t w = r * blockDim.x + threadIdx.x;
+    if (w < nv) perm[hist[key[r]] + rank[r]] = (uint16_t)w;
+  }
   __syncthreads();
-  // entry g0 + t of the first queue: the path at sorted position t,
+  // entry g0 + w of the first queue: the path at sorted position w,
   // generated again (its random numbers are a function of the path), so that
   // the queue entries are written in order
-  const uint32_t nv = min((uint32_t)blockDim.x, B.n_paths - g0);
-  if (threadIdx.x < nv) {
-    const uint32_t k = g0 + perm[threadIdx.x];
+  for (uint32_t r = 0; r < kRaygenSlots; ++r) {
+    const uint32_t w = r * blockDim.x + threadIdx.x;
+    if (w >= nv) break;
+    const uint32_t k = g0 + perm[w];
     const uint32_t u = find_unit(Us, B.n_units, k, false);
     RayState st;
-    uint32_t ska = 0, skb = 0;
+    uint32_t ska = 0, skb = 0, kk;
     double sal = 0.0, sbe = 0.0;
     F3 ro, rd;
-    gen_path(Us[u], UNI ? lds_job[0] : *Us[u].job, u, k, st, ska, skb, sal, sbe, ro, rd, key);
-    store_first(B.Q[0], g0 + threadIdx.x, st, ska, skb, sal, sbe, ro, rd);
+    gen_path(Us[u], UNI ? lds_job[0] : *Us[u].job, u, k, st, ska, skb, sal, sbe, ro, rd, kk);
+    store_first(B.Q[0], g0 + w, st, ska, skb, sal, sbe, ro, rd);
   }
 }
 
@@ -1193,7 +1207,7 @@ static inline uint32_t grid_for(uint64_t n) { return (uint32_t)((n + kBlock - 1)
 static inline uint32_t round8(uint32_t g) { return (g + 7u) & ~7u; }
 
 hipError_t launch_raygen(const BatchDev &B, bool uni, hipStream_t st) {
-  uint32_t g = (uint32_t)(((uint64_t)B.n_paths + kRaygenBlock - 1) / kRaygenBlock);
+  uint32_t g = (uint32_t)(((uint64_t)B.n_paths + kRaygenWindow - 1) / kRaygenWindow);
   if (uni)
     hipLaunchKernelGGL(k_raygen<true>, dim3(g), dim3(kRaygenBlock), 0, st, B);
   else
