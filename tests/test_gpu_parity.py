@@ -73,6 +73,31 @@ def test_mid_scene_rgb_crop(ctx):
     assert r["ok"]
 
 
+def test_many_materials_read_from_global_memory(ctx):
+    """A scene with more materials than shading keeps in LDS (64) is shaded
+    from its descriptors in global memory: the mid scene with its floor
+    material split into 70 identical copies gives the same field, bit for
+    bit, as the original (shaded from LDS), and matches the oracle."""
+    sc = scenes.scene_mid(1)
+    job = jobs.job_for_config(1, crop=(236, 240, 40, 36), spp=8)
+    floor = int(sc["tri_mat"][0])   # the heightfield is added first
+    n0, k = len(sc["mat_type"]), 70
+    many = {key: np.array(v, copy=True) for key, v in sc.items()}
+    for key in ("mat_type", "mat_rgb", "mat_rough", "mat_ior", "mat_emit", "mat_pbr"):
+        many[key] = np.concatenate([sc[key], np.repeat(sc[key][floor:floor + 1], k, axis=0)])
+    idx = np.flatnonzero(sc["tri_mat"] == floor)
+    many["tri_mat"][idx] = (n0 + np.arange(idx.size) % k).astype(np.uint32)
+    assert len(many["mat_type"]) > 64
+    sid0, sid1 = ctx.upload_scene(sc), ctx.upload_scene(many)
+    a, b = ctx.trace(sid0, job), ctx.trace(sid1, job)
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    r = compare(*gpu_run(ctx, sid1, job), *oracle_run(many, job))
+    ctx.release_scene(sid0)
+    ctx.release_scene(sid1)
+    _say("many-materials", r)
+    assert r["ok"]
+
+
 @pytest.mark.parametrize("name", ["slab", "mirror", "furnace", "patch", "emitter_glass"])
 def test_closed_form_scenes(ctx, name):
     """The scenes whose oracle results are pinned by closed forms."""
