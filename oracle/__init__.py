@@ -35,12 +35,14 @@ class OracleScene:
                       _c(sc["mat_rough"], np.float32), _c(sc["mat_ior"], np.float32),
                       _c(sc["mat_emit"], np.float32), _c(sc["env"], np.float32),
                       _c(sc.get("mat_pbr", np.tile(np.float32([0.0, 0.5, 0.0, 1.0]), (len(sc["mat_type"]), 1))),
-                         np.float32)]
+                         np.float32),
+                      _c(sc.get("pts", np.zeros((0, 6))), np.float32).reshape(-1, 6)]
         k = self._keep
         d = _lib.OScene(k[0].ctypes.data, len(k[1]), k[1].ctypes.data,
                         k[2].ctypes.data, len(k[3]), k[3].ctypes.data,
                         len(k[4]), k[4].ctypes.data, k[5].ctypes.data, k[6].ctypes.data,
-                        k[7].ctypes.data, k[8].ctypes.data, k[9].ctypes.data, k[10].ctypes.data)
+                        k[7].ctypes.data, k[8].ctypes.data, k[9].ctypes.data, k[10].ctypes.data,
+                        k[11].ctypes.data if len(k[11]) else None, len(k[11]))
         self.h = _lib.lib().oracle_scene_create(C.byref(d))
         self.n_sph = len(k[3])
 
@@ -111,6 +113,7 @@ def make_job(job, grf=None):
     J.random_phase, J.use_cache, J.cache_depth = (job["random_phase"], job["use_cache"],
                                                   job["cache_depth"])
     J.nee = int(job.get("nee", 0))
+    J.weight_mode = int(job.get("weight_mode", 0))
     for i in range(4):
         J.crop[i] = job["crop"][i]
     J.spp_begin, J.spp_end = job["spp_begin"], job["spp_end"]

@@ -14,7 +14,7 @@ class OScene(C.Structure):
                 ("sph", C.c_void_p), ("n_sph", C.c_int32), ("sph_mat", C.c_void_p),
                 ("n_mat", C.c_int32), ("mat_type", C.c_void_p), ("mat_rgb", C.c_void_p),
                 ("mat_rough", C.c_void_p), ("mat_ior", C.c_void_p), ("mat_emit", C.c_void_p),
-                ("env", C.c_void_p), ("mat_pbr", C.c_void_p)]
+                ("env", C.c_void_p), ("mat_pbr", C.c_void_p), ("pts", C.c_void_p), ("n_pts", C.c_int32)]
 
 
 class OJob(C.Structure):
@@ -25,7 +25,8 @@ class OJob(C.Structure):
                 ("random_phase", C.c_int32), ("use_cache", C.c_int32), ("cache_depth", C.c_int32),
                 ("crop", C.c_int32 * 4), ("spp_begin", C.c_int32), ("spp_end", C.c_int32),
                 ("holo_from_world", C.c_double * 12),
-                ("grf_w", C.c_int32), ("grf_h", C.c_int32), ("grf", C.c_void_p), ("nee", C.c_int32)]
+                ("grf_w", C.c_int32), ("grf_h", C.c_int32), ("grf", C.c_void_p), ("nee", C.c_int32),
+                ("weight_mode", C.c_int32)]
 
 
 class ORecord(C.Structure):

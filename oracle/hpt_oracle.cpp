@@ -148,6 +148,8 @@ struct Scene {
   std::vector<Light> lights;     // emitter triangles in id order
   std::vector<double> light_cdf; // running sum of their areas
   double light_area = 0.0;
+  std::vector<V3> pt_pos;        // point emitters: position (world space)
+  std::vector<V3> pt_amp;        // and amplitude per colour component
 };
 
 struct Hit { double t; int gid; };
@@ -778,6 +780,8 @@ struct OScene {
   int32_t n_mat; const uint32_t *mat_type; const float *mat_rgb; const float *mat_rough;
   const float *mat_ior; const float *mat_emit; const float *env;
   const float *mat_pbr;     // [n_mat][4] metallic, specular, clearcoat, clearcoat gloss (nullable)
+  const float *pts;         // [n_pts][6] point emitters: position xyz, amplitude per component (nullable)
+  int32_t n_pts;
 };
 
 struct OJob {
@@ -792,6 +796,7 @@ struct OJob {
   int32_t grf_w, grf_h;
   const double *grf;        // complex128 [grf_h][grf_w][T] interleaved re, im
   int32_t nee;              // next-event estimation with MIS in the tail
+  int32_t weight_mode;      // 0: W = r / p(v) (reading R); 1: W = 1 (Eq. 5 as printed, reading P)
 };
 
 struct ORecord {           // one per (channel, pixel, sample) path
@@ -825,6 +830,11 @@ void *oracle_scene_create(const OScene *d) {
     S->mats.push_back(m);
   }
   for (int c = 0; c < 3; ++c) S->env[c] = d->env[c];
+  for (int i = 0; i < d->n_pts; ++i) {
+    const float *p = d->pts + 6 * i;
+    S->pt_pos.push_back({p[0], p[1], p[2]});
+    S->pt_amp.push_back({p[3], p[4], p[5]});
+  }
   for (int i = 0; i < S->n_tri; ++i) {
     int mi = S->prim_mat[S->n_sph + i];
     if (S->mats[mi].type != EMITTER) continue;
@@ -1044,6 +1054,37 @@ void oracle_grf_lookup(const OJob *J, int32_t t, double qx, double qy, double *o
   out[0] = p.real(); out[1] = p.imag();
 }
 
+// Point emitter (a test primitive outside the paper's scenes; Eq. 2 for a
+// source concentrated at one point with isotropic amplitude a, so the
+// obliquity factor is 1): pixel p of the recording plane receives
+// a exp(i (k r + phi_t(Q))) / r, with Q = T y the emitter in hologram space
+// and r = |Q - x_p|, when Q lies in front of the plane inside the recordable
+// cone (the direction cosines of Q - x_p within the disc of radius
+// lambda/2d, boundary included, as for the sampled directions) and no scene
+// primitive lies on the world-space segment from T^-1 x_p to y. The term is
+// exact (not sampled); a job adds it once, in the sample range that starts
+// at sample 0. acc: the pixel's T frame sums.
+static void add_point_emitters(const Scene &S, const OJob &J, const double *Tinv, V3 xp, int comp,
+                               double k, double s, std::complex<double> *acc) {
+  for (size_t e = 0; e < S.pt_pos.size(); ++e) {
+    double a = comp_of(S.pt_amp[e], comp);
+    if (a == 0.0) continue;
+    V3 y = S.pt_pos[e];
+    V3 Q = apply_affine(J.holo_from_world, y);
+    V3 dq = Q - xp;
+    double r = length(dq);
+    if (!(dq.z > 0.0) || dq.x * dq.x + dq.y * dq.y > s * s * r * r) continue;
+    V3 O = apply_affine(Tinv, xp);
+    V3 seg = y - O;
+    double dist = length(seg);
+    Hit h = closest_hit(S, O, (1.0 / dist) * seg, 1e-7, -1, false);
+    if (h.gid >= 0 && h.t < dist) continue;
+    std::complex<double> base = (a / r) * std::exp(std::complex<double>(0.0, k * r));
+    for (int t = 0; t < J.T; ++t)
+      acc[t] += J.random_phase ? base * grf_phasor(J, t, Q.x, Q.y) : base;
+  }
+}
+
 // Trace every (channel, pixel, sample) path of the crop and accumulate the T
 // frames. field: complex128 [n_ch][T][crop_h][crop_w]; recs (nullable):
 // [n_ch][crop_h][crop_w][spp_end - spp_begin]; recs_t (nullable): per-path
@@ -1133,8 +1174,9 @@ int32_t oracle_trace(void *scene, void *cache, const OJob *J, double *field, ORe
           V3 Q = apply_affine(J->holo_from_world, Pp);
           double r = length(Q - xp);
           // weight of Eq. 2 per unit solid angle divided by the disc density
+          // (reading R); Eq. 5 as printed has no weight (reading P: W = 1)
           double pdf = v.z / (M_PI * s * s);
-          double W = r / pdf;
+          double W = J->weight_mode == 1 ? 1.0 : r / pdf;
           // s5: incoherent amplitude from the image point
           int tk = 0, nh = 0;
           double Lhat = radiance_tail(X, o, dir, gid, b, b, comp, J->seed, pixel, smp,
@@ -1168,6 +1210,7 @@ int32_t oracle_trace(void *scene, void *cache, const OJob *J, double *field, ORe
         R.sig = sig; R.kind = kind;
         if (recs) recs[(((size_t)c * ch + yy) * cw + xx) * ns + si] = R;
       }
+      if (sb == 0) add_point_emitters(*S, *J, Tinv, xp, comp, k, s, acc.data());
       for (int t = 0; t < J->T; ++t) {
         size_t o = (((size_t)c * J->T + t) * ch + yy) * cw + xx;
         field[2 * o] = acc[t].real(); field[2 * o + 1] = acc[t].imag();

@@ -445,3 +445,38 @@ def scene_single_tri(z0, size=0.2 * MM, env=1.0, albedo=1.0):
     m = b.material(LAMBERT, rgb=(albedo,) * 3)
     b.add_tris([[(0, 0, z0), (size, 0, z0), (0, size, z0 + size)]], m)
     return b.finish(env=(env,) * 3)
+
+
+def scene_point_emitters(pts, occluder=None, env=0.0):
+    """Point emitters (rows: x, y, z, amplitude per colour component) and,
+    optionally, one black Lambert sphere (cx, cy, cz, r) between them and the
+    recording plane. Paths that reach the sphere carry no radiance (albedo 0,
+    environment `env`), so with env = 0 the field is the emitters' alone."""
+    b = _Builder()
+    m = b.material(LAMBERT, rgb=(0.0, 0.0, 0.0))
+    if occluder is not None:
+        b.add_sphere(occluder[:3], occluder[3], m)
+    sc = b.finish(env=(env,) * 3)
+    sc["pts"] = np.asarray(pts, dtype=np.float32).reshape(-1, 6)
+    return sc
+
+
+def scene_emitter_box(half, radiances, env=0.25):
+    """Closed box [-half, half]^3 whose six walls are emitters facing inward,
+    wall k (order -x, +x, -y, +y, -z, +z) with radiance radiances[k] (rgb),
+    plus a black two-sided Lambert half-plane z = 0, x in [-half, 0]."""
+    b = _Builder()
+    axes = np.eye(3)
+    k = 0
+    for a in range(3):
+        for sgn in (-1.0, 1.0):
+            m = b.material(EMITTER, emit=radiances[k])
+            u, v = axes[(a + 1) % 3] * 2 * half, axes[(a + 2) % 3] * 2 * half
+            p0 = sgn * half * axes[a] - 0.5 * u - 0.5 * v
+            if np.cross(u, v) @ axes[a] * (-sgn) < 0:   # normal must point into the box
+                u, v = v, u
+            b.add_quad(p0, u, v, m)
+            k += 1
+    m = b.material(LAMBERT, rgb=(0.0, 0.0, 0.0))
+    b.add_quad((-half, -half, 0.0), (0, 2 * half, 0), (half, 0, 0), m)
+    return b.finish(env=(env,) * 3)

@@ -674,3 +674,108 @@ def test_grf_lookup_texel_centres(oracle_lib):
                 assert abs(oracle.grf_lookup(job, grf, t, qx, qy) - want) < 1e-12
                 got = oracle.grf_lookup(job, grf, t, qx + gw * PITCH, qy - gh * PITCH)
                 assert abs(got - want) < 1e-9
+
+
+def test_grf_lookup_bilinear_off_centres(oracle_lib):
+    """Sec. 4.3 hologram-space phase between texel centres: bilinear
+    interpolation reproduces an affine field exactly, so for a table
+    r(i, j) = a + b i + c j the lookup at texel coordinates (i0 + fx,
+    j0 + fy) is the unit phasor of a + b (i0 + fx) + c (j0 + fy). Offsets
+    (1/4, 3/4), (3/4, 1/4) and random ones; a swap of the two weights, a
+    half-texel offset or a wrong wrap fails it."""
+    W, H, gw, gh, T = 10, 8, 24, 20, 2
+    a = np.array([3.0 + 1.0j, -2.0 + 2.5j])
+    b = np.array([0.40 - 0.15j, -0.10 + 0.35j])
+    c = np.array([-0.25 + 0.30j, 0.45 + 0.05j])
+    jj, ii = np.meshgrid(np.arange(gh), np.arange(gw), indexing="ij")
+    grf = np.stack([a[t] + b[t] * ii + c[t] * jj for t in range(T)], axis=-1)
+    job = _job(width=W, height=H, T=T, grf_w=gw, grf_h=gh)
+    rng = np.random.default_rng(7)
+    offs = [(0.25, 0.75), (0.75, 0.25), (0.5, 0.125)] + [tuple(rng.random(2)) for _ in range(12)]
+    n = 0
+    for fx, fy in offs:
+        for i0, j0 in ((0, 0), (3, 5), (gw - 2, gh - 2), (11, 2)):
+            u, v = i0 + fx, j0 + fy
+            qx = (u + 0.5 - W / 2) * PITCH
+            qy = (v + 0.5 - H / 2) * PITCH
+            for t in range(T):
+                z = a[t] + b[t] * u + c[t] * v
+                assert abs(oracle.grf_lookup(job, grf, t, qx, qy) - z / abs(z)) < 1e-12
+                n += 1
+    assert n == len(offs) * 4 * T
+    # across the periodic seam the neighbour of column gw-1 is column 0
+    u, v = gw - 1 + 0.25, 3.5
+    qx, qy = (u + 0.5 - W / 2) * PITCH, (v + 0.5 - H / 2) * PITCH
+    z = 0.75 * 0.5 * (grf[3, gw - 1, 0] + grf[4, gw - 1, 0]) + 0.25 * 0.5 * (grf[3, 0, 0] + grf[4, 0, 0])
+    assert abs(oracle.grf_lookup(job, grf, 0, qx, qy) - z / abs(z)) < 1e-12
+
+
+def _box_classify(o, d, half):
+    """Index of the first surface a ray meets inside the box [-half, half]^3
+    of scene_emitter_box: wall k = 2 axis + (direction > 0), or 6 for the
+    black half-plane z = 0, x < 0. Rays are started inside the box."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        tw = np.where(d != 0, (np.sign(d) * half - o) / d, np.inf)
+    ax = int(np.argmin(tw))
+    t_exit = tw[ax]
+    if d[2] != 0:
+        t0 = -o[2] / d[2]
+        if 0 < t0 < t_exit and o[0] + t0 * d[0] < 0:
+            return 6
+    return 2 * ax + (1 if d[ax] > 0 else 0)
+
+
+def test_cache_entries_by_cell_and_bin(oracle_lib):
+    """Radiance cache ("texture baking", Sec. 4.2) beyond the furnace: inside
+    a box whose six walls emit inward with six different radiances, with a
+    black half-plane z = 0 over x < 0, an entry whose cell and direction bin
+    see one surface from every point of the cell along every direction of
+    the bin equals that surface's radiance (0 for the black plane). The
+    surfaces are found here by ray casting the box geometry, for points of
+    the cell box and directions of the bin's octahedral square (the pinned
+    octahedral map); entries differ by cell (below / above the half-plane,
+    x < 0 / x > 0) and by bin (the wall a direction faces), so a transposed
+    cell order, a swapped bin decode or a misplaced sampling point fails."""
+    half, res, bins = 1e-3, 6, 8
+    rad = [(1.0, 2.0, 0.5), (2.0, 3.0, 1.5), (3.0, 0.25, 2.5), (4.0, 1.25, 3.5),
+           (5.0, 4.5, 0.75), (6.0, 5.5, 1.75)]
+    sc = scenes.scene_emitter_box(half, rad)
+    o = oracle.OracleScene(sc)
+    c = oracle.OracleCache(o, res=res, bins=bins, spb=4, max_bounces=3, seed=11)
+    lo, hi = c.bounds()
+    ext = (hi - lo) / res
+    fr = np.array([0.0005, 0.5, 0.9995])
+    cell_pts = np.stack(np.meshgrid(fr, fr, fr, indexing="ij"), -1).reshape(-1, 3)
+    gu = np.array([0.002, 0.25, 0.5, 0.75, 0.998])
+    want, keys = {}, []
+    for iz in range(1, res - 1):
+        for iy in range(1, res - 1):
+            for ix in range(1, res - 1):
+                cell = (iz * res + iy) * res + ix
+                pts = lo + (np.array([ix, iy, iz]) + cell_pts) * ext
+                for bv in range(bins):
+                    for bu in range(bins):
+                        seen = set()
+                        for su in gu:
+                            for sv in gu:
+                                d = oracle.oct_decode(-1 + 2 * (bu + su) / bins, -1 + 2 * (bv + sv) / bins)
+                                for p in pts:
+                                    seen.add(_box_classify(p, d, half))
+                            if len(seen) > 1:
+                                break
+                        if len(seen) == 1:
+                            want[(cell, bv * bins + bu)] = seen.pop()
+    assert len(want) > 600
+    kinds = np.array(list(want.values()))
+    assert set(kinds.tolist()) == set(range(7))
+    cells = np.array([k[0] for k in want], np.int32)
+    bns = np.array([k[1] for k in want], np.int32)
+    for comp in range(3):
+        expect = np.array([0.0 if k == 6 else rad[k][comp] for k in kinds])
+        got = c.entries(np.full(len(cells), comp, np.int32), cells, bns)
+        assert np.array_equal(got, expect), np.flatnonzero(got != expect)[:10]
+    # the same bin differs between a cell above and below the half-plane at x < 0
+    up = oracle.oct_map(np.array([0.0, 0.0, 1.0]), bins)[1]
+    below = (2 * res + 2) * res + 1
+    above = (3 * res + 2) * res + 1
+    assert want.get((below, up)) == 6 and want.get((above, up)) == 5
