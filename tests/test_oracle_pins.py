@@ -779,3 +779,39 @@ def test_cache_entries_by_cell_and_bin(oracle_lib):
     below = (2 * res + 2) * res + 1
     above = (3 * res + 2) * res + 1
     assert want.get((below, up)) == 6 and want.get((above, up)) == 5
+
+
+def test_cache_lookup_cell_of_image_points(oracle_lib):
+    """A path that ends in the radiance cache at its image point P reads the
+    entry of the cell containing P (Sec. 4.2 texture baking, nearest cell):
+    on a tilted Lambert plane around depth z0 every path's P lies on it, its
+    position follows from the record (Q = P for the identity transform; the
+    depth from r), and its cell index (iz res + iy) res + ix is computed
+    here from the cache grid; points within 1e-9 of a cell face are skipped."""
+    z0, half, res = 2e-3, 48e-6, 8
+    sc = scenes.scene_lambert_plane(z0, (0.5,) * 3, env=1.0, half=half)
+    a = math.radians(25.0)                        # tilt about x through (0, 0, z0): depth varies
+    v = sc["tri"].astype(np.float64)
+    y, z = v[..., 1], v[..., 2] - z0
+    sc["tri"] = np.stack([v[..., 0], y * math.cos(a) - z * math.sin(a), z0 + y * math.sin(a) + z * math.cos(a)],
+                         -1).astype(np.float32)
+    o = oracle.OracleScene(sc)
+    c = oracle.OracleCache(o, res=res, bins=4, spb=1, max_bounces=2, seed=3)
+    lo, hi = c.bounds()
+    job = _job(width=14, height=12, spp=24, max_bounces=3, use_cache=1)
+    _, recs, _ = oracle.trace(o, job, grf=_grf_dummy(job), cache=c, records=True)
+    r = recs.reshape(recs.shape[1], recs.shape[2], -1)
+    X = ((np.arange(14) + 0.5) - 7) * PITCH
+    Y = ((np.arange(12) + 0.5) - 6) * PITCH
+    xp = np.broadcast_to(X[None, :, None], r.shape)
+    yp = np.broadcast_to(Y[:, None, None], r.shape)
+    used = r["cache_cell"] >= 0
+    assert used.sum() > 1000
+    P = np.stack([r["qx"], r["qy"], np.sqrt(np.maximum(r["r"] ** 2 - (r["qx"] - xp) ** 2 - (r["qy"] - yp) ** 2, 0))], -1)
+    f = (P - lo) / (hi - lo) * res
+    idx = np.clip(np.floor(f), 0, res - 1).astype(int)
+    safe = np.all(np.abs(f - np.round(f)) > 1e-9, axis=-1) & used
+    assert safe.sum() > 900
+    cell = (idx[..., 2] * res + idx[..., 1]) * res + idx[..., 0]
+    assert np.array_equal(cell[safe], r["cache_cell"][safe])
+    assert len(np.unique(cell[safe])) >= 9        # the image points spread over several cells
