@@ -98,6 +98,17 @@ typedef struct {
                                 0.25 clearcoat; a lobe is sampled with probability proportional
                                 to (1 - metallic, 1, 0.25 clearcoat) and weighted by the full
                                 f cos over the combined pdf. */
+  const float *pts;          /* host, [n_pts][6] (nullable when n_pts = 0): point emitters, a test
+                                primitive with a closed-form field (Eq. 2 for a source concentrated
+                                at one point y, isotropic, so the obliquity factor is 1): world
+                                position xyz, then the amplitude a >= 0 per colour component.
+                                Pixel p receives a exp(i (k r + phi_m(Q))) / r in every frame m,
+                                Q = T y, r = |Q - x_p|, when Q is in front of the plane inside the
+                                recordable cone (the direction cosines of Q - x_p within the disc
+                                of radius lambda/2d, boundary included) and no primitive lies on
+                                the segment from T^-1 x_p to y. The term is exact, not sampled; a
+                                job adds it once, in its sample range only if that starts at 0. */
+  uint32_t n_pts;            /* 0 .. 4096 */
 } hpt_scene_desc;
 
 typedef struct {
@@ -135,6 +146,14 @@ typedef struct {
 hpt_status hpt_cache_build(hpt_ctx *ctx, uint64_t scene, const hpt_cache_desc *desc);
 /* Copy the cache to host memory: n = 3 * res^3 * bins^2 binary16 values. */
 hpt_status hpt_cache_export(hpt_ctx *ctx, uint64_t scene, uint16_t *host_out, size_t n);
+/* Install a cache built elsewhere (e.g. exported from a scene with the same
+ * geometry): desc gives its res and bins (spb, max_bounces and seed are
+ * recorded only); host: n = 3 * res^3 * bins^2 binary16 values in the layout
+ * above, copied before the call returns. The grid is this scene's bounds
+ * inflated as for hpt_cache_build. EINVAL on a size mismatch or
+ * out-of-range desc, EBUSY while a job uses the scene, EBUDGET, ENOMEM. */
+hpt_status hpt_cache_import(hpt_ctx *ctx, uint64_t scene, const hpt_cache_desc *desc, const uint16_t *host,
+                            size_t n);
 
 /* ---------------------------------------------------------------- jobs */
 enum { HPT_PHASE_FP64 = 0, HPT_PHASE_SPLIT = 1, HPT_PHASE_FP32 = 2 };
@@ -169,7 +188,13 @@ typedef struct {
                                the complementary weight (Eq. 1 by two combined estimators).
                                Random numbers: Philox counter (interaction << 8) | 1.
                                0: BSDF sampling only. */
+  uint32_t weight_mode;     /* HPT_WEIGHT_RS_AREA (0): every path is weighted W = r / p(v),
+                               p(v) = v_z / (pi s^2) the density of the cone directions per unit
+                               solid angle, so A W exp(i k r) is an unbiased sample of Eq. 2's
+                               integrand; HPT_WEIGHT_PAPER_LITERAL (1): W = 1, Eq. 5 as printed
+                               (the same paths and phases, amplitudes without the weight). */
 } hpt_job_desc;
+enum { HPT_WEIGHT_RS_AREA = 0, HPT_WEIGHT_PAPER_LITERAL = 1 };
 
 typedef struct {
   uint64_t paths;            /* (channel, pixel, sample) paths traced */
@@ -188,14 +213,19 @@ typedef struct {
 } hpt_path_record;
 
 /* Queue a job. d_field: device buffer of n_ch*T*crop_h*crop_w complex64
- * (nullable: the library allocates it). Validation (EINVAL): sizes zero,
+ * (nullable: the library allocates it). hip_stream (a hipStream_t on the
+ * context's device, nullable): the job's device work starts only after all
+ * work enqueued on that stream before this call (an event is recorded on it
+ * here), so a caller may submit right after its own kernels that produce or
+ * still use d_field, without synchronising; completion is reported by
+ * hpt_job_wait. Validation (EINVAL): sizes zero,
  * T not in [1,64], n_ch not in [1,3], lambda <= 0, lambda/(2 pitch) >= 1,
  * grf smaller than the SLM, crop outside the SLM, spp range empty,
  * max_bounces not in [1,31], non-finite or singular T, use_cache without a
  * built cache. EBUDGET if the job can never fit the budget; otherwise it
  * waits in the queue until memory frees up. */
 hpt_status hpt_trace_submit(hpt_ctx *ctx, uint64_t scene, const hpt_job_desc *job,
-                            void *d_field, uint64_t *job_out);
+                            void *d_field, void *hip_stream, uint64_t *job_out);
 /* Wait for completion; timeout_ms < 0 waits forever. */
 hpt_status hpt_job_wait(hpt_ctx *ctx, uint64_t job, int64_t timeout_ms);
 hpt_status hpt_job_stats_get(hpt_ctx *ctx, uint64_t job, hpt_job_stats *out);
@@ -243,14 +273,15 @@ hpt_status hpt_ctx_stats_get(hpt_ctx *ctx, hpt_ctx_stats *out);
  *   d_in, d_out: device, complex64 [n_fields][height][width] (interleaved
  *     re, im), row-major; may be the same buffer. Caller-owned.
  *   width, height: 1..4096; pitch, lambda > 0 (metres); distance finite.
- * Synchronous (returns when d_out is written). Scratch (two [height][P_x]
+ * hip_stream (nullable): the propagation starts after all work enqueued on
+ * that stream before the call. Synchronous (returns when d_out is written). Scratch (two [height][P_x]
  * complex64 buffers per field of a chunk of fields, at most 1 GiB, and the
  * transforms' twiddle tables) is taken from the context's budget for the call. EINVAL on bad arguments, EBUDGET if
  * one field's scratch does not fit, EDEVICE on a HIP error. */
 #define HPT_ASM_BAND_LIMIT 1u
 hpt_status hpt_asm_propagate(hpt_ctx *ctx, const void *d_in, void *d_out, uint32_t n_fields,
                              uint32_t width, uint32_t height, double pitch, double lambda,
-                             double distance, uint32_t flags);
+                             double distance, uint32_t flags, void *hip_stream);
 
 /* Reconstruction (simulated viewing of the hologram; the paper's focal
  * stacks and time multiplexing, Sec. 5.3, physical configuration): each of the
@@ -266,13 +297,15 @@ hpt_status hpt_asm_propagate(hpt_ctx *ctx, const void *d_in, void *d_out, uint32
  *     metres; lambdas > 0, distances finite; width, height: 1..4096;
  *     n_ch, T >= 1; 1 <= n_planes <= 64; na finite.
  * The forward transforms of a chunk of frames are computed once and reused
- * for every plane. Synchronous. Scratch (three [height][P_x] complex64
+ * for every plane. hip_stream (nullable): starts after the work enqueued on
+ * it before the call. Synchronous. Scratch (three [height][P_x] complex64
  * buffers per frame of a chunk, at most 1 GiB, and twiddle tables) from the
  * context's budget for the call. EINVAL on bad arguments, EBUDGET if one
  * frame's scratch does not fit, EDEVICE on a HIP error. */
 hpt_status hpt_reconstruct(hpt_ctx *ctx, const void *d_fields, uint32_t n_ch, uint32_t T, uint32_t width,
                            uint32_t height, double pitch, const double *lambdas, uint32_t n_planes,
-                           const double *distances, double na, uint32_t flags, void *d_out);
+                           const double *distances, double na, uint32_t flags, void *d_out,
+                           void *hip_stream);
 
 /* Phase-only encoding (the paper's hologram encoding: SGD under
  * complex-amplitude supervision on one plane with a phase-shift-invariant
@@ -293,14 +326,16 @@ hpt_status hpt_reconstruct(hpt_ctx *ctx, const void *d_fields, uint32_t n_ch, ui
  *     1 - |<V, A>|^2 / (<V, V> <A, A>) in [0, 1].
  *   width, height 1..4096; pitch, lambda > 0; distance finite;
  *   iterations 0..100000; lr > 0.
- * Synchronous. Scratch (five [height][width] buffers and two [height][P_x]
+ * hip_stream (nullable): starts after the work enqueued on it before the
+ * call. Synchronous. Scratch (five [height][width] buffers and two [height][P_x]
  * complex64 buffers per field of a chunk, at most 1 GiB) from the
  * context's budget for the call. EINVAL, EBUDGET, EDEVICE as for
  * hpt_asm_propagate. */
 #define HPT_ENCODE_WARM_START 2u
 hpt_status hpt_encode_phase(hpt_ctx *ctx, const void *d_fields, uint32_t n_fields, uint32_t width,
                             uint32_t height, double pitch, double lambda, double distance,
-                            uint32_t iterations, double lr, uint32_t flags, void *d_phase, double *loss_out);
+                            uint32_t iterations, double lr, uint32_t flags, void *d_phase, double *loss_out,
+                            void *hip_stream);
 
 /* ---------------------------------------------------------------- profiling
  * Level 1: HIP events around every kernel launch on the context stream,
@@ -317,6 +352,13 @@ hpt_status hpt_profile_set(hpt_ctx *ctx, uint32_t level);
 /* out: HPT_K_KINDS entries; node_visits / prim_tests: level-2 counters (nullable). */
 hpt_status hpt_profile_get(hpt_ctx *ctx, hpt_kernel_time *out, uint64_t *node_visits, uint64_t *prim_tests);
 hpt_status hpt_profile_reset(hpt_ctx *ctx);
+
+/* ---------------------------------------------------------------- testing
+ * Failure injection for tests of the error paths: the next n batches the
+ * scheduler packs fail at launch, before any of their work is enqueued,
+ * exactly as a launch error would (their jobs end with HPT_EDEVICE once no
+ * other batch holds their units). n = 0 turns it off. */
+hpt_status hpt_debug_fail_batches(hpt_ctx *ctx, uint32_t n);
 
 #ifdef __cplusplus
 }

@@ -30,7 +30,7 @@ class SceneDesc(C.Structure):
                 ("sph", C.c_void_p), ("n_sph", C.c_uint32), ("sph_mat", C.c_void_p),
                 ("n_mat", C.c_uint32), ("mat_type", C.c_void_p), ("mat_rgb", C.c_void_p),
                 ("mat_rough", C.c_void_p), ("mat_ior", C.c_void_p), ("mat_emit", C.c_void_p),
-                ("env", C.c_void_p), ("mat_pbr", C.c_void_p)]
+                ("env", C.c_void_p), ("mat_pbr", C.c_void_p), ("pts", C.c_void_p), ("n_pts", C.c_uint32)]
 
 
 class SceneInfo(C.Structure):
@@ -53,7 +53,8 @@ class JobDesc(C.Structure):
                 ("phase_mode", C.c_uint32), ("random_phase", C.c_uint32),
                 ("use_cache", C.c_uint32), ("cache_depth", C.c_uint32),
                 ("crop", C.c_uint32 * 4), ("spp_begin", C.c_uint32), ("spp_end", C.c_uint32),
-                ("holo_from_world", C.c_double * 12), ("debug", C.c_uint32), ("nee", C.c_uint32)]
+                ("holo_from_world", C.c_double * 12), ("debug", C.c_uint32), ("nee", C.c_uint32),
+                ("weight_mode", C.c_uint32)]
 
 
 class JobStats(C.Structure):
@@ -93,7 +94,8 @@ SIGNATURES = {
     "hpt_scene_release": (C.c_int, [_vp, _u64]),
     "hpt_cache_build": (C.c_int, [_vp, _u64, C.POINTER(CacheDesc)]),
     "hpt_cache_export": (C.c_int, [_vp, _u64, _vp, _sz]),
-    "hpt_trace_submit": (C.c_int, [_vp, _u64, C.POINTER(JobDesc), _vp, C.POINTER(_u64)]),
+    "hpt_cache_import": (C.c_int, [_vp, _u64, C.POINTER(CacheDesc), _vp, _sz]),
+    "hpt_trace_submit": (C.c_int, [_vp, _u64, C.POINTER(JobDesc), _vp, _vp, C.POINTER(_u64)]),
     "hpt_job_wait": (C.c_int, [_vp, _u64, _i64]),
     "hpt_job_stats_get": (C.c_int, [_vp, _u64, C.POINTER(JobStats)]),
     "hpt_field_read": (C.c_int, [_vp, _u64, _vp, _sz]),
@@ -109,11 +111,12 @@ SIGNATURES = {
     "hpt_profile_get": (C.c_int, [_vp, C.POINTER(KernelTime), C.POINTER(_u64), C.POINTER(_u64)]),
     "hpt_profile_reset": (C.c_int, [_vp]),
     "hpt_asm_propagate": (C.c_int, [_vp, _vp, _vp, _u32, _u32, _u32, C.c_double, C.c_double, C.c_double,
-                                    _u32]),
+                                    _u32, _vp]),
     "hpt_reconstruct": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _u32, C.c_double, C.POINTER(C.c_double), _u32,
-                                  C.POINTER(C.c_double), C.c_double, _u32, _vp]),
+                                  C.POINTER(C.c_double), C.c_double, _u32, _vp, _vp]),
     "hpt_encode_phase": (C.c_int, [_vp, _vp, _u32, _u32, _u32, C.c_double, C.c_double, C.c_double, _u32,
-                                   C.c_double, _u32, _vp, C.POINTER(C.c_double)]),
+                                   C.c_double, _u32, _vp, C.POINTER(C.c_double), _vp]),
+    "hpt_debug_fail_batches": (C.c_int, [_vp, _u32]),
 }
 ASM_BAND_LIMIT = 1
 ENCODE_WARM_START = 2
@@ -173,6 +176,7 @@ def job_desc(job):
         d.holo_from_world[i] = job["holo_from_world"][i]
     d.debug = job.get("debug", 0)
     d.nee = job.get("nee", 0)
+    d.weight_mode = job.get("weight_mode", 0)
     return d
 
 
@@ -194,7 +198,8 @@ class Context:
         h = C.c_void_p()
         _check(self.lib.hpt_create(device, budget_bytes, C.byref(h)))
         self.h = h
-        self._scene_keep = {}
+        self.device = device
+        self._held = {}   # job id -> caller tensor the job writes, kept alive until wait/release
 
     def close(self):
         if getattr(self, "h", None):
@@ -222,11 +227,14 @@ class Context:
                 _arr(sc["mat_emit"], np.float32), _arr(sc["env"], np.float32)]
         pbr = sc.get("mat_pbr")
         keep.append(_arr(pbr, np.float32) if pbr is not None else None)
+        pts = _arr(sc.get("pts", np.zeros((0, 6))), np.float32).reshape(-1, 6)
+        keep.append(pts)
         d = SceneDesc(keep[0].ctypes.data, len(keep[1]), keep[1].ctypes.data,
                       keep[2].ctypes.data, len(keep[3]), keep[3].ctypes.data,
                       len(keep[4]), keep[4].ctypes.data, keep[5].ctypes.data,
                       keep[6].ctypes.data, keep[7].ctypes.data, keep[8].ctypes.data,
-                      keep[9].ctypes.data, keep[10].ctypes.data if keep[10] is not None else None)
+                      keep[9].ctypes.data, keep[10].ctypes.data if keep[10] is not None else None,
+                      pts.ctypes.data if len(pts) else None, len(pts))
         sid = C.c_uint64()
         _check(self.lib.hpt_scene_upload(self.h, C.byref(d), C.byref(sid)))
         return sid.value
@@ -249,20 +257,58 @@ class Context:
         _check(self.lib.hpt_cache_export(self.h, sid, out.ctypes.data, out.size))
         return out
 
+    def import_cache(self, sid, entries, res=64, bins=8, spb=4, max_bounces=6, seed=7):
+        a = _arr(entries, np.uint16)
+        d = CacheDesc(res, bins, spb, max_bounces, seed)
+        _check(self.lib.hpt_cache_import(self.h, sid, C.byref(d), a.ctypes.data, a.size))
+
+    def _stream(self, stream, tensors):
+        """hipStream_t handle to order a call after: an int handle, a torch
+        stream, or (None) torch's current stream when a tensor is passed."""
+        if stream is not None:
+            return stream if isinstance(stream, int) else stream.cuda_stream
+        if any(t is not None and not isinstance(t, int) for t in tensors):
+            import torch
+            return torch.cuda.current_stream(self.device).cuda_stream
+        return None
+
+    def _dev_ptr(self, t, n_elems, dtype_name, what):
+        """Device pointer of a caller buffer: an int is taken as is; a torch
+        tensor must be contiguous, on this context's device, of the given dtype
+        and element count."""
+        if isinstance(t, int):
+            return t
+        import torch
+        want = getattr(torch, dtype_name)
+        if t.dtype != want or not t.is_contiguous() or t.device.type != "cuda" or \
+                (t.device.index or 0) != self.device or t.numel() != n_elems:
+            raise ValueError("%s must be a contiguous %s tensor on cuda:%d with %d elements (got %s %s on %s, %d)"
+                             % (what, dtype_name, self.device, n_elems, t.dtype,
+                                "contiguous" if t.is_contiguous() else "strided", t.device, t.numel()))
+        return t.data_ptr()
+
     # jobs
-    def submit(self, sid, job, field=None):
+    def submit(self, sid, job, field=None, stream=None):
         """Queue a job; `field` may be a device pointer (int) or a torch
-        tensor on the context's device with n_ch*T*h*w complex64 elements."""
+        tensor on the context's device with n_ch*T*h*w complex64 elements
+        (kept alive until wait() or release_job()). The job starts after the
+        work already enqueued on `stream` (default: torch's current stream
+        when a tensor is passed)."""
         d = job_desc(job)
         ptr = None
         if field is not None:
-            ptr = field if isinstance(field, int) else field.data_ptr()
+            w, h = crop_dims(job)
+            ptr = self._dev_ptr(field, len(job["lambdas"]) * job["T"] * w * h, "complex64", "field")
+        st = self._stream(stream, [field])
         jid = C.c_uint64()
-        _check(self.lib.hpt_trace_submit(self.h, sid, C.byref(d), ptr, C.byref(jid)))
+        _check(self.lib.hpt_trace_submit(self.h, sid, C.byref(d), ptr, st, C.byref(jid)))
+        if field is not None and not isinstance(field, int):
+            self._held[jid.value] = field
         return jid.value
 
     def wait(self, jid, timeout_ms=-1):
         _check(self.lib.hpt_job_wait(self.h, jid, timeout_ms))
+        self._held.pop(jid, None)
 
     def stats(self, jid):
         s = JobStats()
@@ -308,21 +354,29 @@ class Context:
 
     def release_job(self, jid):
         _check(self.lib.hpt_job_release(self.h, jid))
+        self._held.pop(jid, None)
+
+    def debug_fail_batches(self, n):
+        _check(self.lib.hpt_debug_fail_batches(self.h, n))
 
     def grf(self, gw, gh, T, seed):
         out = np.zeros((gh, gw, T), dtype=np.complex64)
         _check(self.lib.hpt_grf_read(self.h, gw, gh, T, seed, out.ctypes.data, out.size * 2))
         return out
 
-    def asm_propagate(self, src, dst, n_fields, width, height, pitch, lam, distance, band_limit=True):
+    def asm_propagate(self, src, dst, n_fields, width, height, pitch, lam, distance, band_limit=True,
+                      stream=None):
         """Angular-spectrum propagation of n_fields complex64 [height][width]
         fields; src, dst: device pointers (int) or torch tensors."""
-        ps = src if isinstance(src, int) else src.data_ptr()
-        pd = dst if isinstance(dst, int) else dst.data_ptr()
+        n = n_fields * width * height
+        ps = self._dev_ptr(src, n, "complex64", "src")
+        pd = self._dev_ptr(dst, n, "complex64", "dst")
         _check(self.lib.hpt_asm_propagate(self.h, ps, pd, n_fields, width, height, float(pitch), float(lam),
-                                          float(distance), ASM_BAND_LIMIT if band_limit else 0))
+                                          float(distance), ASM_BAND_LIMIT if band_limit else 0,
+                                          self._stream(stream, [src, dst])))
 
-    def reconstruct(self, fields, n_ch, T, width, height, pitch, lambdas, distances, na, out, band_limit=True):
+    def reconstruct(self, fields, n_ch, T, width, height, pitch, lambdas, distances, na, out, band_limit=True,
+                    stream=None):
         """Focal stack: mean over the T frames of the intensity of each of the
         n_ch x T complex64 [height][width] fields carried to each distance,
         through a pupil of numerical aperture na (<= 0: none); fields: device
@@ -330,24 +384,27 @@ class Context:
         (device pointers (int) or torch tensors)."""
         if len(lambdas) != n_ch:
             raise ValueError("one wavelength per channel")
-        pf = fields if isinstance(fields, int) else fields.data_ptr()
-        po = out if isinstance(out, int) else out.data_ptr()
+        pf = self._dev_ptr(fields, n_ch * T * width * height, "complex64", "fields")
+        po = self._dev_ptr(out, n_ch * len(distances) * width * height, "float32", "out")
         lam = (C.c_double * len(lambdas))(*[float(x) for x in lambdas])
         dist = (C.c_double * len(distances))(*[float(x) for x in distances])
         _check(self.lib.hpt_reconstruct(self.h, pf, n_ch, T, width, height, float(pitch), lam, len(distances),
-                                        dist, float(na), ASM_BAND_LIMIT if band_limit else 0, po))
+                                        dist, float(na), ASM_BAND_LIMIT if band_limit else 0, po,
+                                        self._stream(stream, [fields, out])))
 
     def encode_phase(self, fields, phase, n_fields, width, height, pitch, lam, distance, iterations, lr,
-                     band_limit=True, warm_start=False):
+                     band_limit=True, warm_start=False, stream=None):
         """Phase-only encoding of n_fields complex64 [height][width] fields
         into float32 phases (device pointers (int) or torch tensors); returns
         the final relative loss of each field."""
-        pf = fields if isinstance(fields, int) else fields.data_ptr()
-        pp = phase if isinstance(phase, int) else phase.data_ptr()
+        n = n_fields * width * height
+        pf = self._dev_ptr(fields, n, "complex64", "fields")
+        pp = self._dev_ptr(phase, n, "float32", "phase")
         loss = (C.c_double * n_fields)()
         flags = (ASM_BAND_LIMIT if band_limit else 0) | (ENCODE_WARM_START if warm_start else 0)
         _check(self.lib.hpt_encode_phase(self.h, pf, n_fields, width, height, float(pitch), float(lam),
-                                         float(distance), int(iterations), float(lr), flags, pp, loss))
+                                         float(distance), int(iterations), float(lr), flags, pp, loss,
+                                         self._stream(stream, [fields, phase])))
         return np.array(loss[:], dtype=np.float64)
 
     # profiling

@@ -84,6 +84,9 @@ struct SceneDev {
   const double *light_cdf;   // running sum of the light areas
   uint32_t n_lights, pad2;
   double light_area;
+  // point emitters (a test primitive with a closed-form field)
+  const float4 *pts;         // 2 x float4 per emitter: world position (w unused), amplitude rgb (w unused)
+  uint32_t n_pts, pad3;
 };
 
 // Device view of a job (or of a cache build).
@@ -111,6 +114,7 @@ struct JobDev {
   uint16_t *cache_out;       // [3][res^3][bins^2]
   uint32_t cache_res, cache_bins, cache_spb;
   uint32_t nee;              // next-event estimation with MIS in the tail
+  uint32_t weight_mode;      // HPT_WEIGHT_RS_AREA: W = r / p(v); HPT_WEIGHT_PAPER_LITERAL: W = 1
 };
 
 // A contiguous block of paths of one job: pixels [p_lo, p_lo + p_n) of the

@@ -615,7 +615,7 @@ __device__ __forceinline__ void image_point(const BatchDev &B, const RayQueue &Q
     }
     D3 dq = Q - xp;
     r = sqrt(dot(dq, dq));
-    W = (float)(r * (M_PI * s * s) / vz);
+    W = J.weight_mode == HPT_WEIGHT_PAPER_LITERAL ? 1.0f : (float)(r * (M_PI * s * s) / vz);
     double x = r * J.inv_lambda[U.ch];
     rev = x - floor(x);
     qx = Q.x; qy = Q.y;
@@ -645,7 +645,7 @@ __device__ __forceinline__ void image_point(const BatchDev &B, const RayQueue &Q
     F3 dq = Q - xp;
     float rf = sqrtf(dot(dq, dq));
     float sf = J.s_cone_f[U.ch];
-    W = rf * (3.14159265358979f * sf * sf) / vz;
+    W = J.weight_mode == HPT_WEIGHT_PAPER_LITERAL ? 1.0f : rf * (3.14159265358979f * sf * sf) / vz;
     float x = rf * J.inv_lambda_f[U.ch];
     rev = x - floorf(x);
     r = rf; qx = Q.x; qy = Q.y;
@@ -1100,6 +1100,151 @@ __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
   if (dbg_s) J.sigsum[(size_t)U.ch * plane + (size_t)cy * J.crop_w + cx] += sigsum;
 }
 
+// ------------------------------------------------------------------ point emitters
+// Closest-hit-free occlusion query: whether any primitive lies on the ray
+// (o, d) at a distance in (kTmin, tmax). Plain stack traversal with the
+// whole stack (kStackMax entries per lane) in LDS, so that it needs no
+// global spill; `st` is this lane's column (stride kPtsBlock).
+constexpr int kPtsBlock = 64;
+__device__ bool segment_blocked(const SceneDev &S, F3 o, F3 d, float tmax, int32_t *st) {
+  if (S.n_nodes == 0) return false;
+  const RayPre r = ray_pre(o, d);
+  const GF4 N = as_global(S.nodes), P = as_global(S.prims);
+  int32_t node = 0;
+  int sp = 0;
+  for (;;) {
+    if (node >= 0) {
+      const float4 a = ld4(N + 4 * node), b = ld4(N + 4 * node + 1), c = ld4(N + 4 * node + 2),
+                   l4 = ld4(N + 4 * node + 3);
+      float t0, t1;
+      bool h0, h1;
+      box2(r, a, b, c, kTmin, tmax, t0, t1, h0, h1);
+      const int32_t c0 = __float_as_int(l4.x), c1 = __float_as_int(l4.y);
+      if (h0 && h1) {
+        st[sp * kPtsBlock] = t0 <= t1 ? c1 : c0;
+        ++sp;
+        node = t0 <= t1 ? c0 : c1;
+        continue;
+      }
+      if (h0 || h1) { node = h0 ? c0 : c1; continue; }
+    } else {
+      const uint32_t v = (uint32_t)(~node), first = v >> 3, cnt = (v & 7u) + 1u;
+      for (uint32_t k = 0; k < cnt; ++k) {
+        const GF4 p = P + 3 * (size_t)(first + k);
+        const float4 p0 = ld4(p), p1 = ld4(p + 1);
+        float t;
+        const bool h = __float_as_int(p1.w) == 1
+                           ? sph_hit(r, f3(p0.x, p0.y, p0.z), p1.x, kTmin, tmax, t)
+                           : tri_hit(r, f3(p0.x, p0.y, p0.z), f3(p1.x, p1.y, p1.z),
+                                     f3(ld4(p + 2).x, ld4(p + 2).y, ld4(p + 2).z), kTmin, tmax, t);
+        if (h && t < tmax) return true;
+      }
+    }
+    if (sp == 0) return false;
+    node = st[--sp * kPtsBlock];
+  }
+}
+
+// Unit phasor of frame t at hologram-space (qx, qy): bilinear interpolation
+// of the random field (texel (i, j) on pixel centre (i, j), periodic), then
+// normalised (1 where it vanishes); the same arithmetic as the accumulation.
+__device__ __forceinline__ float2 grf_unit(const JobDev &J, uint32_t t, double qx, double qy) {
+  const double u = qx / J.pitch + 0.5 * (double)J.width - 0.5;
+  const double v = qy / J.pitch + 0.5 * (double)J.height - 0.5;
+  const double fu = floor(u), fv = floor(v);
+  int64_t i0 = (int64_t)fu % (int64_t)J.grf_w, j0 = (int64_t)fv % (int64_t)J.grf_h;
+  if (i0 < 0) i0 += J.grf_w;
+  if (j0 < 0) j0 += J.grf_h;
+  const uint32_t i1 = i0 + 1 == J.grf_w ? 0 : (uint32_t)i0 + 1, j1 = j0 + 1 == J.grf_h ? 0 : (uint32_t)j0 + 1;
+  const auto G2 = glb(J.grf) + t;
+  const size_t gw = J.grf_w, T = J.T;
+  const float2 qa = G2[((size_t)j0 * gw + i0) * T], qb = G2[((size_t)j0 * gw + i1) * T],
+               qc = G2[((size_t)j1 * gw + i0) * T], qd = G2[((size_t)j1 * gw + i1) * T];
+  const float x = (float)(u - fu), y = (float)(v - fv);
+  const float w00 = (1.f - x) * (1.f - y), w10 = x * (1.f - y), w01 = (1.f - x) * y, w11 = x * y;
+  const float zr = w00 * qa.x + w10 * qb.x + w01 * qc.x + w11 * qd.x;
+  const float zi = w00 * qa.y + w10 * qb.y + w01 * qc.y + w11 * qd.y;
+  const float m2 = zr * zr + zi * zi;
+  if (!(m2 > 0.f)) return make_float2(1.f, 0.f);
+  const float inv = rsqrtf(m2);
+  return make_float2(zr * inv, zi * inv);
+}
+
+// Point emitters: pixel p of a unit that starts at sample 0 receives, for
+// every emitter y in front of the plane inside its recordable cone and not
+// occluded, a exp(i (k r + phi_t(Q))) / r in frame t, Q = T y, r = |Q - x_p|
+// (Eq. 2 for a point source, obliquity 1). Grid: x over a unit's pixels,
+// y over the batch's units. The cone test and r are FP64 in every mode; the
+// phase is carried like a path's (FP64 reduction frac(r / lambda), sin/cos
+// in FP64 for FP64 phase, FP32 otherwise; all FP32 in FP32 phase).
+__global__ void __launch_bounds__(kPtsBlock) k_points(BatchDev B) {
+  __shared__ int32_t stack[kStackMax * kPtsBlock];
+  const UnitDev U = B.units[blockIdx.y];
+  if (U.kind != UNIT_HOLO || U.s_lo != 0) return;
+  const uint32_t pl = blockIdx.x * kPtsBlock + threadIdx.x;
+  if (pl >= U.p_n) return;
+  const JobDev &J = *U.job;
+  const SceneDev &S = *J.scene;
+  if (S.n_pts == 0) return;
+  uint32_t cx, cy;
+  crop_xy(J, U.p_lo + pl, cx, cy);
+  const uint32_t px = J.crop_x0 + cx, py = J.crop_y0 + cy;
+  const uint32_t comp = J.comp[U.ch];
+  const D3 xp = {((double)px + 0.5 - 0.5 * (double)J.width) * J.pitch,
+                 ((double)py + 0.5 - 0.5 * (double)J.height) * J.pitch, 0.0};
+  const double *Ti = J.Ti, *M = J.Tm;
+  const D3 O = {Ti[0] * xp.x + Ti[1] * xp.y + Ti[2] * xp.z + Ti[3], Ti[4] * xp.x + Ti[5] * xp.y + Ti[6] * xp.z + Ti[7],
+                Ti[8] * xp.x + Ti[9] * xp.y + Ti[10] * xp.z + Ti[11]};
+  const double s = J.s_cone[U.ch];
+  const size_t plane = (size_t)J.crop_h * J.crop_w;
+  const auto F = glb(J.field) + (size_t)U.ch * J.T * plane + (size_t)cy * J.crop_w + cx;
+  const auto E = as_global(S.pts);
+  for (uint32_t e = 0; e < S.n_pts; ++e) {
+    const float4 pos = ld4(E + 2 * e), amp4 = ld4(E + 2 * e + 1);
+    const float a = comp == 0 ? amp4.x : (comp == 1 ? amp4.y : amp4.z);
+    if (a == 0.f) continue;
+    const D3 y = {pos.x, pos.y, pos.z};
+    const D3 Q = {M[0] * y.x + M[1] * y.y + M[2] * y.z + M[3], M[4] * y.x + M[5] * y.y + M[6] * y.z + M[7],
+                  M[8] * y.x + M[9] * y.y + M[10] * y.z + M[11]};
+    const D3 dq = Q - xp;
+    const double r = sqrt(dot(dq, dq));
+    if (!(dq.z > 0.0) || dq.x * dq.x + dq.y * dq.y > s * s * r * r) continue;
+    const D3 seg = y - O;
+    const double dist = sqrt(dot(seg, seg));
+    if (segment_blocked(S, to_f(O), to_f((1.0 / dist) * seg), (float)dist, stack + threadIdx.x)) continue;
+    double cr, ci;
+    if (J.phase_mode == HPT_PHASE_FP32) {
+      const float rf = (float)r, x = rf * J.inv_lambda_f[U.ch];
+      float sn, cs;
+      sincospif(2.0f * (x - floorf(x)), &sn, &cs);
+      cr = (double)(a / rf * cs); ci = (double)(a / rf * sn);
+    } else {
+      const double x = r * J.inv_lambda[U.ch], rev = x - floor(x);
+      if (J.phase_mode == HPT_PHASE_FP64) {
+        double sn, cs;
+        sincospi(2.0 * rev, &sn, &cs);
+        cr = a / r * cs; ci = a / r * sn;
+      } else {
+        float sn, cs;
+        sincospif(2.0f * (float)rev, &sn, &cs);
+        const float ar = (float)(a / r);
+        cr = (double)(ar * cs); ci = (double)(ar * sn);
+      }
+    }
+    for (uint32_t t = 0; t < J.T; ++t) {
+      double zr = cr, zi = ci;
+      if (J.random_phase) {
+        const float2 ph = grf_unit(J, t, Q.x, Q.y);
+        zr = cr * ph.x - ci * ph.y;
+        zi = cr * ph.y + ci * ph.x;
+      }
+      float2 v = F[(size_t)t * plane];
+      v.x += (float)zr; v.y += (float)zi;
+      F[(size_t)t * plane] = v;
+    }
+  }
+}
+
 // Mean radiance of each cache entry over its paths, rounded to binary16.
 __global__ void __launch_bounds__(kBlock) k_cache_reduce(BatchDev B) {
   uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1253,6 +1398,12 @@ hipError_t launch_accumulate(const BatchDev &B, bool has_f64, bool has_f32, hipS
   uint32_t g = round8(grid_for(B.n_acc));
   if (has_f32) hipLaunchKernelGGL(k_accumulate<false>, dim3(g), dim3(kBlock), 0, st, B);
   if (has_f64) hipLaunchKernelGGL(k_accumulate<true>, dim3(g), dim3(kBlock), 0, st, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_points(const BatchDev &B, uint32_t max_pn, hipStream_t st) {
+  if (B.n_units == 0 || max_pn == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_points, dim3((max_pn + kPtsBlock - 1) / kPtsBlock, B.n_units), dim3(kPtsBlock), 0, st, B);
   return hipGetLastError();
 }
 

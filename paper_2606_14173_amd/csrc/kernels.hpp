@@ -24,6 +24,10 @@ uint32_t shade_lds_mats();
 uint32_t shade_lds_units();
 hipError_t launch_accumulate(const BatchDev &B, bool has_f64, bool has_f32, hipStream_t st);
 hipError_t launch_cache_reduce(const BatchDev &B, hipStream_t st);
+// Point-emitter terms of the batch's hologram units that start at sample 0
+// (added to the field; run after the batch's accumulation, on its stream).
+// max_pn: the largest pixel count of a unit in the batch.
+hipError_t launch_points(const BatchDev &B, uint32_t max_pn, hipStream_t st);
 hipError_t launch_grf(double2 *spec, double2 *rows, float2 *table, uint32_t gw, uint32_t gh, uint32_t T,
                       uint64_t seed, double scale, hipStream_t st);
 

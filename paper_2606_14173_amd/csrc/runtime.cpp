@@ -106,6 +106,9 @@ struct Job {
   hpt_status status = HPT_OK;
   std::string err;
   bool cancel = false;
+  hpt_status fail_status = HPT_OK;  // a batch holding its units failed; retired once none is in flight
+  std::string fail_err;
+  hipEvent_t ready = nullptr;  // recorded on the caller's stream at submit: the job's work waits for it
   size_t bytes = 0;       // device bytes it holds while admitted (not counting the table)
   size_t grf_bytes = 0;   // bytes of its random-phase table if it must be built
   Clock::time_point t_submit, t_start, t_end;
@@ -180,10 +183,12 @@ struct hpt_ctx {
     std::vector<Picked> P;
     uint32_t profile = 0, paths = 0;
     bool has_holo = false, has_cache = false;
+    uint32_t pts_max_pn = 0;    // largest pixel count of a unit with point-emitter terms (0: none)
     hpt_status launch_status = HPT_OK;
     std::string err;
   } slots[2];
   uint64_t batches = 0, jobs_done = 0;
+  uint32_t fail_batches = 0;  // failure injection (hpt_debug_fail_batches)
   // profiling (guarded by mu; events used by the scheduler thread only)
   uint32_t profile = 0;
   hpt_kernel_time ktime[HPT_K_KINDS] = {};
@@ -315,6 +320,7 @@ void free_job_buffers(hpt_ctx *C, Job *J) {
   C->release(J->sigsum, J->n_sig * sizeof(unsigned long long));
   C->release(J->dev, sizeof(JobDev));
   J->field = nullptr; J->rec = nullptr; J->contrib = nullptr; J->sigsum = nullptr; J->dev = nullptr;
+  if (J->ready) { (void)hipEventDestroy(J->ready); J->ready = nullptr; }
 }
 
 void retire(hpt_ctx *C, Job *J, JobState st, hpt_status status, const std::string &err) {
@@ -357,7 +363,10 @@ hpt_status admit(hpt_ctx *C, Job *J) {
   J->host.contrib = J->contrib;
   J->host.sigsum = J->sigsum;
   hipError_t e = hipSuccess;
-  if (J->field && !J->cache_build) e = hipMemsetAsync(J->field, 0, J->field_elems * sizeof(float2), C->stream);
+  // the caller's stream: everything it had enqueued at submit runs before the job's first work
+  if (J->ready) e = hipStreamWaitEvent(C->stream, J->ready, 0);
+  if (e == hipSuccess && J->field && !J->cache_build)
+    e = hipMemsetAsync(J->field, 0, J->field_elems * sizeof(float2), C->stream);
   if (e == hipSuccess && J->rec) e = hipMemsetAsync(J->rec, 0, J->n_rec * sizeof(hpt_path_record), C->stream);
   if (e == hipSuccess && J->contrib) e = hipMemsetAsync(J->contrib, 0, J->n_contrib * sizeof(float2), C->stream);
   if (e == hipSuccess && J->sigsum)
@@ -443,6 +452,9 @@ hipError_t launch_accumulation(hpt_ctx *C, int si, hipEvent_t after) {
   const BatchDev &B = L.B;
   if (L.has_holo)
     timed_launch(L, HPT_K_ACCUMULATE, C->acc, e, [&] { return launch_accumulate(B, L.has_f64, L.has_f32, C->acc); });
+  // point-emitter terms: on the same stream after the accumulation, so that
+  // every read-modify-write of a pixel's field is ordered
+  if (e == hipSuccess && L.pts_max_pn) e = launch_points(B, L.pts_max_pn, C->acc);
   if (L.has_cache) timed_launch(L, HPT_K_CACHE_REDUCE, C->acc, e, [&] { return launch_cache_reduce(B, C->acc); });
   if (e == hipSuccess) e = hipEventRecord(L.ev_done, C->acc);
   return e;
@@ -460,6 +472,7 @@ hpt_status launch_batch(hpt_ctx *C, int si, int prev) {
   const std::vector<Picked> &P = L.P;
   uint32_t slot = 0, acc = 0, max_b = 0;
   L.has_holo = L.has_cache = L.has_f64 = L.has_f32 = L.has_ext = false;
+  L.pts_max_pn = 0;
   for (size_t k = 0; k < P.size(); ++k) {
     const Unit &u = P[k].job->units[P[k].unit];
     UnitDev &d = L.h_units[k];
@@ -473,6 +486,7 @@ hpt_status launch_batch(hpt_ctx *C, int si, int prev) {
     if (u.kind == UNIT_HOLO) {
       L.has_holo = true;
       if (J.phase_mode == HPT_PHASE_FP64) L.has_f64 = true; else L.has_f32 = true;
+      if (u.s_lo == 0 && P[k].job->scene->host.n_pts) L.pts_max_pn = std::max(L.pts_max_pn, u.p_n);
     } else {
       L.has_cache = true;
     }
@@ -585,8 +599,18 @@ void account_batch(hpt_ctx *C, int si, hpt_status s, const std::string &err, dou
     seen.push_back(J);
     J->stats.batches++;
     if (J->state != JS_RUNNING) continue;
-    if (s != HPT_OK) retire(C, J, JS_FAILED, s, err);
-    else if (J->done == J->units.size()) retire(C, J, JS_DONE, HPT_OK, "");
+    if (s != HPT_OK) {
+      // the job stops at its next batch boundary; a batch in the other slot
+      // may still hold its units (and read its scene, table and buffers), so
+      // it is retired only once none is in flight
+      if (J->fail_status == HPT_OK) { J->fail_status = s; J->fail_err = err; }
+      J->cancel = true;
+    }
+    if (J->fail_status != HPT_OK) {
+      if (J->in_flight == 0) retire(C, J, JS_FAILED, J->fail_status, J->fail_err);
+    } else if (J->done == J->units.size()) {
+      retire(C, J, JS_DONE, HPT_OK, "");
+    }
   }
   C->slots[si].P.clear();
 }
@@ -611,8 +635,12 @@ void scheduler(hpt_ctx *C) {
     // retired once its batch has finished
     for (size_t k = 0; k < C->running.size();) {
       Job *J = C->running[k];
-      if (J->cancel && J->in_flight == 0) retire(C, J, JS_CANCELED, HPT_ECANCELED, "cancelled");
-      else ++k;
+      if (J->cancel && J->in_flight == 0) {
+        if (J->fail_status != HPT_OK) retire(C, J, JS_FAILED, J->fail_status, J->fail_err);
+        else retire(C, J, JS_CANCELED, HPT_ECANCELED, "cancelled");
+      } else {
+        ++k;
+      }
     }
     // admission in arrival order while memory allows
     while (!C->stop && !C->queue.empty()) {
@@ -649,8 +677,15 @@ void scheduler(hpt_ctx *C) {
         hpt_ctx::Slot &L = C->slots[cur];
         L.P = std::move(P);
         L.profile = C->profile;
+        const bool inject = C->fail_batches > 0;
+        if (inject) C->fail_batches--;
         lk.unlock();
-        L.launch_status = launch_batch(C, cur, inflight);
+        if (inject) {
+          L.acc_pending = false;
+          L.launch_status = fail(HPT_EDEVICE, "batch launch failed (injected)");
+        } else {
+          L.launch_status = launch_batch(C, cur, inflight);
+        }
         L.err = L.launch_status == HPT_OK ? std::string() : g_err;
         lk.lock();
         launched = cur;
@@ -857,6 +892,12 @@ hpt_status hpt_scene_upload(hpt_ctx *C, const hpt_scene_desc *d, uint64_t *out) 
     if (!finite3(d->mat_rgb + 3 * i) || !finite3(d->mat_emit + 3 * i)) return fail(HPT_EINVAL, "non-finite material");
   }
   if (!finite3(d->env)) return fail(HPT_EINVAL, "non-finite environment");
+  if (d->n_pts > 4096 || (d->n_pts && !d->pts)) return fail(HPT_EINVAL, "point emitters: at most 4096, array required");
+  for (uint32_t i = 0; i < d->n_pts; ++i) {
+    const float *p = d->pts + 6 * (size_t)i;
+    if (!finite3(p) || !finite3(p + 3) || p[3] < 0.f || p[4] < 0.f || p[5] < 0.f)
+      return fail(HPT_EINVAL, "point emitter: non-finite position or negative amplitude");
+  }
   for (uint32_t i = 0; i < d->n_tri; ++i) {
     if (d->tri_mat[i] >= d->n_mat) return fail(HPT_EINVAL, "triangle material index out of range");
     for (int k = 0; k < 3; ++k)
@@ -949,9 +990,15 @@ hpt_status hpt_scene_upload(hpt_ctx *C, const hpt_scene_desc *d, uint64_t *out) 
   }
   std::lock_guard<std::mutex> g(C->mu);
   (void)hipSetDevice(C->device);
+  std::vector<float4> pts(2 * (size_t)d->n_pts);
+  for (uint32_t i = 0; i < d->n_pts; ++i) {
+    const float *p = d->pts + 6 * (size_t)i;
+    pts[2 * i] = make_float4(p[0], p[1], p[2], 0.f);
+    pts[2 * i + 1] = make_float4(p[3], p[4], p[5], 0.f);
+  }
   size_t need = bvh.nodes.size() * 4 + bvh.prims.size() * 4 + sizeof(HitRec) * hits.size() +
                 sizeof(MaterialDev) * mats.size() + sizeof(SceneDev) + sizeof(float4) * lights.size() +
-                sizeof(double) * light_cdf.size();
+                sizeof(double) * light_cdf.size() + sizeof(float4) * pts.size();
   if (C->used + need > C->budget) evict_grfs(C, need);
   if (C->used + need > C->budget) return fail(HPT_EBUDGET, "scene does not fit the budget");
   auto put = [&](const void *src, size_t bytes, void **dst) {
@@ -976,6 +1023,8 @@ hpt_status hpt_scene_upload(hpt_ctx *C, const hpt_scene_desc *d, uint64_t *out) 
   }
   h.n_lights = (uint32_t)light_cdf.size();
   h.light_area = light_area;
+  if (!pts.empty()) { ok &= put(pts.data(), sizeof(float4) * pts.size(), &p); h.pts = (const float4 *)p; }
+  h.n_pts = d->n_pts;
   for (uint32_t i = 0; i < d->n_mat; ++i)
     if (d->mat_type[i] == HPT_PRINCIPLED) S->principled = true;
   h.n_sph = d->n_sph; h.n_tri = d->n_tri; h.n_mat = d->n_mat; h.n_nodes = n ? bvh.n_nodes : 0;
@@ -1026,14 +1075,69 @@ hpt_status hpt_scene_release(hpt_ctx *C, uint64_t scene) {
   return HPT_OK;
 }
 
-hpt_status hpt_cache_build(hpt_ctx *C, uint64_t scene, const hpt_cache_desc *cd) {
-  if (!C || !cd) return fail(HPT_EINVAL, "null argument");
+namespace {
+hpt_status check_cache_desc(const hpt_cache_desc *cd, uint64_t &entries) {
   if (cd->res < 1 || cd->res > 256 || cd->bins < 1 || cd->bins > 64 || cd->spb < 1 || cd->spb > 4096 ||
       cd->max_bounces < 1 || cd->max_bounces > 31)
     return fail(HPT_EINVAL, "cache parameters out of range");
-  uint64_t entries = (uint64_t)cd->res * cd->res * cd->res * cd->bins * cd->bins;
+  entries = (uint64_t)cd->res * cd->res * cd->res * cd->bins * cd->bins;
   if (entries >= (1ull << 31) || cd->bins * cd->bins > 65536 || cd->spb > 65535)
     return fail(HPT_EINVAL, "cache too large");
+  return HPT_OK;
+}
+
+// (Re)allocate the cache of S and set up its grid: the scene bounds inflated
+// by 1e-3 of their largest extent, res^3 cells (lock held).
+hpt_status cache_alloc(hpt_ctx *C, Scene *S, const hpt_cache_desc *cd, uint64_t entries) {
+  size_t bytes = 3 * entries * sizeof(uint16_t);
+  if (S->cache) { C->release(S->cache, S->cache_bytes); S->cache = nullptr; S->cache_bytes = 0; }
+  if (C->used + bytes > C->budget) evict_grfs(C, bytes);
+  if (C->used + bytes > C->budget) return fail(HPT_EBUDGET, "cache does not fit the budget");
+  if (C->alloc((void **)&S->cache, bytes) != hipSuccess) return fail(HPT_ENOMEM, "cache allocation failed");
+  S->cache_bytes = bytes;
+  S->cache_desc = *cd;
+  double ext = std::max({S->hi[0] - S->lo[0], S->hi[1] - S->lo[1], S->hi[2] - S->lo[2]});
+  double pad = 1e-3 * ext;
+  SceneDev &h = S->host;
+  for (int a = 0; a < 3; ++a) {
+    h.cache_lo_d[a] = S->lo[a] - pad;
+    h.cache_hi_d[a] = S->hi[a] + pad;
+    h.cache_lo[a] = (float)h.cache_lo_d[a];
+    double w = h.cache_hi_d[a] - h.cache_lo_d[a];
+    h.cache_scale[a] = (float)(w > 0 ? cd->res / w : 0.0);
+  }
+  h.cache = nullptr;  // set once the entries are in place
+  h.cache_res = cd->res; h.cache_bins = cd->bins;
+  return HPT_OK;
+}
+}  // namespace
+
+hpt_status hpt_cache_import(hpt_ctx *C, uint64_t scene, const hpt_cache_desc *cd, const uint16_t *host, size_t n) {
+  if (!C || !cd || !host) return fail(HPT_EINVAL, "null argument");
+  uint64_t entries = 0;
+  hpt_status st = check_cache_desc(cd, entries);
+  if (st != HPT_OK) return st;
+  if (n != 3 * entries) return fail(HPT_EINVAL, "size mismatch: n must be 3 res^3 bins^2");
+  std::lock_guard<std::mutex> g(C->mu);
+  Scene *S = find_scene(C, scene);
+  if (!S) return fail(HPT_ENOTFOUND, "unknown scene");
+  if (S->users > 0) return fail(HPT_EBUSY, "scene in use by a job");
+  (void)hipSetDevice(C->device);
+  st = cache_alloc(C, S, cd, entries);
+  if (st != HPT_OK) return st;
+  if (hipMemcpy(S->cache, host, S->cache_bytes, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(HPT_EDEVICE, "cache copy failed");
+  S->host.cache = S->cache;
+  if (hipMemcpy(S->dev, &S->host, sizeof(SceneDev), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(HPT_EDEVICE, "scene update failed");
+  return HPT_OK;
+}
+
+hpt_status hpt_cache_build(hpt_ctx *C, uint64_t scene, const hpt_cache_desc *cd) {
+  if (!C || !cd) return fail(HPT_EINVAL, "null argument");
+  uint64_t entries = 0;
+  hpt_status cst = check_cache_desc(cd, entries);
+  if (cst != HPT_OK) return cst;
   uint64_t id;
   {
     std::unique_lock<std::mutex> lk(C->mu);
@@ -1041,26 +1145,9 @@ hpt_status hpt_cache_build(hpt_ctx *C, uint64_t scene, const hpt_cache_desc *cd)
     if (!S) return fail(HPT_ENOTFOUND, "unknown scene");
     if (S->users > 0) return fail(HPT_EBUSY, "scene in use by a job");
     (void)hipSetDevice(C->device);
-    size_t bytes = 3 * entries * sizeof(uint16_t);
-    if (S->cache) { C->release(S->cache, S->cache_bytes); S->cache = nullptr; S->cache_bytes = 0; }
-    if (C->used + bytes > C->budget) evict_grfs(C, bytes);
-    if (C->used + bytes > C->budget) return fail(HPT_EBUDGET, "cache does not fit the budget");
-    if (C->alloc((void **)&S->cache, bytes) != hipSuccess) return fail(HPT_ENOMEM, "cache allocation failed");
-    S->cache_bytes = bytes;
-    S->cache_desc = *cd;
-    // grid: bounds inflated by 1e-3 of the largest extent
-    double ext = std::max({S->hi[0] - S->lo[0], S->hi[1] - S->lo[1], S->hi[2] - S->lo[2]});
-    double pad = 1e-3 * ext;
-    SceneDev &h = S->host;
-    for (int a = 0; a < 3; ++a) {
-      h.cache_lo_d[a] = S->lo[a] - pad;
-      h.cache_hi_d[a] = S->hi[a] + pad;
-      h.cache_lo[a] = (float)h.cache_lo_d[a];
-      double w = h.cache_hi_d[a] - h.cache_lo_d[a];
-      h.cache_scale[a] = (float)(w > 0 ? cd->res / w : 0.0);
-    }
-    h.cache = nullptr;  // not used while it is being built
-    h.cache_res = cd->res; h.cache_bins = cd->bins;
+    cst = cache_alloc(C, S, cd, entries);
+    if (cst != HPT_OK) return cst;
+    SceneDev &h = S->host;  // h.cache stays null (unused) while the cache is being built
     if (hipMemcpy(S->dev, &h, sizeof(SceneDev), hipMemcpyHostToDevice) != hipSuccess)
       return fail(HPT_EDEVICE, "scene update failed");
     auto J = std::make_unique<Job>();
@@ -1114,7 +1201,8 @@ hpt_status hpt_cache_export(hpt_ctx *C, uint64_t scene, uint16_t *host, size_t n
   return HPT_OK;
 }
 
-hpt_status hpt_trace_submit(hpt_ctx *C, uint64_t scene, const hpt_job_desc *d, void *d_field, uint64_t *out) {
+hpt_status hpt_trace_submit(hpt_ctx *C, uint64_t scene, const hpt_job_desc *d, void *d_field, void *hip_stream,
+                            uint64_t *out) {
   if (!C || !d || !out) return fail(HPT_EINVAL, "null argument");
   if (d->width == 0 || d->height == 0 || d->width > 32768 || d->height > 32768)
     return fail(HPT_EINVAL, "bad SLM size");
@@ -1148,6 +1236,7 @@ hpt_status hpt_trace_submit(hpt_ctx *C, uint64_t scene, const hpt_job_desc *d, v
   if (!S) return fail(HPT_ENOTFOUND, "unknown scene");
   if (d->use_cache && !S->host.cache) return fail(HPT_EINVAL, "use_cache needs hpt_cache_build first");
   if (d->nee > 1) return fail(HPT_EINVAL, "nee must be 0 or 1");
+  if (d->weight_mode > HPT_WEIGHT_PAPER_LITERAL) return fail(HPT_EINVAL, "unknown weight mode");
   auto J = std::make_unique<Job>();
   J->desc = *d;
   J->scene = S;
@@ -1170,6 +1259,7 @@ hpt_status hpt_trace_submit(hpt_ctx *C, uint64_t scene, const hpt_job_desc *d, v
   jd.random_phase = d->random_phase ? 1 : 0;
   jd.use_cache = d->use_cache ? 1 : 0;
   jd.nee = d->nee ? 1 : 0;
+  jd.weight_mode = d->weight_mode;
   jd.cache_depth = d->cache_depth;
   jd.debug = d->debug;
   jd.seed = d->seed;
@@ -1193,6 +1283,14 @@ hpt_status hpt_trace_submit(hpt_ctx *C, uint64_t scene, const hpt_job_desc *d, v
   uint64_t fixed = C->batch_bytes;
   for (auto &kv : C->scenes) fixed += kv.second->bytes + kv.second->cache_bytes;
   if (fixed + J->bytes + J->grf_bytes > C->budget) return fail(HPT_EBUDGET, "job can never fit the budget");
+  if (hip_stream) {
+    (void)hipSetDevice(C->device);
+    if (hipEventCreateWithFlags(&J->ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(J->ready, (hipStream_t)hip_stream) != hipSuccess) {
+      if (J->ready) (void)hipEventDestroy(J->ready);
+      return fail(HPT_EDEVICE, "cannot record an event on the caller's stream");
+    }
+  }
   split_units(J.get(), C->capacity);
   J->id = C->next_id++;
   J->t_submit = Clock::now();
@@ -1289,6 +1387,16 @@ hpt_status hpt_job_release(hpt_ctx *C, uint64_t id) {
   return HPT_OK;
 }
 
+hpt_status hpt_debug_fail_batches(hpt_ctx *C, uint32_t n) {
+  if (!C) return fail(HPT_EINVAL, "null context");
+  {
+    std::lock_guard<std::mutex> g(C->mu);
+    C->fail_batches = n;
+  }
+  C->cv.notify_all();
+  return HPT_OK;
+}
+
 hpt_status hpt_profile_set(hpt_ctx *C, uint32_t level) {
   if (!C || level > 2) return fail(HPT_EINVAL, "bad argument");
   std::lock_guard<std::mutex> g(C->mu);
@@ -1334,6 +1442,19 @@ hpt_status hpt_grf_read(hpt_ctx *C, uint32_t gw, uint32_t gh, uint32_t T, uint64
 constexpr uint32_t kMaxFieldsPerLaunch = 65535;
 
 namespace {
+// Order the work about to be enqueued on `work` after everything enqueued on
+// the caller's stream so far (no-op for a null caller stream).
+hipError_t after_caller(hipStream_t work, void *caller) {
+  if (!caller) return hipSuccess;
+  hipEvent_t ev;
+  hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(ev, (hipStream_t)caller);
+  if (e == hipSuccess) e = hipStreamWaitEvent(work, ev, 0);
+  (void)hipEventDestroy(ev);  // released once the wait has been satisfied
+  return e;
+}
+
 // Transfer-function constants of one propagation (na > 0: pupil cutoff NA / lambda).
 AsmParams asm_params(uint32_t width, uint32_t height, double pitch, double lambda, double distance, uint32_t flags,
                      double na) {
@@ -1357,7 +1478,8 @@ AsmParams asm_params(uint32_t width, uint32_t height, double pitch, double lambd
 extern "C" {
 
 hpt_status hpt_asm_propagate(hpt_ctx *C, const void *d_in, void *d_out, uint32_t n_fields, uint32_t width,
-                             uint32_t height, double pitch, double lambda, double distance, uint32_t flags) {
+                             uint32_t height, double pitch, double lambda, double distance, uint32_t flags,
+                             void *hip_stream) {
   if (!C || !d_in || !d_out) return fail(HPT_EINVAL, "null argument");
   if (n_fields < 1 || width < 1 || height < 1 || width > 4096 || height > 4096)
     return fail(HPT_EINVAL, "field size out of range (1..4096 per axis, at least one field)");
@@ -1392,7 +1514,8 @@ hpt_status hpt_asm_propagate(hpt_ctx *C, const void *d_in, void *d_out, uint32_t
       return fail(HPT_ENOMEM, "scratch allocation failed");
     }
   }
-  hipError_t e = launch_asm_twiddles(W, width, height, C->aux);
+  hipError_t e = after_caller(C->aux, hip_stream);
+  if (e == hipSuccess) e = launch_asm_twiddles(W, width, height, C->aux);
   const size_t field = (size_t)width * height;
   for (uint32_t f0 = 0; f0 < n_fields && e == hipSuccess; f0 += chunk) {
     uint32_t nf = std::min(chunk, n_fields - f0);
@@ -1414,7 +1537,7 @@ hpt_status hpt_asm_propagate(hpt_ctx *C, const void *d_in, void *d_out, uint32_t
 
 hpt_status hpt_encode_phase(hpt_ctx *C, const void *d_fields, uint32_t n_fields, uint32_t width, uint32_t height,
                             double pitch, double lambda, double distance, uint32_t iterations, double lr,
-                            uint32_t flags, void *d_phase, double *loss_out) {
+                            uint32_t flags, void *d_phase, double *loss_out, void *hip_stream) {
   if (!C || !d_fields || !d_phase) return fail(HPT_EINVAL, "null argument");
   if (n_fields < 1 || width < 1 || height < 1 || width > 4096 || height > 4096)
     return fail(HPT_EINVAL, "field size out of range (1..4096 per axis, at least one field)");
@@ -1464,7 +1587,8 @@ hpt_status hpt_encode_phase(hpt_ctx *C, const void *d_fields, uint32_t n_fields,
     }
   }
   hipStream_t st = C->aux;
-  hipError_t e = launch_asm_twiddles(W, width, height, st);
+  hipError_t e = after_caller(st, hip_stream);
+  if (e == hipSuccess) e = launch_asm_twiddles(W, width, height, st);
   const bool warm = (flags & HPT_ENCODE_WARM_START) != 0;
   for (uint32_t f0 = 0; f0 < n_fields && e == hipSuccess; f0 += chunk) {
     const uint32_t nf = std::min(chunk, n_fields - f0);
@@ -1502,7 +1626,7 @@ hpt_status hpt_encode_phase(hpt_ctx *C, const void *d_fields, uint32_t n_fields,
 
 hpt_status hpt_reconstruct(hpt_ctx *C, const void *d_fields, uint32_t n_ch, uint32_t T, uint32_t width,
                            uint32_t height, double pitch, const double *lambdas, uint32_t n_planes,
-                           const double *distances, double na, uint32_t flags, void *d_out) {
+                           const double *distances, double na, uint32_t flags, void *d_out, void *hip_stream) {
   if (!C || !d_fields || !d_out || !lambdas || !distances) return fail(HPT_EINVAL, "null argument");
   if (n_ch < 1 || T < 1 || n_planes < 1 || n_planes > 64)
     return fail(HPT_EINVAL, "need n_ch >= 1, T >= 1 and 1..64 planes");
@@ -1544,7 +1668,8 @@ hpt_status hpt_reconstruct(hpt_ctx *C, const void *d_fields, uint32_t n_ch, uint
       return fail(HPT_ENOMEM, "scratch allocation failed");
     }
   }
-  hipError_t e = launch_asm_twiddles(W, width, height, C->aux);
+  hipError_t e = after_caller(C->aux, hip_stream);
+  if (e == hipSuccess) e = launch_asm_twiddles(W, width, height, C->aux);
   const size_t field = (size_t)width * height;
   const float weight = 1.0f / (float)T;
   for (uint32_t c = 0; c < n_ch && e == hipSuccess; ++c) {

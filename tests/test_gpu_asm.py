@@ -90,7 +90,7 @@ def test_asm_rejects_bad_arguments(ctx):
         a = dict(n=1, w=8, h=8, pitch=8e-6, lam=520e-9, z=1e-3, flags=1)
         a.update(b)
         st = ctx.lib.hpt_asm_propagate(ctx.h, buf.data_ptr(), buf.data_ptr(), a["n"], a["w"], a["h"], a["pitch"],
-                                       a["lam"], a["z"], a["flags"])
+                                       a["lam"], a["z"], a["flags"], None)
         assert hpt.STATUS[st] == "HPT_EINVAL", b
 
 

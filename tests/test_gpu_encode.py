@@ -134,5 +134,5 @@ def test_encode_rejects_bad_arguments(ctx):
         a = dict(good)
         a.update(b)
         st = ctx.lib.hpt_encode_phase(ctx.h, f.data_ptr(), a["n"], a["w"], a["h"], a["pitch"], a["lam"], a["z"],
-                                      a["K"], a["lr"], a["flags"], p.data_ptr(), None)
+                                      a["K"], a["lr"], a["flags"], p.data_ptr(), None, None)
         assert hpt.STATUS[st] == "HPT_EINVAL", b

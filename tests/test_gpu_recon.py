@@ -100,7 +100,7 @@ def test_recon_rejects_bad_arguments(ctx):
         lam = (C.c_double * len(a["lam"]))(*a["lam"])
         dist = (C.c_double * len(a["dist"]))(*a["dist"])
         st = ctx.lib.hpt_reconstruct(ctx.h, f.data_ptr(), a["n_ch"], a["T"], a["w"], a["h"], a["pitch"], lam,
-                                     len(a["dist"]), dist, a["na"], a["flags"], o.data_ptr())
+                                     len(a["dist"]), dist, a["na"], a["flags"], o.data_ptr(), None)
         assert hpt.STATUS[st] == "HPT_EINVAL", b
 
 
