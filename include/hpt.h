@@ -283,6 +283,25 @@ hpt_status hpt_asm_propagate(hpt_ctx *ctx, const void *d_in, void *d_out, uint32
                              uint32_t width, uint32_t height, double pitch, double lambda,
                              double distance, uint32_t flags, void *hip_stream);
 
+/* The same propagation without any device allocation, for callers that
+ * cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): it allocates nothing, host or device, and
+ * its kernels (those of hpt_asm_propagate) work in a static scratch of
+ * 9437184 complex64 (72 MiB) that each device holds from the library's first
+ * context until the process ends. Limit: 2 height P_x + P_x + P_y <= 9437184
+ * (P_x, P_y: the padded sizes), e.g. one 1920 x 1080 field at a time; larger
+ * fields return EINVAL. hip_stream non-null: the work is enqueued on that
+ * stream and the call returns without waiting (d_out is ready in stream
+ * order); null: it runs on the context's stream and the call returns when
+ * d_out is written. The scratch needs no clearing (the transforms pad in
+ * LDS). All calls on one device share its scratch and keep the last call's
+ * contents: calls that overlap on one device (different streams or threads)
+ * race and must be ordered by the caller. Arguments and other errors as for
+ * hpt_asm_propagate. */
+hpt_status hpt_asm_propagate_noalloc(hpt_ctx *ctx, const void *d_in, void *d_out, uint32_t n_fields,
+                                     uint32_t width, uint32_t height, double pitch, double lambda,
+                                     double distance, uint32_t flags, void *hip_stream);
+
 /* Reconstruction (simulated viewing of the hologram; the paper's focal
  * stacks and time multiplexing, Sec. 5.3, physical configuration): each of the
  * n_ch x T fields is carried to each of n_planes distances by the ASM of

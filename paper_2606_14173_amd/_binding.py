@@ -117,6 +117,8 @@ SIGNATURES = {
     "hpt_encode_phase": (C.c_int, [_vp, _vp, _u32, _u32, _u32, C.c_double, C.c_double, C.c_double, _u32,
                                    C.c_double, _u32, _vp, C.POINTER(C.c_double), _vp]),
     "hpt_debug_fail_batches": (C.c_int, [_vp, _u32]),
+    "hpt_asm_propagate_noalloc": (C.c_int, [_vp, _vp, _vp, _u32, _u32, _u32, C.c_double, C.c_double, C.c_double,
+                                            _u32, _vp]),
 }
 ASM_BAND_LIMIT = 1
 ENCODE_WARM_START = 2

@@ -29,6 +29,9 @@
 // exp(-2 pi i m / n), m < n, per transform length, built once per call in FP64.
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+
 #include "asm.hpp"
 
 namespace hpt {
@@ -485,6 +488,26 @@ void intensity_rows(const float2 *A, float *I, uint32_t nf, uint32_t w, uint32_t
 }
 
 }  // namespace
+
+// Scratch of the allocation-free propagation (hpt_asm_propagate_noalloc):
+// one array per device, held until the process ends. Host code never names
+// it directly (its host-side name is a stand-in, not a device address): the
+// device address comes from asm_noalloc_scratch().
+static __device__ __align__(256) float2 scratch[kNoAllocScratchElems];
+
+hipError_t asm_noalloc_scratch(int device, float2 **ptr) {
+  static std::mutex mu;
+  static std::map<int, float2 *> table;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = table.find(device);
+  if (it != table.end()) { *ptr = it->second; return hipSuccess; }
+  float2 *p = nullptr;
+  hipError_t e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  table[device] = p;
+  *ptr = p;
+  return hipSuccess;
+}
 
 uint32_t asm_padded(uint32_t n) {
   uint32_t p = 1;

@@ -21,6 +21,14 @@ struct AsmParams {
 // Padded length of one axis: the next power of two >= 2 n.
 uint32_t asm_padded(uint32_t n);
 
+// Complex64 elements of the static scratch of the allocation-free
+// propagation (72 MiB: one 1920 x 1080 field, padded to 4096 columns, with
+// its two work buffers and the twiddle tables).
+constexpr size_t kNoAllocScratchElems = 9437184;
+// Device address of that scratch on `device` (which must be current): taken
+// once per device with hipGetSymbolAddress and kept for the process.
+hipError_t asm_noalloc_scratch(int device, float2 **ptr);
+
 // Twiddle tables for fields of w x h: tw[0, Px) for the rows, tw[Px, Px + Py)
 // for the columns (Px, Py: the padded sizes).
 hipError_t launch_asm_twiddles(float2 *tw, uint32_t w, uint32_t h, hipStream_t st);

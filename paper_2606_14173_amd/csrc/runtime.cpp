@@ -189,6 +189,7 @@ struct hpt_ctx {
   } slots[2];
   uint64_t batches = 0, jobs_done = 0;
   uint32_t fail_batches = 0;  // failure injection (hpt_debug_fail_batches)
+  float2 *na_scratch = nullptr;  // this device's static scratch of the allocation-free propagation
   // profiling (guarded by mu; events used by the scheduler thread only)
   uint32_t profile = 0;
   hpt_kernel_time ktime[HPT_K_KINDS] = {};
@@ -795,6 +796,10 @@ hpt_status hpt_create(int device, uint64_t budget, hpt_ctx **out) {
   if (hipSetDevice(device) != hipSuccess) return fail(HPT_ENODEV, "hipSetDevice failed");
   auto C = std::make_unique<hpt_ctx>();
   C->device = device;
+  // device address of the allocation-free propagation's static scratch,
+  // taken once per device with the device current
+  if (hipError_t e = asm_noalloc_scratch(device, &C->na_scratch); e != hipSuccess)
+    return fail(HPT_EDEVICE, std::string("scratch symbol lookup failed: ") + hipGetErrorString(e));
   size_t free_b = 0, total_b = 0;
   (void)hipMemGetInfo(&free_b, &total_b);
   C->budget = budget ? budget : (uint64_t)(0.9 * (double)free_b);
@@ -1531,6 +1536,40 @@ hpt_status hpt_asm_propagate(hpt_ctx *C, const void *d_in, void *d_out, uint32_t
     C->release(B, half);
     C->release(W, tw_bytes);
   }
+  if (e != hipSuccess) return fail(HPT_EDEVICE, std::string("propagation failed: ") + hipGetErrorString(e));
+  return HPT_OK;
+}
+
+hpt_status hpt_asm_propagate_noalloc(hpt_ctx *C, const void *d_in, void *d_out, uint32_t n_fields, uint32_t width,
+                                     uint32_t height, double pitch, double lambda, double distance, uint32_t flags,
+                                     void *hip_stream) {
+  if (!C || !d_in || !d_out) return fail(HPT_EINVAL, "null argument");
+  if (n_fields < 1 || width < 1 || height < 1 || width > 4096 || height > 4096)
+    return fail(HPT_EINVAL, "field size out of range (1..4096 per axis, at least one field)");
+  if (!(pitch > 0) || !std::isfinite(pitch) || !(lambda > 0) || !std::isfinite(lambda) || !std::isfinite(distance))
+    return fail(HPT_EINVAL, "bad pitch, wavelength or distance");
+  if (flags & ~HPT_ASM_BAND_LIMIT) return fail(HPT_EINVAL, "unknown flags");
+  const uint32_t px = asm_padded(width), py = asm_padded(height);
+  auto up = [](size_t n) { return (n + 31) / 32 * 32; };   // 256-byte boundaries
+  const size_t tw = up((size_t)px + py), per = up((size_t)height * px);
+  if (tw + 2 * per > kNoAllocScratchElems)
+    return fail(HPT_EINVAL, "field too large for the static scratch: 2 height P_x + P_x + P_y complex64 must fit "
+                            "9437184 (P: padded sizes)");
+  const uint32_t chunk = (uint32_t)std::min<size_t>({(size_t)n_fields, (kNoAllocScratchElems - tw) / (2 * per),
+                                                     (size_t)kMaxFieldsPerLaunch});
+  const AsmParams P = asm_params(width, height, pitch, lambda, distance, flags, 0.0);
+  // scratch: twiddle tables, then the two work buffers of a chunk of fields
+  float2 *W = C->na_scratch, *A = W + tw, *B = A + (size_t)chunk * height * px;
+  hipStream_t st = hip_stream ? (hipStream_t)hip_stream : C->aux;
+  (void)hipSetDevice(C->device);
+  hipError_t e = launch_asm_twiddles(W, width, height, st);
+  const size_t field = (size_t)width * height;
+  for (uint32_t f0 = 0; f0 < n_fields && e == hipSuccess; f0 += chunk) {
+    const uint32_t nf = std::min(chunk, n_fields - f0);
+    e = launch_asm((const float2 *)d_in + f0 * field, (float2 *)d_out + f0 * field, A, B, W, nf, width, height, P,
+                   st);
+  }
+  if (e == hipSuccess && !hip_stream) e = hipStreamSynchronize(st);
   if (e != hipSuccess) return fail(HPT_EDEVICE, std::string("propagation failed: ") + hipGetErrorString(e));
   return HPT_OK;
 }
