@@ -361,7 +361,7 @@ hpt_status hpt_encode_phase(hpt_ctx *ctx, const void *d_fields, uint32_t n_field
  * summed per kernel kind. Level 2: also counts BVH node visits and primitive
  * tests in the traversal kernel (slower; for work accounting only). */
 enum { HPT_K_RAYGEN = 0, HPT_K_TRACE = 1, HPT_K_SHADE = 2, HPT_K_ACCUMULATE = 3,
-       HPT_K_CACHE_REDUCE = 4, HPT_K_KINDS = 5 };
+       HPT_K_CACHE_REDUCE = 4, HPT_K_COMPACT = 5 /* ray ordering between interactions */, HPT_K_KINDS = 6 };
 typedef struct {
   uint64_t launches;  /* kernel launches timed */
   uint64_t items;     /* rays (trace, shade), paths (raygen), pixel-units (accumulate) */

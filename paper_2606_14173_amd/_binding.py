@@ -73,7 +73,7 @@ class KernelTime(C.Structure):
     _fields_ = [("launches", C.c_uint64), ("items", C.c_uint64), ("total_ms", C.c_double)]
 
 
-KERNEL_KINDS = ("raygen", "trace", "shade", "accumulate", "cache_reduce")
+KERNEL_KINDS = ("raygen", "trace", "shade", "accumulate", "cache_reduce", "compact")
 
 PATH_RECORD = np.dtype([("sig", np.uint64), ("kind", np.int32), ("bP", np.int32),
                         ("first_gid", np.int32), ("n_hits", np.int32),

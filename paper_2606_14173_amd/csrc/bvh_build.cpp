@@ -198,6 +198,34 @@ bool build_bvh(const float *tri, uint32_t n_tri, const float *sph, uint32_t n_sp
     int32_t root = B.build(0, n, 0);
     (void)root;  // the first node emitted is the root (index 0)
   }
+  // Node order: the first kBvhTopNodes nodes in breadth-first order from the
+  // root (the levels every traversal starts with, which the traversal keeps
+  // in LDS), then the rest in depth-first order; links renumbered.
+  {
+    const uint32_t nn = (uint32_t)(B.nodes.size() / 16);
+    std::vector<uint32_t> order, newid(nn, UINT32_MAX);
+    order.reserve(nn);
+    order.push_back(0);
+    newid[0] = 0;
+    for (size_t h = 0; h < order.size() && order.size() < kBvhTopNodes; ++h)
+      for (int k = 0; k < 2 && order.size() < kBvhTopNodes; ++k) {
+        int32_t c;
+        std::memcpy(&c, &B.nodes[16 * (size_t)order[h] + 12 + k], 4);
+        if (c >= 0 && newid[c] == UINT32_MAX) { newid[c] = (uint32_t)order.size(); order.push_back((uint32_t)c); }
+      }
+    for (uint32_t i = 0; i < nn; ++i)
+      if (newid[i] == UINT32_MAX) { newid[i] = (uint32_t)order.size(); order.push_back(i); }
+    std::vector<float> re(B.nodes.size());
+    for (uint32_t j = 0; j < nn; ++j) {
+      std::memcpy(&re[16 * (size_t)j], &B.nodes[16 * (size_t)order[j]], 16 * sizeof(float));
+      for (int k = 0; k < 2; ++k) {
+        int32_t c;
+        std::memcpy(&c, &re[16 * (size_t)j + 12 + k], 4);
+        if (c >= 0) { c = (int32_t)newid[c]; std::memcpy(&re[16 * (size_t)j + 12 + k], &c, 4); }
+      }
+    }
+    B.nodes.swap(re);
+  }
   out.nodes.swap(B.nodes);
   out.prims.assign(12 * (size_t)n, 0.f);
   for (uint32_t i = 0; i < n; ++i) {

@@ -6,6 +6,7 @@
 namespace hpt {
 
 constexpr uint32_t kBvhDepthMax = 64;   // traversal stack entries
+constexpr uint32_t kBvhTopNodes = 256;  // nodes stored first, in breadth-first order from the root
 
 struct BvhResult {
   std::vector<float> nodes;   // 16 floats per node

@@ -243,27 +243,53 @@ __device__ __forceinline__ void trav_init(Trav &T, F3 o, F3 d, float tmin, int32
 // part are rare: they need a path with that many pending far children.
 typedef int32_t __attribute__((address_space(3))) *LdsI32;
 typedef int32_t __attribute__((address_space(1))) *GlbI32;
+typedef const v4f __attribute__((address_space(3))) *LF4;
 
+// `nodes`: the first n_nodes BVH nodes (the top levels, stored first by the
+// builder) copied to LDS by the workgroup, or n_nodes = 0.
 struct Stack {
   LdsI32 lds;
   uint32_t stride;
   GlbI32 spill;
   uint32_t sstride;
+  LF4 nodes;
+  uint32_t n_nodes;
 };
 
+__device__ __forceinline__ void st_store(const Stack &S, int j, int32_t v) {
+  if (j < kStackLds) S.lds[j * S.stride] = v;
+  else S.spill[(size_t)(j - kStackLds) * S.sstride] = v;
+}
+
+__device__ __forceinline__ int32_t st_load(const Stack &S, int j) {
+  return j < kStackLds ? S.lds[j * S.stride] : S.spill[(size_t)(j - kStackLds) * S.sstride];
+}
+
 __device__ __forceinline__ void push(const Stack &S, int &sp, int32_t v) {
-  if (sp < kStackLds) S.lds[sp * S.stride] = v;
-  else S.spill[(size_t)(sp - kStackLds) * S.sstride] = v;
+  st_store(S, sp, v);
   ++sp;
 }
 
 __device__ __forceinline__ int32_t pop(const Stack &S, int &sp) {
   if (sp == 0) return kDone;
   --sp;
-  int32_t v;
-  if (sp < kStackLds) v = S.lds[sp * S.stride];
-  else v = S.spill[(size_t)(sp - kStackLds) * S.sstride];
-  return v;
+  return st_load(S, sp);
+}
+
+__device__ __forceinline__ float4 ld4l(LF4 p) {
+  v4f v = *p;
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
+// The four float4 of BVH node `node`: from LDS for the top levels.
+__device__ __forceinline__ void load_node(const Stack &S, GF4 N, int32_t node, float4 &a, float4 &b, float4 &c,
+                                          float4 &l) {
+  if ((uint32_t)node < S.n_nodes) {
+    a = ld4l(S.nodes + 4 * node); b = ld4l(S.nodes + 4 * node + 1);
+    c = ld4l(S.nodes + 4 * node + 2); l = ld4l(S.nodes + 4 * node + 3);
+  } else {
+    a = ld4(N + 4 * node); b = ld4(N + 4 * node + 1); c = ld4(N + 4 * node + 2); l = ld4(N + 4 * node + 3);
+  }
 }
 
 // Advance this lane by one round: descend inner nodes, postponing the first
@@ -284,8 +310,8 @@ __device__ __forceinline__ void trav_step(Trav &T, GF4 N, GF4 P, const Stack &St
   for (;;) {
     if (node >= 0 && node != kDone) {
       if (COUNT) ++nv;
-      float4 a = ld4(N + 4 * node), b = ld4(N + 4 * node + 1), c = ld4(N + 4 * node + 2),
-             l4 = ld4(N + 4 * node + 3);
+      float4 a, b, c, l4;
+      load_node(St, N, node, a, b, c, l4);
       int32_t c0 = __float_as_int(l4.x), c1 = __float_as_int(l4.y);
       float t0, t1;
       bool h0, h1;

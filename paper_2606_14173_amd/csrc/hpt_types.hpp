@@ -10,8 +10,14 @@ namespace hpt {
 constexpr int kMaxT = 64;
 constexpr int kStackMax = 64;        // BVH depth bound enforced by the builder
 #ifndef HPT_STACK_LDS
-#define HPT_STACK_LDS 16
+#define HPT_STACK_LDS 12
 #endif
+#ifndef HPT_LDS_NODES
+#define HPT_LDS_NODES 224
+#endif
+// top BVH nodes a traversal workgroup keeps in LDS (the builder stores the
+// first levels first; at most its kBvhTopNodes)
+constexpr uint32_t kLdsNodes = HPT_LDS_NODES;
 constexpr int kStackLds = HPT_STACK_LDS;           // traversal stack entries per lane in LDS
 constexpr int kStackSpill = kStackMax - kStackLds;  // further entries per lane in global memory
 #ifndef HPT_TRACE_CHUNK
@@ -145,6 +151,13 @@ struct RayQueue {
   float4 *ray;                     // 2 per entry: (o, tmin), (d, exclude id bits), traversal input
   float *t;                        // hit distance
   int32_t *prim;                   // leaf-order primitive index of the hit, -1: none
+  // A queue filled by shading is compacted per 256-entry chunk of the
+  // source queue (entries [256 c, 256 c + cnt[c]) hold rays); off holds the
+  // exclusive prefix sums of cnt and idx the entries in order (idx[v] = the
+  // entry of ray v), which the next traversal and shading passes read. The
+  // first queue (ray generation) is dense and read without idx.
+  uint32_t *idx, *cnt, *off;
+  uint32_t *tile_sum;              // totals of the counts per tile of 4096 chunks (at most 64)
 };
 
 // What the accumulation reads of a path: one 32-byte record per path slot,

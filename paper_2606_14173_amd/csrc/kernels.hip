@@ -413,7 +413,8 @@ __global__ void __launch_bounds__(kRaygenBlock) k_raygen(BatchDev B) {
 }
 
 // ------------------------------------------------------------------ trace
-// FP32 closest hit for every ray of queue q. The queue is cut into chunks of
+// FP32 closest hit for every ray of queue q (rays in order: entries 0..n-1
+// of the dense first queue, else the entries idx lists). The queue is cut into chunks of
 // kTraceChunk entries; chunk j belongs to class j mod kClaimClasses, and the
 // waves of workgroups with blockIdx mod kClaimClasses = c claim the chunks of
 // class c one at a time from that class's counter (zeroed by the shading pass
@@ -426,8 +427,20 @@ __global__ void __launch_bounds__(kRaygenBlock) k_raygen(BatchDev B) {
 // The traversal stack is kStackLds entries per lane in LDS, then the lane's
 // column of the global spill.
 template <bool COUNT>
-__global__ void __launch_bounds__(kBlock) k_trace(BatchDev B, int q) {
+__global__ void __launch_bounds__(kBlock) k_trace(BatchDev B, int q, int dense) {
   __shared__ int32_t stack[kStackLds * kBlock];
+  __shared__ v4f top_nodes[4 * (kLdsNodes ? kLdsNodes : 1)];
+  // the top levels of the BVH (its first kLdsNodes nodes) in LDS, when every
+  // ray of the batch traverses the same scene
+  const uint32_t n_top = (kLdsNodes && B.scene_uniform) ? min(kLdsNodes, B.scene_uniform->n_nodes) : 0u;
+  if (n_top) {
+    const GF4 src = as_global(B.scene_uniform->nodes);
+    for (uint32_t k = threadIdx.x; k < 4 * n_top; k += blockDim.x) {
+      const float4 v = ld4(src + k);
+      top_nodes[k] = v4f{v.x, v.y, v.z, v.w};
+    }
+    __syncthreads();
+  }
   const uint32_t n = B.counters[q];
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     B.counters[q ^ 1] = 0;
@@ -438,7 +451,8 @@ __global__ void __launch_bounds__(kBlock) k_trace(BatchDev B, int q) {
   const uint32_t n_chunks = (n + kTraceChunk - 1) / kTraceChunk;
   const uint32_t lane = __lane_id();
   const Stack St{(LdsI32)(stack + threadIdx.x), kBlock,
-                 (GlbI32)(B.stack_spill + xcd_block() * blockDim.x + threadIdx.x), B.spill_threads};
+                 (GlbI32)(B.stack_spill + xcd_block() * blockDim.x + threadIdx.x), B.spill_threads,
+                 (LF4)top_nodes, n_top};
   uint32_t nv = 0, nt = 0;
   uint32_t next = 0, end = 0;  // unassigned entries of the wave's chunk
   bool more = true;            // the queue may hold unclaimed entries
@@ -465,6 +479,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(BatchDev B, int q) {
       if (i < 0) {
         uint32_t k = next + (uint32_t)__popcll(need & ((1ull << lane) - 1ull));
         if (k < end) {
+          if (!dense) k = B.Q[q].idx[k];   // the k-th ray of a compacted queue
           i = k;
           if (!B.scene_uniform) {
             S = B.units[B.Q[q].unit[k]].scene;
@@ -914,6 +929,8 @@ __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, 
 // descriptors are read from LDS.
 template <bool FIRST, bool EXT, bool UNI>
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EXT ? 2 : 3))) k_shade(BatchDev B, int q) {
+  // FIRST: queue 0 as ray generation wrote it (dense); else a compacted
+  // queue, read through its index list
   __shared__ StageLds G;
   __shared__ int32_t nee_stack[EXT ? kStackLds * kBlock : 1];
   __shared__ JobDev lds_job[1];
@@ -937,7 +954,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EXT
   const uint32_t cend = EXT ? nb8 : (b % 8u + 1u) * per;
   if (c0 >= cend || c0 * blockDim.x >= n) return;  // no entries for this workgroup
   const Stack St{(LdsI32)(nee_stack + (EXT ? threadIdx.x : 0u)), kBlock,
-                 (GlbI32)(B.stack_spill + blockIdx.x * blockDim.x + threadIdx.x), B.spill_threads};
+                 (GlbI32)(B.stack_spill + blockIdx.x * blockDim.x + threadIdx.x), B.spill_threads, nullptr, 0u};
   if (UNI) {
     const uint32_t t = threadIdx.x;
     const uint32_t *jsrc = (const uint32_t *)B.job_uniform, *ssrc = (const uint32_t *)B.scene_uniform;
@@ -953,11 +970,12 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EXT
     __syncthreads();
   }
   for (uint32_t c = c0; c < cend && c * blockDim.x < n; c += cstep) {
-    const uint32_t i = c * blockDim.x + threadIdx.x;
-    const bool live = i < n;
+    const uint32_t v = c * blockDim.x + threadIdx.x;  // v-th ray of the queue
+    const bool live = v < n;
     Emit e;
     e.on = false;
     if (live) {
+      const uint32_t i = FIRST ? v : B.Q[q].idx[v];
       // the hit record is requested first: it is the longest chain
       // (entry -> primitive -> record); the rest of the state is loaded
       // while it is in flight
@@ -977,8 +995,10 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EXT
       else load_state<EXT>(Qc, i, st);
       shade_one<EXT>(B, q, i, st, G, U, J, S, M, t, hp, H, &St, e);
     }
-    // compaction: wave counts from ballots, one atomic per workgroup (all
-    // workgroups add to the same counter, so fewer atomics is what matters)
+    // compaction within the chunk: the continuing rays of chunk c take
+    // entries [256 c, 256 c + count) of the next queue in lane order (wave
+    // counts from ballots, their prefix in LDS), and the count is recorded
+    // for the scan that orders the chunks; no atomic leaves the workgroup
     unsigned long long m = __ballot(e.on);
     const uint32_t lane = __lane_id(), wv = threadIdx.x / 64u;
     if (lane == 0) wave_cnt[wv] = (uint32_t)__popcll(m);
@@ -986,11 +1006,74 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EXT
     if (threadIdx.x == 0) {
       uint32_t tot = 0;
       for (uint32_t k = 0; k < kBlock / 64; ++k) { wave_base[k] = tot; tot += wave_cnt[k]; }
-      wave_base[kBlock / 64] = tot ? atomicAdd(&B.counters[qo], tot) : 0u;
+      B.Q[qo].cnt[c] = tot;
     }
     __syncthreads();
     const uint32_t before = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-    if (e.on) stage_store<EXT>(G, B.Q[qo], wave_base[kBlock / 64] + wave_base[wv] + before, B.Q[q]);
+    if (e.on) stage_store<EXT>(G, B.Q[qo], c * kBlock + wave_base[wv] + before, B.Q[q]);
+  }
+}
+
+// Ordering of queue qo after the shading pass over the n rays of queue q
+// (ceil(n / 256) chunks with a count each). k_scan: each workgroup takes a
+// tile of kScanTile consecutive chunk counts, writes their exclusive prefix
+// sums within the tile to off and the tile's total to tile_sum. k_index:
+// the entries of chunk c are idx[base(c) + off[c] + k] = 256 c + k, k <
+// cnt[c], with base(c) the sum of the totals of the tiles before c's (at
+// most 64 tiles: one wave adds them); it also records qo's ray count.
+constexpr uint32_t kScanPer = 16, kScanTile = kBlock * kScanPer;
+__global__ void __launch_bounds__(kBlock) k_scan(BatchDev B, int q) {
+  __shared__ uint32_t wsum[kBlock / 64];
+  const int qo = q ^ 1;
+  const uint32_t nc = (B.counters[q] + kBlock - 1) / kBlock;
+  const uint32_t c0 = blockIdx.x * kScanTile + threadIdx.x * kScanPer;
+  if (blockIdx.x * kScanTile >= nc) return;
+  const auto cnt = glb(B.Q[qo].cnt);
+  const auto off = glb(B.Q[qo].off);
+  const uint32_t lane = __lane_id(), wv = threadIdx.x / 64u;
+  uint32_t v[kScanPer], sum = 0;
+#pragma unroll
+  for (uint32_t j = 0; j < kScanPer; ++j) {
+    v[j] = c0 + j < nc ? cnt[c0 + j] : 0u;
+    sum += v[j];
+  }
+  uint32_t inc = sum;  // inclusive scan of the thread sums: in the wave, then over the waves
+  for (uint32_t o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) wsum[wv] = inc;
+  __syncthreads();
+  uint32_t before = inc - sum;
+  for (uint32_t k = 0; k < wv; ++k) before += wsum[k];
+#pragma unroll
+  for (uint32_t j = 0; j < kScanPer; ++j) {
+    if (c0 + j < nc) off[c0 + j] = before;
+    before += v[j];
+  }
+  if (threadIdx.x == kBlock - 1) B.Q[qo].tile_sum[blockIdx.x] = before;
+}
+
+__global__ void __launch_bounds__(kBlock) k_index(BatchDev B, int q) {
+  const int qo = q ^ 1;
+  const uint32_t nc = (B.counters[q] + kBlock - 1) / kBlock;
+  const uint32_t n_tiles = (nc + kScanTile - 1) / kScanTile;
+  const auto cnt = glb(B.Q[qo].cnt);
+  const auto off = glb(B.Q[qo].off);
+  const auto idx = glb(B.Q[qo].idx);
+  const auto ts = glb(B.Q[qo].tile_sum);
+  const uint32_t lane = __lane_id();
+  if (blockIdx.x == 0 && threadIdx.x < 64) {  // the queue's ray count
+    uint32_t t = lane < n_tiles ? ts[lane] : 0u;
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    if (lane == 0) B.counters[qo] = t;
+  }
+  for (uint32_t c = xcd_block(); c < nc; c += gridDim.x) {
+    const uint32_t tile = c / kScanTile;
+    uint32_t base = lane < tile ? ts[lane] : 0u;   // every wave sums the earlier tiles
+    for (int o = 32; o > 0; o >>= 1) base += __shfl_xor(base, o);
+    const uint32_t k = threadIdx.x;
+    if (k < cnt[c]) idx[base + off[c] + k] = c * kBlock + k;
   }
 }
 
@@ -1371,11 +1454,21 @@ uint32_t trace_grid(uint32_t n_paths) {
 
 uint32_t trace_block() { return kBlock; }
 
-hipError_t launch_trace(const BatchDev &B, int q, bool count, hipStream_t st) {
+hipError_t launch_trace(const BatchDev &B, int q, bool dense, bool count, hipStream_t st) {
   uint32_t g = trace_grid(B.n_paths);
   if ((uint64_t)g * kBlock > B.spill_threads) return hipErrorInvalidValue;
-  if (count) hipLaunchKernelGGL(k_trace<true>, dim3(g), dim3(kBlock), 0, st, B, q);
-  else hipLaunchKernelGGL(k_trace<false>, dim3(g), dim3(kBlock), 0, st, B, q);
+  if (count) hipLaunchKernelGGL(k_trace<true>, dim3(g), dim3(kBlock), 0, st, B, q, dense ? 1 : 0);
+  else hipLaunchKernelGGL(k_trace<false>, dim3(g), dim3(kBlock), 0, st, B, q, dense ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(const BatchDev &B, int q, hipStream_t st) {
+  const uint32_t max_chunks = (B.n_paths + kBlock - 1) / kBlock;
+  const uint32_t tiles = (max_chunks + kScanTile - 1) / kScanTile;
+  if (tiles > 64) return hipErrorInvalidValue;   // k_index sums the tile totals with one wave
+  hipLaunchKernelGGL(k_scan, dim3(tiles), dim3(kBlock), 0, st, B, q);
+  const uint32_t g = min(round8((B.n_paths + kBlock - 1) / kBlock), 4096u);
+  hipLaunchKernelGGL(k_index, dim3(g), dim3(kBlock), 0, st, B, q);
   return hipGetLastError();
 }
 

@@ -11,7 +11,12 @@ hipError_t launch_raygen(const BatchDev &B, bool uni, hipStream_t st);
 // One interaction for every ray in queue q: closest hit (trace), then
 // shading that compacts continuing rays into queue q^1 (shade).
 // Fails (hipErrorInvalidValue) if the batch's stack spill is too small.
-hipError_t launch_trace(const BatchDev &B, int q, bool count, hipStream_t st);
+// dense: queue q is the first queue (ray generation order), else it is read
+// through its index list.
+hipError_t launch_trace(const BatchDev &B, int q, bool dense, bool count, hipStream_t st);
+// After the shading pass over queue q: prefix sums of the per-chunk counts
+// of queue q^1, its ray count and its index list.
+hipError_t launch_compact(const BatchDev &B, int q, hipStream_t st);
 // Workgroups and threads per workgroup of a traversal launch for a batch of
 // n_paths (they size the stack spill).
 uint32_t trace_grid(uint32_t n_paths);

@@ -51,8 +51,8 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
 constexpr uint32_t kMaxUnitsPerBatch = 4096;
 // per path, in two sets: final signature, first hit, results; per queue
 // entry (two queues): state (40 B), FP64 prefix ray (72 B), FP32 ray (32 B),
-// hit (8 B)
-constexpr size_t kBytesPerPath = 2 * (8 + 4 + 32 + 16) + 2 * (44 + 72 + 32 + 8);
+// hit (8 B), index list (4 B; chunk counts and offsets: 8 B per 256 entries)
+constexpr size_t kBytesPerPath = 2 * (8 + 4 + 32 + 16) + 2 * (44 + 72 + 32 + 8 + 4 + 1);
 
 struct Scene {
   uint64_t id = 0;
@@ -163,7 +163,7 @@ struct hpt_ctx {
   uint64_t batch_bytes = 0;   // device bytes of batch_bufs
   BatchDev batch{};
   hipStream_t acc = nullptr;  // accumulation stream
-  static constexpr int kEvents = 80;
+  static constexpr int kEvents = 200;   // 2 per timed launch: ray generation, 3 per interaction, accumulation
   struct Slot {
     unsigned long long *s_sig = nullptr;
     int32_t *s_first = nullptr;
@@ -525,8 +525,11 @@ hpt_status launch_batch(hpt_ctx *C, int si, int prev) {
                    B.n_units <= shade_lds_units();
   for (uint32_t it = 0; it <= max_b; ++it) {
     int q = (int)(it & 1u);
-    timed_launch(L, HPT_K_TRACE, S, e, [&] { return launch_trace(B, q, profile >= 2, S); });
+    timed_launch(L, HPT_K_TRACE, S, e, [&] { return launch_trace(B, q, it == 0, profile >= 2, S); });
     timed_launch(L, HPT_K_SHADE, S, e, [&] { return launch_shade(B, q, it == 0, L.has_ext, uni, S); });
+    // the last pass ends every path (interaction max_b + 1 exceeds the
+    // budget), so only the earlier ones leave rays to order
+    if (it < max_b) timed_launch(L, HPT_K_COMPACT, S, e, [&] { return launch_compact(B, q, S); });
   }
   if (e == hipSuccess) e = hipMemcpyAsync(L.h_cnt, B.counters, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, S);
   if (e == hipSuccess && profile >= 2)
@@ -565,6 +568,7 @@ hpt_status finish_batch(hpt_ctx *C, int si, double &gpu_ms, uint64_t &rays, hpt_
   kt[HPT_K_SHADE].items += L.profile ? nr : 0;
   kt[HPT_K_ACCUMULATE].items += (L.profile && L.has_holo) ? L.paths : 0;
   kt[HPT_K_CACHE_REDUCE].items += (L.profile && L.has_cache) ? L.paths : 0;
+  kt[HPT_K_COMPACT].items += L.profile ? nr : 0;
   gpu_ms = ms;
   rays = nr;
   return HPT_OK;
@@ -741,6 +745,8 @@ hpt_status alloc_batch(hpt_ctx *C) {
           A((void **)&Q.dx, 8ull * N) && A((void **)&Q.dy, 8ull * N) && A((void **)&Q.dz, 8ull * N) &&
           A((void **)&Q.ell, 8ull * N) && A((void **)&Q.al, 8ull * N) && A((void **)&Q.be, 8ull * N);
     ok &= A((void **)&Q.ray, 32ull * N) && A((void **)&Q.t, 4ull * N) && A((void **)&Q.prim, 4ull * N);
+    ok &= A((void **)&Q.idx, 4ull * N) && A((void **)&Q.cnt, 4ull * (N / 256 + 1)) &&
+          A((void **)&Q.off, 4ull * (N / 256 + 1)) && A((void **)&Q.tile_sum, 4ull * 64);
   }
   ok &= A((void **)&B.counters, 64);
   ok &= A((void **)&B.claims, 2 * kClaimClasses * kClaimStride * sizeof(uint32_t));
