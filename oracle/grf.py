@@ -5,6 +5,13 @@ sampled on the periodic grid of pitch d; phi_t = arg r_t. The spectral phases
 xi_t come from the oracle's counter-based generator; the inverse transform is
 numpy's FFT (a library step). Values are scaled by 1/sqrt(#passband bins) so
 that E|r|^2 = 1; the scale does not change the phase.
+
+The tables are stored as complex64: the FP64 inverse transform, each value
+rounded once to complex64 (the precision a table is held in). Sec. 4.3
+takes phi_t as the argument of r_t at the image point, which is
+ill-conditioned near the zeros of r_t (an error e in r moves the phase by
+about e / |r|), so the lookup must interpolate the same stored values on
+both sides; it then works in FP64 on them.
 """
 import numpy as np
 
@@ -20,12 +27,16 @@ def grf_phases(gw, gh, t0, nt, seed):
     return xi, mask.astype(bool)
 
 
-def grf_table(gw, gh, T, seed):
-    """Complex table [gh, gw, T] (complex128): frame t at texel (i, j)."""
+def grf_table(gw, gh, T, seed, stored=True):
+    """Complex table [gh, gw, T] (complex128 array): frame t at texel (i, j);
+    stored=True: the values as stored (rounded to complex64), False: the
+    FP64 transform itself."""
     out = np.empty((gh, gw, T), dtype=np.complex128)
     for t in range(T):
         xi, mask = grf_phases(gw, gh, t, 1, seed)
         scale = (gw * gh) / np.sqrt(int(mask[0].sum()))
         spec = np.where(mask[0], np.exp(1j * xi[0]), 0.0)
         out[:, :, t] = np.fft.ifft2(spec) * scale
+    if stored:
+        out = out.astype(np.complex64).astype(np.complex128)
     return out

@@ -165,10 +165,10 @@ struct RayQueue {
 // the scattered writes of a shading pass touch one cache line per path.
 struct alignas(32) PathRes {
   uint32_t tex;   // random-field texel of the image point: i0 | j0 << 16
-  float fx, fy;   // position of the image point in the texel
   float amp;      // hologram path: amplitude weight A W / spp; cache path: radiance (0: none)
   float2 cs;      // unit phasor exp(i k r) (FP32 and split phase)
-  float pad[2];
+  double fx, fy;  // position of the image point in the texel (FP64: the lookup's
+                  // phase is ill-conditioned near zeros of the random field)
 };
 static_assert(sizeof(PathRes) == 32, "PathRes is one 32-byte record");
 

@@ -673,8 +673,8 @@ __device__ __forceinline__ void image_point(const BatchDev &B, const RayQueue &Q
   if (j0 < 0) j0 += J.grf_h;
   PathRes &res = B.res[slot];
   res.tex = (uint32_t)i0 | ((uint32_t)j0 << 16);
-  res.fx = (float)(u - fu);
-  res.fy = (float)(v - fv);
+  res.fx = u - fu;
+  res.fy = v - fv;
   // unit phasor exp(i k r) of the path (the same for all T frames), in the
   // precision the accumulation of this mode sums in
   if (J.phase_mode == HPT_PHASE_FP64) {
@@ -1110,6 +1110,7 @@ __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
   unsigned long long sigsum = 0;
   const bool dbg_c = (J.debug & 2u) != 0, dbg_s = (J.debug & 4u) != 0 && t == 0;
   const bool rp = J.random_phase != 0;
+  const bool f32_lookup = J.phase_mode == HPT_PHASE_FP32;  // the FP32 comparison mode looks up in FP32
   const uint32_t n = U.s_n, slot0 = U.slot_base + p_local * n;
   // Paths are taken kAccBatch at a time: the records of all of them are
   // requested, then the table corners of all of them, before the first is
@@ -1117,7 +1118,8 @@ __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
   // round trips per path. The sum still runs in sample order.
   for (uint32_t k0 = 0; k0 < n; k0 += kAccBatch) {
     uint32_t tex[kAccBatch];
-    float amp[kAccBatch], fx[kAccBatch], fy[kAccBatch];
+    float amp[kAccBatch];
+    double fx[kAccBatch], fy[kAccBatch];
     R csr[kAccBatch], csi[kAccBatch];
     float2 qa[kAccBatch], qb[kAccBatch], qc[kAccBatch], qd[kAccBatch];
 #pragma unroll
@@ -1134,8 +1136,8 @@ __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
         csr[u] = (R)pr.cs.x; csi[u] = (R)pr.cs.y;
       }
       tex[u] = rp ? pr.tex : 0u;
-      fx[u] = rp ? pr.fx : 0.f;
-      fy[u] = rp ? pr.fy : 0.f;
+      fx[u] = rp ? pr.fx : 0.0;
+      fy[u] = rp ? pr.fy : 0.0;
     }
 #pragma unroll
     for (uint32_t u = 0; u < kAccBatch; ++u) {
@@ -1159,8 +1161,20 @@ __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
         } else {
           br = (R)(amp[u] * csr[u]); bi = (R)(amp[u] * csi[u]);
         }
-        if (rp) {
-          const float x = fx[u], y = fy[u];
+        if (rp && !f32_lookup) {
+          // the stored table interpolated in FP64: the phase of the result
+          // is exact where |z| is small (an error e moves it by e / |z|);
+          // the normalisation only scales the phasor, in FP32
+          const double x = fx[u], y = fy[u];
+          const double w00 = (1.0 - x) * (1.0 - y), w10 = x * (1.0 - y), w01 = (1.0 - x) * y, w11 = x * y;
+          const double zr = w00 * qa[u].x + w10 * qb[u].x + w01 * qc[u].x + w11 * qd[u].x;
+          const double zi = w00 * qa[u].y + w10 * qb[u].y + w01 * qc[u].y + w11 * qd[u].y;
+          const double m2 = zr * zr + zi * zi;
+          const double inv = m2 > 0.0 ? (double)rsqrtf((float)m2) : 0.0;
+          const R pr = m2 > 0.0 ? (R)(zr * inv) : (R)1, pi = (R)(zi * inv);
+          cr = br * pr - bi * pi; ci = br * pi + bi * pr;
+        } else if (rp) {
+          const float x = (float)fx[u], y = (float)fy[u];
           const float w00 = (1.f - x) * (1.f - y), w10 = x * (1.f - y), w01 = (1.f - x) * y, w11 = x * y;
           const float zr = w00 * qa[u].x + w10 * qb[u].x + w01 * qc[u].x + w11 * qd[u].x;
           const float zi = w00 * qa[u].y + w10 * qb[u].y + w01 * qc[u].y + w11 * qd[u].y;
@@ -1229,8 +1243,8 @@ __device__ bool segment_blocked(const SceneDev &S, F3 o, F3 d, float tmax, int32
 }
 
 // Unit phasor of frame t at hologram-space (qx, qy): bilinear interpolation
-// of the random field (texel (i, j) on pixel centre (i, j), periodic), then
-// normalised (1 where it vanishes); the same arithmetic as the accumulation.
+// of the random field (texel (i, j) on pixel centre (i, j), periodic) in
+// FP64, then normalised (1 where it vanishes), as the accumulation does.
 __device__ __forceinline__ float2 grf_unit(const JobDev &J, uint32_t t, double qx, double qy) {
   const double u = qx / J.pitch + 0.5 * (double)J.width - 0.5;
   const double v = qy / J.pitch + 0.5 * (double)J.height - 0.5;
@@ -1243,14 +1257,14 @@ __device__ __forceinline__ float2 grf_unit(const JobDev &J, uint32_t t, double q
   const size_t gw = J.grf_w, T = J.T;
   const float2 qa = G2[((size_t)j0 * gw + i0) * T], qb = G2[((size_t)j0 * gw + i1) * T],
                qc = G2[((size_t)j1 * gw + i0) * T], qd = G2[((size_t)j1 * gw + i1) * T];
-  const float x = (float)(u - fu), y = (float)(v - fv);
-  const float w00 = (1.f - x) * (1.f - y), w10 = x * (1.f - y), w01 = (1.f - x) * y, w11 = x * y;
-  const float zr = w00 * qa.x + w10 * qb.x + w01 * qc.x + w11 * qd.x;
-  const float zi = w00 * qa.y + w10 * qb.y + w01 * qc.y + w11 * qd.y;
-  const float m2 = zr * zr + zi * zi;
-  if (!(m2 > 0.f)) return make_float2(1.f, 0.f);
-  const float inv = rsqrtf(m2);
-  return make_float2(zr * inv, zi * inv);
+  const double x = u - fu, y = v - fv;
+  const double w00 = (1.0 - x) * (1.0 - y), w10 = x * (1.0 - y), w01 = (1.0 - x) * y, w11 = x * y;
+  const double zr = w00 * qa.x + w10 * qb.x + w01 * qc.x + w11 * qd.x;
+  const double zi = w00 * qa.y + w10 * qb.y + w01 * qc.y + w11 * qd.y;
+  const double m2 = zr * zr + zi * zi;
+  if (!(m2 > 0.0)) return make_float2(1.f, 0.f);
+  const double inv = (double)rsqrtf((float)m2);
+  return make_float2((float)(zr * inv), (float)(zi * inv));
 }
 
 // Point emitters: pixel p of a unit that starts at sample 0 receives, for

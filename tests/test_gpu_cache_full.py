@@ -80,6 +80,28 @@ def test_large_scene_crop_with_cache(ctx, large):
     assert r["phase"][2] <= 1e-3
 
 
+def test_full_job_crop_per_path_records(ctx, large):
+    """The benchmark's job (1920x1080 RGB, 256 spp, 6 bounces, T = 24, split
+    phase, cache 64^3 x 8x8) on its centred 64x64 crop with per-path records
+    (3.1M paths): >= 99.9 % of the paths have identical hit/lobe signatures
+    and radiance-cache entries, their phase error is <= 1e-3 rad, and the
+    field of every pixel whose paths all match is within 1e-4 of the RMS."""
+    job = jobs.job_for_config(2, crop=(928, 508, 64, 64))
+    Ug, recg = ctx.trace(large["sid"], job, records=True)
+    Uo, reco, _ = oracle.trace(large["os"], job, grf=large["grf"], cache=large["oc"], records=True)
+    match = (recg["sig"] == reco["sig"]) & cache_agree(recg, reco, job["comps"], large["gcache"], large["oc"])
+    img = match & (reco["amp"] != 0)
+    dphi = np.abs(np.angle(np.exp(2j * np.pi * (recg["rev"][img] - reco["rev"][img]))))
+    pix = match.all(axis=-1)
+    rms = float(np.sqrt(np.mean(np.abs(Uo) ** 2)))
+    err = float(np.abs(Ug - Uo).max(axis=1)[pix].max() / rms)
+    _say("full job 64x64 crop: paths %d, identical %.6f, pixels all matched %.4f, phase max %.1e, err/rms %.2e"
+         % (match.size, match.mean(), pix.mean(), dphi.max(), err))
+    assert match.mean() >= 0.999
+    assert dphi.max() <= 1e-3
+    assert err <= 1e-4
+
+
 def test_full_size_sampled_pixels(ctx, large):
     """The benchmark's job (1920x1080, RGB, 256 spp, T=24, split phase, cache),
     with per-pixel signature sums; 24 sampled pixels recomputed by the oracle."""

@@ -73,6 +73,21 @@ def test_mid_scene_rgb_crop(ctx):
     assert r["ok"]
 
 
+def test_config1_full_spp_crop(ctx):
+    """The 512x512 RGB workload at its stated sample count: ~58k triangles,
+    mixed materials, 64 spp, 4 bounces, T = 8, split phase, on the centred
+    128x128 crop (3.1M paths), against the oracle."""
+    sc = scenes.scene_mid(1)
+    job = jobs.job_for_config(1, crop=(192, 192, 128, 128))
+    assert job["spp"] == 64 and job["T"] == 8 and job["max_bounces"] == 4
+    sid = ctx.upload_scene(sc)
+    r = compare(*gpu_run(ctx, sid, job), *oracle_run(sc, job))
+    ctx.release_scene(sid)
+    _say("config1 128x128 64spp", r)
+    assert r["ok"]
+    assert r["phase"][2] <= 1e-3
+
+
 def test_many_materials_read_from_global_memory(ctx):
     """A scene with more materials than shading keeps in LDS (64) is shaded
     from its descriptors in global memory: the mid scene with its floor

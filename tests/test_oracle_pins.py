@@ -468,7 +468,9 @@ def test_grf_brute_force_dft(oracle_lib):
     """Eq. 4 written as an explicit sum over passband frequencies on a small
     grid equals the table (which uses an FFT)."""
     gw, gh, T, seed = 12, 10, 2, 9
-    tab = oracle.grf_table(gw, gh, T, seed)
+    tab = oracle.grf_table(gw, gh, T, seed, stored=False)
+    # the stored table is that transform rounded once to complex64
+    assert np.array_equal(oracle.grf_table(gw, gh, T, seed), tab.astype(np.complex64).astype(np.complex128))
     xi, mask = oracle.grf_phases(gw, gh, 0, T, seed)
     d = 1.0
     fx = np.fft.fftfreq(gw, d)
@@ -498,10 +500,14 @@ def test_grf_statistics(oracle_lib):
     from scipy import stats
     gw, gh, T = 96, 64, 3
     tab = oracle.grf_table(gw, gh, T, 11)
+    exact = oracle.grf_table(gw, gh, T, 11, stored=False)
     _, mask = oracle.grf_phases(gw, gh, 0, 1, 11)
     for t in range(T):
-        spec = np.fft.fft2(tab[:, :, t])
+        spec = np.fft.fft2(exact[:, :, t])
         assert np.abs(spec[~mask[0]]).max() < 1e-9 * np.abs(spec).max()
+        # the stored (complex64) table leaks only its rounding out of the band
+        spec = np.fft.fft2(tab[:, :, t])
+        assert np.abs(spec[~mask[0]]).max() < 1e-6 * np.abs(spec).max()
         ph = np.angle(tab[:, :, t]).ravel()
         assert stats.kstest((ph + np.pi) / (2 * np.pi), "uniform").pvalue > 1e-4
     n = gw * gh
