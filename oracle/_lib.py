@@ -40,9 +40,11 @@ class ORecord(C.Structure):
 def lib():
     global _LIB
     if _LIB is None:
-        path = _build.LIB
-        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
-            _build.build()
+        path = os.environ.get("HPT_ORACLE_LIB")   # a sanitizer build of the same source (tests only)
+        if not path:
+            path = _build.LIB
+            if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+                _build.build()
         L = C.CDLL(path)
         vp, i32, u64, dbl = C.c_void_p, C.c_int32, C.c_uint64, C.c_double
         L.oracle_scene_create.restype = vp
