@@ -24,8 +24,14 @@ constexpr int kStackSpill = kStackMax - kStackLds;  // further entries per lane 
 #define HPT_TRACE_CHUNK 64
 #endif
 constexpr int kTraceChunk = HPT_TRACE_CHUNK;  // queue entries a traversal wave claims at a time
-constexpr uint32_t kTraceGridMax = 2048;      // traversal workgroups per launch (8 per CU)
-constexpr int kTraceStragglers = 24;          // lanes a wave's descent stops waiting for
+#ifndef HPT_TRACE_GRID
+#define HPT_TRACE_GRID 2048
+#endif
+#ifndef HPT_STRAGGLERS
+#define HPT_STRAGGLERS 24
+#endif
+constexpr uint32_t kTraceGridMax = HPT_TRACE_GRID;  // traversal workgroups per launch (8 per CU)
+constexpr int kTraceStragglers = HPT_STRAGGLERS;    // lanes a wave's descent stops waiting for
 #ifndef HPT_CLAIM_CLASSES
 #define HPT_CLAIM_CLASSES 8
 #endif
@@ -39,8 +45,8 @@ constexpr double kTminD = 1e-7;
 enum Stage : uint32_t { STAGE_PREFIX = 0, STAGE_TAIL = 1 };
 enum UnitKind : uint32_t { UNIT_HOLO = 0, UNIT_CACHE = 1 };
 
-// Lanes per pixel in the accumulation: one per frame.
-__host__ __device__ inline uint32_t frame_group(uint32_t T) { return T; }
+// Lanes per pixel in the accumulation: one per two frames.
+__host__ __device__ inline uint32_t frame_group(uint32_t T) { return (T + 1) / 2; }
 
 // Path events hashed into the signature (same codes as the FP64 reference).
 enum : uint32_t { EV_MIRROR = 1, EV_DIEL_REFL = 2, EV_DIEL_REFR = 3, EV_LAMBERT = 4, EV_GGX = 5,

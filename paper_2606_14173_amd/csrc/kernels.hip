@@ -1078,14 +1078,46 @@ __global__ void __launch_bounds__(kBlock) k_index(BatchDev B, int q) {
 }
 
 // ------------------------------------------------------------------ accumulate
-// s8-s9 and Path Reuse. A group of T consecutive lanes owns one pixel of a
-// unit; lane t of the group owns frame t. The group walks the unit's samples
-// in order; for each path it forms A W exp(i k r) / spp from the amplitude and
-// the phasor the shading stored (the same value in every lane) and lane t
-// multiplies it by the unit phasor of frame t at Q, so the T frames of a
-// texel are read by consecutive lanes from consecutive addresses. Partial
-// sums are added to the field at the end.
+// s8-s9 and Path Reuse. A group of ceil(T/2) consecutive lanes owns one
+// pixel of a unit; lane t of the group owns frames 2t and 2t + 1 (the second
+// when T > 2t + 1). The group walks the unit's samples in order; for each
+// path it forms A W exp(i k r) / spp from the amplitude and the phasor the
+// shading stored (the same value in every lane) and multiplies it by the
+// unit phasors of its two frames at Q. The T frames of a texel are
+// contiguous, so a lane reads its two frames of a table corner with one
+// 16-byte load (two 8-byte loads when T is odd, where the pairs are not
+// 16-byte aligned): what the gathers cost is their number of load
+// instructions, not their bytes. Partial sums are added to the field at the
+// end.
 constexpr uint32_t kAccBatch = 4;  // paths whose loads are in flight together
+
+// Unit phasor of the bilinear interpolation of four table values (corners
+// (i0, j0), (i1, j0), (i0, j1), (i1, j1)) at offsets (x, y): in FP64 on the
+// stored values (the phase is ill-conditioned where the interpolated value
+// is small), normalised in FP32 (which only scales it); FP32 throughout in
+// the FP32 comparison mode. 1 where the value vanishes.
+template <class R>
+__device__ __forceinline__ void corner_phasor(bool f32_lookup, double x, double y, float ar, float ai, float br,
+                                              float bi, float cr, float ci, float dr, float di, R &pr, R &pi) {
+  if (!f32_lookup) {
+    const double w00 = (1.0 - x) * (1.0 - y), w10 = x * (1.0 - y), w01 = (1.0 - x) * y, w11 = x * y;
+    const double zr = w00 * ar + w10 * br + w01 * cr + w11 * dr;
+    const double zi = w00 * ai + w10 * bi + w01 * ci + w11 * di;
+    const double m2 = zr * zr + zi * zi;
+    const double inv = m2 > 0.0 ? (double)rsqrtf((float)m2) : 0.0;
+    pr = m2 > 0.0 ? (R)(zr * inv) : (R)1;
+    pi = (R)(zi * inv);
+  } else {
+    const float xf = (float)x, yf = (float)y;
+    const float w00 = (1.f - xf) * (1.f - yf), w10 = xf * (1.f - yf), w01 = (1.f - xf) * yf, w11 = xf * yf;
+    const float zr = w00 * ar + w10 * br + w01 * cr + w11 * dr;
+    const float zi = w00 * ai + w10 * bi + w01 * ci + w11 * di;
+    const float m2 = zr * zr + zi * zi;
+    const float inv = m2 > 0.f ? rsqrtf(m2) : 0.f;
+    pr = m2 > 0.f ? (R)(zr * inv) : (R)1;
+    pi = (R)(zi * inv);
+  }
+}
 
 template <bool F64>
 __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
@@ -1097,21 +1129,33 @@ __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
   const JobDev &J = *U.job;
   if (F64 != (J.phase_mode == HPT_PHASE_FP64)) return;
   const uint32_t T = J.T, G = frame_group(T);
-  uint32_t local = idx - U.acc_base;
-  uint32_t p_local = local / G, t = local - p_local * G;
-  if (t >= T) return;
+  const uint32_t local = idx - U.acc_base;
+  const uint32_t p_local = local / G, t = local - p_local * G;
+  const uint32_t f0 = 2 * t;                 // this lane's frames: f0 and, if two, f0 + 1
+  const bool two = f0 + 1 < T;
+  const bool pairs = (T & 1u) == 0;          // every (texel, f0) pair is 16-byte aligned
   uint32_t cx, cy;
   crop_xy(J, U.p_lo + p_local, cx, cy);
   using R = typename std::conditional<F64, double, float>::type;
   const uint32_t gw = J.grf_w, gh = J.grf_h;
-  const auto G2 = glb(J.grf) + t;
+  const auto G2 = glb(J.grf);
+  const auto G4 = glb(reinterpret_cast<const float4 *>(J.grf));
   const size_t plane = (size_t)J.crop_h * J.crop_w;
-  R ar = 0, ai = 0;
+  R ar0 = 0, ai0 = 0, ar1 = 0, ai1 = 0;
   unsigned long long sigsum = 0;
   const bool dbg_c = (J.debug & 2u) != 0, dbg_s = (J.debug & 4u) != 0 && t == 0;
   const bool rp = J.random_phase != 0;
   const bool f32_lookup = J.phase_mode == HPT_PHASE_FP32;  // the FP32 comparison mode looks up in FP32
   const uint32_t n = U.s_n, slot0 = U.slot_base + p_local * n;
+  // frames f0, f0 + 1 of texel (i, j): one 16-byte load, or two 8-byte ones
+  auto corner = [&](uint32_t i, uint32_t j) -> float4 {
+    const size_t e = (size_t)j * gw + i;
+    if (pairs) return G4[(e * T + f0) >> 1];
+    const float2 a = G2[e * T + f0];
+    float2 b = make_float2(0.f, 0.f);
+    if (two) b = G2[e * T + f0 + 1];
+    return make_float4(a.x, a.y, b.x, b.y);
+  };
   // Paths are taken kAccBatch at a time: the records of all of them are
   // requested, then the table corners of all of them, before the first is
   // used, so a wave has several gathers in flight instead of two dependent
@@ -1121,7 +1165,7 @@ __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
     float amp[kAccBatch];
     double fx[kAccBatch], fy[kAccBatch];
     R csr[kAccBatch], csi[kAccBatch];
-    float2 qa[kAccBatch], qb[kAccBatch], qc[kAccBatch], qd[kAccBatch];
+    float4 qa[kAccBatch], qb[kAccBatch], qc[kAccBatch], qd[kAccBatch];
 #pragma unroll
     for (uint32_t u = 0; u < kAccBatch; ++u) {
       const bool v = k0 + u < n;
@@ -1144,8 +1188,8 @@ __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
       if (rp && amp[u] != 0.f) {  // the texel is written only for paths with an image point
         const uint32_t i0 = tex[u] & 0xFFFFu, j0 = tex[u] >> 16;
         const uint32_t i1 = i0 + 1 == gw ? 0 : i0 + 1, j1 = j0 + 1 == gh ? 0 : j0 + 1;
-        qa[u] = G2[((size_t)j0 * gw + i0) * T]; qb[u] = G2[((size_t)j0 * gw + i1) * T];
-        qc[u] = G2[((size_t)j1 * gw + i0) * T]; qd[u] = G2[((size_t)j1 * gw + i1) * T];
+        qa[u] = corner(i0, j0); qb[u] = corner(i1, j0);
+        qc[u] = corner(i0, j1); qd[u] = corner(i1, j1);
       }
     }
 #pragma unroll
@@ -1153,7 +1197,7 @@ __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
       const uint32_t s = k0 + u;
       if (s >= n) break;
       if (dbg_s) sigsum += B.s_sig[slot0 + s];
-      R cr = 0, ci = 0;
+      R c0r = 0, c0i = 0, c1r = 0, c1i = 0;
       if (amp[u] != 0.f) {
         R br, bi;
         if (F64) {
@@ -1161,39 +1205,39 @@ __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
         } else {
           br = (R)(amp[u] * csr[u]); bi = (R)(amp[u] * csi[u]);
         }
-        if (rp && !f32_lookup) {
-          // the stored table interpolated in FP64: the phase of the result
-          // is exact where |z| is small (an error e moves it by e / |z|);
-          // the normalisation only scales the phasor, in FP32
-          const double x = fx[u], y = fy[u];
-          const double w00 = (1.0 - x) * (1.0 - y), w10 = x * (1.0 - y), w01 = (1.0 - x) * y, w11 = x * y;
-          const double zr = w00 * qa[u].x + w10 * qb[u].x + w01 * qc[u].x + w11 * qd[u].x;
-          const double zi = w00 * qa[u].y + w10 * qb[u].y + w01 * qc[u].y + w11 * qd[u].y;
-          const double m2 = zr * zr + zi * zi;
-          const double inv = m2 > 0.0 ? (double)rsqrtf((float)m2) : 0.0;
-          const R pr = m2 > 0.0 ? (R)(zr * inv) : (R)1, pi = (R)(zi * inv);
-          cr = br * pr - bi * pi; ci = br * pi + bi * pr;
-        } else if (rp) {
-          const float x = (float)fx[u], y = (float)fy[u];
-          const float w00 = (1.f - x) * (1.f - y), w10 = x * (1.f - y), w01 = (1.f - x) * y, w11 = x * y;
-          const float zr = w00 * qa[u].x + w10 * qb[u].x + w01 * qc[u].x + w11 * qd[u].x;
-          const float zi = w00 * qa[u].y + w10 * qb[u].y + w01 * qc[u].y + w11 * qd[u].y;
-          const float m2 = zr * zr + zi * zi;
-          const float inv = m2 > 0.f ? rsqrtf(m2) : 0.f;
-          const R pr = m2 > 0.f ? (R)(zr * inv) : (R)1, pi = (R)(zi * inv);
-          cr = br * pr - bi * pi; ci = br * pi + bi * pr;
+        if (rp) {
+          R pr, pi;
+          corner_phasor<R>(f32_lookup, fx[u], fy[u], qa[u].x, qa[u].y, qb[u].x, qb[u].y, qc[u].x, qc[u].y,
+                           qd[u].x, qd[u].y, pr, pi);
+          c0r = br * pr - bi * pi; c0i = br * pi + bi * pr;
+          if (two) {
+            corner_phasor<R>(f32_lookup, fx[u], fy[u], qa[u].z, qa[u].w, qb[u].z, qb[u].w, qc[u].z, qc[u].w,
+                             qd[u].z, qd[u].w, pr, pi);
+            c1r = br * pr - bi * pi; c1i = br * pi + bi * pr;
+          }
         } else {
-          cr = br; ci = bi;
+          c0r = br; c0i = bi;
+          c1r = br; c1i = bi;
         }
-        ar += cr; ai += ci;
+        ar0 += c0r; ai0 += c0i;
+        ar1 += c1r; ai1 += c1i;
       }
-      if (dbg_c) J.contrib[rec_index(J, U, p_local, s) * T + t] = make_float2((float)cr, (float)ci);
+      if (dbg_c) {
+        const size_t ci = rec_index(J, U, p_local, s) * T + f0;
+        J.contrib[ci] = make_float2((float)c0r, (float)c0i);
+        if (two) J.contrib[ci + 1] = make_float2((float)c1r, (float)c1i);
+      }
     }
   }
-  const auto F = glb(J.field) + ((size_t)U.ch * T + t) * plane + (size_t)cy * J.crop_w + cx;
-  float2 v = *F;
-  v.x += (float)ar; v.y += (float)ai;
-  *F = v;
+  const auto F = glb(J.field) + ((size_t)U.ch * T + f0) * plane + (size_t)cy * J.crop_w + cx;
+  float2 v = F[0];
+  v.x += (float)ar0; v.y += (float)ai0;
+  F[0] = v;
+  if (two) {
+    v = F[plane];
+    v.x += (float)ar1; v.y += (float)ai1;
+    F[plane] = v;
+  }
   if (dbg_s) J.sigsum[(size_t)U.ch * plane + (size_t)cy * J.crop_w + cx] += sigsum;
 }
 
