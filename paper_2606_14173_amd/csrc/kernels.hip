@@ -1091,25 +1091,44 @@ __global__ void __launch_bounds__(kBlock) k_index(BatchDev B, int q) {
 // end.
 constexpr uint32_t kAccBatch = 4;  // paths whose loads are in flight together
 
-// Unit phasor of the bilinear interpolation of four table values (corners
-// (i0, j0), (i1, j0), (i0, j1), (i1, j1)) at offsets (x, y): in FP64 on the
+// Bilinear weights of the corners (i0, j0), (i1, j0), (i0, j1), (i1, j1) at
+// offsets (x, y).
+struct BiW { double w00, w10, w01, w11; };
+
+__device__ __forceinline__ BiW bilinear_weights(double x, double y) {
+  return {(1.0 - x) * (1.0 - y), x * (1.0 - y), (1.0 - x) * y, x * y};
+}
+
+// 1 / sqrt(m2) for m2 > 0 from the hardware FP32 reciprocal square root
+// (1 ulp; the result only scales the phasor, whose argument comes from the
+// FP64 sums). Below the normal FP32 range m2 is first scaled by an even
+// power of two into [0.5, 2).
+__device__ __forceinline__ double inv_norm(double m2) {
+  double inv = (double)__builtin_amdgcn_rsqf((float)m2);
+  if (m2 < 1e-37 && m2 > 0.0) {  // rare: below the normal FP32 range
+    const int h = ilogb(m2) / 2;  // m2 = m' 2^(2h), m' in [0.5, 4)
+    inv = (double)__builtin_amdgcn_rsqf((float)ldexp(m2, -2 * h)) * ldexp(1.0, -h);
+  }
+  return inv;
+}
+
+// Unit phasor of the interpolated table value at weights W: in FP64 on the
 // stored values (the phase is ill-conditioned where the interpolated value
-// is small), normalised in FP32 (which only scales it); FP32 throughout in
-// the FP32 comparison mode. 1 where the value vanishes.
+// is small), normalised through FP32 (which only scales it); FP32
+// throughout in the FP32 comparison mode. 1 where the value vanishes.
 template <class R>
-__device__ __forceinline__ void corner_phasor(bool f32_lookup, double x, double y, float ar, float ai, float br,
+__device__ __forceinline__ void corner_phasor(bool f32_lookup, const BiW &W, float ar, float ai, float br,
                                               float bi, float cr, float ci, float dr, float di, R &pr, R &pi) {
   if (!f32_lookup) {
-    const double w00 = (1.0 - x) * (1.0 - y), w10 = x * (1.0 - y), w01 = (1.0 - x) * y, w11 = x * y;
-    const double zr = w00 * ar + w10 * br + w01 * cr + w11 * dr;
-    const double zi = w00 * ai + w10 * bi + w01 * ci + w11 * di;
+    const double zr = W.w00 * ar + W.w10 * br + W.w01 * cr + W.w11 * dr;
+    const double zi = W.w00 * ai + W.w10 * bi + W.w01 * ci + W.w11 * di;
     const double m2 = zr * zr + zi * zi;
-    const double inv = m2 > 0.0 ? (double)rsqrtf((float)m2) : 0.0;
-    pr = m2 > 0.0 ? (R)(zr * inv) : (R)1;
-    pi = (R)(zi * inv);
+    const double inv = inv_norm(m2);  // inf for m2 = 0, not used then
+    const bool nz = m2 > 0.0;
+    pr = nz ? (R)(zr * inv) : (R)1;
+    pi = nz ? (R)(zi * inv) : (R)0;
   } else {
-    const float xf = (float)x, yf = (float)y;
-    const float w00 = (1.f - xf) * (1.f - yf), w10 = xf * (1.f - yf), w01 = (1.f - xf) * yf, w11 = xf * yf;
+    const float w00 = (float)W.w00, w10 = (float)W.w10, w01 = (float)W.w01, w11 = (float)W.w11;
     const float zr = w00 * ar + w10 * br + w01 * cr + w11 * dr;
     const float zi = w00 * ai + w10 * bi + w01 * ci + w11 * di;
     const float m2 = zr * zr + zi * zi;
@@ -1147,15 +1166,16 @@ __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
   const bool rp = J.random_phase != 0;
   const bool f32_lookup = J.phase_mode == HPT_PHASE_FP32;  // the FP32 comparison mode looks up in FP32
   const uint32_t n = U.s_n, slot0 = U.slot_base + p_local * n;
-  // frames f0, f0 + 1 of texel (i, j): one 16-byte load, or two 8-byte ones
-  auto corner = [&](uint32_t i, uint32_t j) -> float4 {
-    const size_t e = (size_t)j * gw + i;
-    if (pairs) return G4[(e * T + f0) >> 1];
-    const float2 a = G2[e * T + f0];
+  // frames f0, f0 + 1 at table element e (texel x T + f0, below 2^30 for
+  // grids up to 4096^2 and T <= 64): one 16-byte load, or two 8-byte ones
+  auto corner = [&](uint32_t e) -> float4 {
+    if (pairs) return G4[e >> 1];
+    const float2 a = G2[e];
     float2 b = make_float2(0.f, 0.f);
-    if (two) b = G2[e * T + f0 + 1];
+    if (two) b = G2[e + 1];
     return make_float4(a.x, a.y, b.x, b.y);
   };
+  const uint32_t rowT = gw * T;  // elements per table row
   // Paths are taken kAccBatch at a time: the records of all of them are
   // requested, then the table corners of all of them, before the first is
   // used, so a wave has several gathers in flight instead of two dependent
@@ -1186,10 +1206,15 @@ __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
 #pragma unroll
     for (uint32_t u = 0; u < kAccBatch; ++u) {
       if (rp && amp[u] != 0.f) {  // the texel is written only for paths with an image point
+        // corners (i0, j0), (i0 + 1, j0), (i0, j0 + 1), (i0 + 1, j0 + 1),
+        // the +1 wrapping to 0 on the periodic grid: 32-bit element offsets,
+        // the steps to the next column and row as (modular) differences
         const uint32_t i0 = tex[u] & 0xFFFFu, j0 = tex[u] >> 16;
-        const uint32_t i1 = i0 + 1 == gw ? 0 : i0 + 1, j1 = j0 + 1 == gh ? 0 : j0 + 1;
-        qa[u] = corner(i0, j0); qb[u] = corner(i1, j0);
-        qc[u] = corner(i0, j1); qd[u] = corner(i1, j1);
+        const uint32_t e00 = j0 * rowT + i0 * T + f0;
+        const uint32_t di = i0 + 1 == gw ? 0u - i0 * T : T;
+        const uint32_t dj = j0 + 1 == gh ? 0u - j0 * rowT : rowT;
+        qa[u] = corner(e00); qb[u] = corner(e00 + di);
+        qc[u] = corner(e00 + dj); qd[u] = corner(e00 + di + dj);
       }
     }
 #pragma unroll
@@ -1207,11 +1232,12 @@ __global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
         }
         if (rp) {
           R pr, pi;
-          corner_phasor<R>(f32_lookup, fx[u], fy[u], qa[u].x, qa[u].y, qb[u].x, qb[u].y, qc[u].x, qc[u].y,
+          const BiW W = bilinear_weights(fx[u], fy[u]);
+          corner_phasor<R>(f32_lookup, W, qa[u].x, qa[u].y, qb[u].x, qb[u].y, qc[u].x, qc[u].y,
                            qd[u].x, qd[u].y, pr, pi);
           c0r = br * pr - bi * pi; c0i = br * pi + bi * pr;
           if (two) {
-            corner_phasor<R>(f32_lookup, fx[u], fy[u], qa[u].z, qa[u].w, qb[u].z, qb[u].w, qc[u].z, qc[u].w,
+            corner_phasor<R>(f32_lookup, W, qa[u].z, qa[u].w, qb[u].z, qb[u].w, qc[u].z, qc[u].w,
                              qd[u].z, qd[u].w, pr, pi);
             c1r = br * pr - bi * pi; c1i = br * pi + bi * pr;
           }
