@@ -365,10 +365,14 @@ __global__ void __launch_bounds__(kRaygenBlock) k_raygen(BatchDev B) {
     key[r] = 0;
     rank[r] = 0;
     if (w < nv) {
-      B.s_first[i] = -1;
-      B.res[i] = PathRes{};  // whole records: coalesced writes
+      // the result record needs no clearing: every path ends in finish(),
+      // which writes its amplitude, and the rest of the record is read only
+      // where the amplitude is non-zero; the first-hit word only feeds the
+      // per-path records of a debug job
       const uint32_t u = find_unit(Us, B.n_units, i, false);
-      key[r] = sort_key(Us[u], UNI ? lds_job[0] : *Us[u].job, u, i);
+      const JobDev &Jr = UNI ? lds_job[0] : *Us[u].job;
+      if (Jr.debug & 1u) B.s_first[i] = -1;
+      key[r] = sort_key(Us[u], Jr, u, i);
       rank[r] = atomicAdd(&hist[key[r]], 1u);
     }
   }
