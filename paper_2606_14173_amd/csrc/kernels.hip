@@ -1337,7 +1337,7 @@ __device__ __forceinline__ float2 grf_unit(const JobDev &J, uint32_t t, double q
   const double zi = w00 * qa.y + w10 * qb.y + w01 * qc.y + w11 * qd.y;
   const double m2 = zr * zr + zi * zi;
   if (!(m2 > 0.0)) return make_float2(1.f, 0.f);
-  const double inv = (double)rsqrtf((float)m2);
+  const double inv = inv_norm(m2);  // also where m2 is below the FP32 range
   return make_float2((float)(zr * inv), (float)(zi * inv));
 }
 
