@@ -5,9 +5,13 @@
 //   k_raygen        s1-s2: cone directions from Philox, world-space rays
 //   k_trace/k_shade  s3-s5, once per interaction: FP32 closest hit, then the
 //                   coherent delta prefix (FP64 or split OPL), the image
-//                   point (s6-s7) and the incoherent radiance tail; live rays
-//                   are compacted into the next queue with one atomic per wave
+//                   point (s6-s7) and the incoherent radiance tail; shading
+//                   compacts the live rays of each 256-entry chunk into the
+//                   next queue (ballots, no atomics)
+//   k_scan/k_index  order the chunks of the next queue (prefix sums of the
+//                   chunk counts, then the index list the next pass reads)
 //   k_accumulate    s8-s9: Eq. 5 for all T frames of every path (Path Reuse)
+//   k_points        exact terms of point emitters, after the accumulation
 // Random-phase tables (Eq. 4) are built by k_grf_* once per grid/T/seed.
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
