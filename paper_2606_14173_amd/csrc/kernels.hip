@@ -1147,9 +1147,9 @@ __device__ __forceinline__ void corner_phasor(bool f32_lookup, const BiW &W, flo
 }
 
 template <bool F64>
-__global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B) {
-  uint32_t idx = xcd_block() * blockDim.x + threadIdx.x;
-  if (idx >= B.n_acc) return;
+__global__ void __launch_bounds__(kBlock) k_accumulate(BatchDev B, uint32_t lane0, uint32_t lane_end) {
+  uint32_t idx = lane0 + xcd_block() * blockDim.x + threadIdx.x;
+  if (idx >= lane_end) return;
   uint32_t u = find_unit(B.units, B.n_units, idx, true);
   const UnitDev U = B.units[u];
   if (U.kind != UNIT_HOLO) return;
@@ -1579,10 +1579,12 @@ hipError_t launch_shade(const BatchDev &B, int q, bool first, bool ext, bool uni
 }
 
 // One launch per precision present in the batch.
-hipError_t launch_accumulate(const BatchDev &B, bool has_f64, bool has_f32, hipStream_t st) {
-  uint32_t g = round8(grid_for(B.n_acc));
-  if (has_f32) hipLaunchKernelGGL(k_accumulate<false>, dim3(g), dim3(kBlock), 0, st, B);
-  if (has_f64) hipLaunchKernelGGL(k_accumulate<true>, dim3(g), dim3(kBlock), 0, st, B);
+hipError_t launch_accumulate(const BatchDev &B, bool has_f64, bool has_f32, uint32_t lane0, uint32_t lane_end,
+                             hipStream_t st) {
+  if (lane_end <= lane0) return hipSuccess;
+  uint32_t g = round8(grid_for(lane_end - lane0));
+  if (has_f32) hipLaunchKernelGGL(k_accumulate<false>, dim3(g), dim3(kBlock), 0, st, B, lane0, lane_end);
+  if (has_f64) hipLaunchKernelGGL(k_accumulate<true>, dim3(g), dim3(kBlock), 0, st, B, lane0, lane_end);
   return hipGetLastError();
 }
 

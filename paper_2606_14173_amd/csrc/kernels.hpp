@@ -27,7 +27,9 @@ uint32_t trace_block();
 hipError_t launch_shade(const BatchDev &B, int q, bool first, bool ext, bool uni, hipStream_t st);
 uint32_t shade_lds_mats();
 uint32_t shade_lds_units();
-hipError_t launch_accumulate(const BatchDev &B, bool has_f64, bool has_f32, hipStream_t st);
+// accumulation lanes [lane0, lane_end) of the batch
+hipError_t launch_accumulate(const BatchDev &B, bool has_f64, bool has_f32, uint32_t lane0, uint32_t lane_end,
+                             hipStream_t st);
 hipError_t launch_cache_reduce(const BatchDev &B, hipStream_t st);
 // Point-emitter terms of the batch's hologram units that start at sample 0
 // (added to the field; run after the batch's accumulation, on its stream).

@@ -52,6 +52,12 @@ constexpr uint32_t kMaxUnitsPerBatch = 4096;
 // per path, in two sets: final signature, first hit, results; per queue
 // entry (two queues): state (40 B), FP64 prefix ray (72 B), FP32 ray (32 B),
 // hit (8 B), index list (4 B; chunk counts and offsets: 8 B per 256 entries)
+#ifndef HPT_ACC_PARTS
+#define HPT_ACC_PARTS 3
+#endif
+constexpr uint32_t kAccParts = HPT_ACC_PARTS;  // accumulation launches per batch
+static_assert(kAccParts >= 1 && kAccParts <= 4, "part k starts beside the next batch's traversal k + 1");
+
 constexpr size_t kBytesPerPath = 2 * (8 + 4 + 32 + 16) + 2 * (44 + 72 + 32 + 8 + 4 + 1);
 
 struct Scene {
@@ -175,7 +181,9 @@ struct hpt_ctx {
     hipEvent_t ev0 = nullptr, ev_rg = nullptr, ev_shade = nullptr, ev_done = nullptr;
     BatchDev B{};               // the batch's device view (for its accumulation)
     bool has_f64 = false, has_f32 = false, has_ext = false;
-    bool acc_pending = false;   // accumulation not enqueued yet
+    bool acc_pending = false;   // accumulation not (fully) enqueued yet
+    uint32_t acc_parts = 0;     // parts of it enqueued
+    hipEvent_t ev_sh[4] = {};   // after the batch's first shading passes
     hipEvent_t pev[kEvents] = {};
     int ne = 0;
     int seg_kind[kEvents / 2] = {};
@@ -440,19 +448,27 @@ void timed_launch(hpt_ctx::Slot &L, int kind, hipStream_t st, hipError_t &e, F &
   }
 }
 
-// Enqueue the accumulation (or cache reduction) of slot si on the
-// accumulation stream, after the batch's last shading pass and after the
-// event `after` (the next batch's ray generation, so that the memory-bound
-// accumulation runs beside the ALU-bound tracing rather than beside the
-// memory-bound ray generation).
-hipError_t launch_accumulation(hpt_ctx *C, int si, hipEvent_t after) {
+// Enqueue parts [L.acc_parts, part_end) of the accumulation (or cache
+// reduction) of slot si on the accumulation stream, after the batch's last
+// shading pass and after the event `after`. The accumulation is cut into
+// kAccParts ranges of its lanes (each lane's sums are its own), which the
+// next batch starts beside its first kAccParts traversal launches, so that
+// the gather-heavy accumulation runs beside the ALU-bound tracing rather
+// than beside the memory-bound ray generation or the latency-bound shading.
+hipError_t launch_accumulation(hpt_ctx *C, int si, hipEvent_t after, uint32_t part_end) {
   hpt_ctx::Slot &L = C->slots[si];
-  L.acc_pending = false;
   hipError_t e = hipStreamWaitEvent(C->acc, L.ev_shade, 0);
   if (e == hipSuccess && after) e = hipStreamWaitEvent(C->acc, after, 0);
   const BatchDev &B = L.B;
-  if (L.has_holo)
-    timed_launch(L, HPT_K_ACCUMULATE, C->acc, e, [&] { return launch_accumulate(B, L.has_f64, L.has_f32, C->acc); });
+  for (; e == hipSuccess && L.acc_parts < part_end; ++L.acc_parts) {
+    const uint32_t lo = (uint32_t)((uint64_t)B.n_acc * L.acc_parts / kAccParts);
+    const uint32_t hi = (uint32_t)((uint64_t)B.n_acc * (L.acc_parts + 1) / kAccParts);
+    if (L.has_holo)
+      timed_launch(L, HPT_K_ACCUMULATE, C->acc, e,
+                   [&] { return launch_accumulate(B, L.has_f64, L.has_f32, lo, hi, C->acc); });
+  }
+  if (L.acc_parts < kAccParts) return e;
+  L.acc_pending = false;
   // point-emitter terms: on the same stream after the accumulation, so that
   // every read-modify-write of a pixel's field is ordered
   if (e == hipSuccess && L.pts_max_pn) e = launch_points(B, L.pts_max_pn, C->acc);
@@ -519,7 +535,7 @@ hpt_status launch_batch(hpt_ctx *C, int si, int prev) {
   timed_launch(L, HPT_K_RAYGEN, S, e,
                [&] { return launch_raygen(B, B.job_uniform && B.n_units <= shade_lds_units(), S); });
   if (e == hipSuccess) e = hipEventRecord(L.ev_rg, S);
-  if (e == hipSuccess && prev >= 0 && C->slots[prev].acc_pending) e = launch_accumulation(C, prev, L.ev_rg);
+  if (e == hipSuccess && prev >= 0 && C->slots[prev].acc_pending) e = launch_accumulation(C, prev, L.ev_rg, 1);
   // shading copies the descriptors of a one-job batch to LDS when they fit
   const bool uni = B.job_uniform && B.scene_uniform && P[0].job->scene->host.n_mat <= shade_lds_mats() &&
                    B.n_units <= shade_lds_units();
@@ -530,12 +546,20 @@ hpt_status launch_batch(hpt_ctx *C, int si, int prev) {
     // the last pass ends every path (interaction max_b + 1 exceeds the
     // budget), so only the earlier ones leave rays to order
     if (it < max_b) timed_launch(L, HPT_K_COMPACT, S, e, [&] { return launch_compact(B, q, S); });
+    // part it + 1 of the previous batch's accumulation starts beside this
+    // batch's next traversal (all that is left after the last such pass)
+    if (it + 1 < kAccParts && e == hipSuccess && prev >= 0 && C->slots[prev].acc_pending) {
+      e = hipEventRecord(L.ev_sh[it], S);
+      const uint32_t end = (it + 2 == kAccParts || it == max_b) ? kAccParts : it + 2;
+      if (e == hipSuccess) e = launch_accumulation(C, prev, L.ev_sh[it], end);
+    }
   }
   if (e == hipSuccess) e = hipMemcpyAsync(L.h_cnt, B.counters, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, S);
   if (e == hipSuccess && profile >= 2)
     e = hipMemcpyAsync(L.h_work, B.work, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, S);
   if (e == hipSuccess) e = hipEventRecord(L.ev_shade, S);
   L.acc_pending = e == hipSuccess;
+  L.acc_parts = 0;
   if (e != hipSuccess) {
     (void)hipStreamSynchronize(S);
     (void)hipStreamSynchronize(C->acc);
@@ -549,7 +573,7 @@ hpt_status finish_batch(hpt_ctx *C, int si, double &gpu_ms, uint64_t &rays, hpt_
                         uint64_t *work) {
   hpt_ctx::Slot &L = C->slots[si];
   if (L.launch_status != HPT_OK) return L.launch_status;
-  hipError_t e = L.acc_pending ? launch_accumulation(C, si, nullptr) : hipSuccess;
+  hipError_t e = L.acc_pending ? launch_accumulation(C, si, nullptr, kAccParts) : hipSuccess;
   if (e == hipSuccess) e = hipEventSynchronize(L.ev_done);
   float ms = 0.f;
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, L.ev0, L.ev_done);
@@ -761,7 +785,11 @@ hpt_status alloc_batch(hpt_ctx *C) {
         hipHostMalloc((void **)&L.h_work, 2 * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess)
       return fail(HPT_ENOMEM, "pinned batch table allocation failed");
     if (hipEventCreate(&L.ev0) != hipSuccess || hipEventCreate(&L.ev_rg) != hipSuccess ||
-        hipEventCreate(&L.ev_shade) != hipSuccess || hipEventCreate(&L.ev_done) != hipSuccess)
+        hipEventCreate(&L.ev_shade) != hipSuccess || hipEventCreate(&L.ev_done) != hipSuccess ||
+        hipEventCreateWithFlags(&L.ev_sh[0], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&L.ev_sh[1], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&L.ev_sh[2], hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&L.ev_sh[3], hipEventDisableTiming) != hipSuccess)
       return fail(HPT_EDEVICE, "event creation failed");
     for (auto &ev : L.pev)
       if (hipEventCreate(&ev) != hipSuccess) return fail(HPT_EDEVICE, "event creation failed");
@@ -858,7 +886,7 @@ void hpt_destroy(hpt_ctx *C) {
     if (L.h_units) (void)hipHostFree(L.h_units);
     if (L.h_cnt) (void)hipHostFree(L.h_cnt);
     if (L.h_work) (void)hipHostFree(L.h_work);
-    for (hipEvent_t ev : {L.ev0, L.ev_rg, L.ev_shade, L.ev_done})
+    for (hipEvent_t ev : {L.ev0, L.ev_rg, L.ev_shade, L.ev_done, L.ev_sh[0], L.ev_sh[1], L.ev_sh[2], L.ev_sh[3]})
       if (ev) (void)hipEventDestroy(ev);
     for (hipEvent_t ev : L.pev)
       if (ev) (void)hipEventDestroy(ev);
