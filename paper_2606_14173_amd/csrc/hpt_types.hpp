@@ -153,7 +153,7 @@ struct RayQueue {
   float *wt;                       // medium index in the prefix, then the weight W
   float *beta, *L;                 // tail throughput and radiance
   float *pdf;                      // lobe pdf of the ray if next-event estimation covers it (MIS), else 0
-  double *ox, *oy, *oz, *dx, *dy, *dz, *ell, *al, *be;
+  double *ox, *oy, *oz, *dx, *dy, *dz, *ell;  // FP64 ray and optical path length of the coherent prefix
   float4 *ray;                     // 2 per entry: (o, tmin), (d, exclude id bits), traversal input
   float *t;                        // hit distance
   int32_t *prim;                   // leaf-order primitive index of the hit, -1: none

@@ -109,7 +109,6 @@ __device__ __forceinline__ uint32_t morton_key(float u, float v) {
 // source entry, are read where they are used, and are copied to the ray's
 // next entry when the path continues.
 struct RayState {
-  uint32_t i;                // entry in the source queue
   uint32_t slot, unit, meta;
   uint32_t ka, kb;           // Philox key words of the path
   unsigned long long sig;
@@ -121,7 +120,6 @@ struct RayState {
 
 template <bool EXT>
 __device__ __forceinline__ void load_state(const RayQueue &Q, uint32_t i, RayState &r) {
-  r.i = i;
   r.slot = Q.slot[i]; r.meta = Q.meta[i];
   r.ka = Q.ka[i]; r.kb = Q.kb[i];
   r.sig = Q.sig[i];
@@ -134,15 +132,36 @@ __device__ __forceinline__ void load_state(const RayQueue &Q, uint32_t i, RaySta
   }
 }
 
+// s1: cone direction cosines (al, be) of a hologram path with Philox key
+// words (gpix, smp): uniform on the disc of radius lambda/(2d), from the
+// path's first two uniforms (FP32 phase draws them in FP32). A function of
+// the key words, so the passes that need the direction recompute it rather
+// than carrying it in the queues.
+__device__ __forceinline__ void cone_cosines(const UnitDev &U, const JobDev &J, uint32_t gpix, uint32_t smp,
+                                             double &al, double &be) {
+  const uint32_t comp = J.comp[U.ch];
+  const U4 w = philox(gpix, smp, 0u, comp << 16, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
+  if (J.phase_mode != HPT_PHASE_FP32) {
+    const double rad = J.s_cone[U.ch] * sqrt(ud(w.x));
+    double sn, cs;
+    sincospi(2.0 * ud(w.y), &sn, &cs);
+    al = rad * cs; be = rad * sn;
+  } else {
+    const float rad = J.s_cone_f[U.ch] * sqrtf(uf(w.x));
+    float sn, cs;
+    sincospif(2.0f * uf(w.y), &sn, &cs);
+    al = rad * cs; be = rad * sn;
+  }
+}
+
 // Entry k of the first queue: what the first shading pass cannot rebuild
-// (slot, unit, key words, cone direction) and the FP32 ray. The start state
-// (signature, throughputs, medium, stage) is the same for every path and the
-// FP64 primary ray is a function of the pixel and the cone direction, so the
-// first shading pass rebuilds both (load_first) instead of reading them.
+// (slot, unit, key words) and the FP32 ray. The start state (signature,
+// throughputs, medium, stage) is the same for every path and the FP64
+// primary ray is a function of the pixel and the key words, so the first
+// shading pass rebuilds both (load_first) instead of reading them.
 __device__ __forceinline__ void store_first(const RayQueue &Q, uint32_t k, const RayState &r, uint32_t ka,
-                                            uint32_t kb, double al, double be, F3 o, F3 d) {
+                                            uint32_t kb, F3 o, F3 d) {
   Q.slot[k] = r.slot; Q.unit[k] = r.unit; Q.ka[k] = ka; Q.kb[k] = kb;
-  if ((r.meta & 1u) == STAGE_PREFIX) { Q.al[k] = al; Q.be[k] = be; }
   Q.ray[2 * k] = make_float4(o.x, o.y, o.z, kTmin);
   Q.ray[2 * k + 1] = make_float4(d.x, d.y, d.z, __int_as_float(-1));
 }
@@ -245,11 +264,10 @@ __device__ __forceinline__ void gen_cache_path(const UnitDev &U, const JobDev &J
 // s1-s2 for path slot i (or a cache path) of unit u of the batch: its
 // state, read-only key words, FP32 ray and direction-sort key.
 __device__ __forceinline__ void gen_path(const UnitDev &U, const JobDev &J, uint32_t u, uint32_t i,
-                                         RayState &st, uint32_t &ska, uint32_t &skb, double &sal, double &sbe,
-                                         F3 &ro, F3 &rd, uint32_t &key) {
+                                         RayState &st, uint32_t &ska, uint32_t &skb, F3 &ro, F3 &rd,
+                                         uint32_t &key) {
   uint32_t p_local, s_local;
   slot_decode(U, i, p_local, s_local);
-  st.i = i;
   st.slot = i;
   st.unit = u;
   st.sig = kSigInit;
@@ -266,23 +284,10 @@ __device__ __forceinline__ void gen_path(const UnitDev &U, const JobDev &J, uint
     uint32_t gpix = py * J.width + px, smp = U.s_lo + s_local;
     ska = gpix;
     skb = smp;
-    U4 w = philox(gpix, smp, 0u, comp << 16, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
     double al, be;
-    if (J.phase_mode != HPT_PHASE_FP32) {
-      // s1: direction cosines uniform on the disc of radius lambda/(2d)
-      double rad = J.s_cone[U.ch] * sqrt(ud(w.x));
-      double sn, cs;
-      sincospi(2.0 * ud(w.y), &sn, &cs);
-      al = rad * cs; be = rad * sn;
-    } else {
-      float rad = J.s_cone_f[U.ch] * sqrtf(uf(w.x));
-      float sn, cs;
-      sincospif(2.0f * uf(w.y), &sn, &cs);
-      al = rad * cs; be = rad * sn;
-    }
+    cone_cosines(U, J, gpix, smp, al, be);
     D3 O, d;
     primary_ray(J, px, py, al, be, O, d);
-    sal = al; sbe = be;
     st.o = O; st.d = d;
     st.ell = 0.0;
     st.meta = STAGE_PREFIX;
@@ -297,18 +302,16 @@ __device__ __forceinline__ void gen_path(const UnitDev &U, const JobDev &J, uint
 
 
 // State of entry i of the first queue, as gen_path made it (store_first).
-// The cone direction is read for every entry (a cache path's entry holds
-// stale words there, unused), so that all loads are in flight together.
 __device__ __forceinline__ void load_first(const RayQueue &Q, uint32_t i, RayState &r, const UnitDev &U,
                                            const JobDev &J) {
-  r.i = i;
   r.slot = Q.slot[i];
   r.ka = Q.ka[i]; r.kb = Q.kb[i];
-  const double al = Q.al[i], be = Q.be[i];
   r.sig = kSigInit;
   r.bpre = 1.f; r.wt = 1.f; r.beta = 1.f; r.L = 0.f; r.pdf = 0.f;
   if (U.kind == UNIT_HOLO) {
     r.meta = STAGE_PREFIX;
+    double al, be;
+    cone_cosines(U, J, r.ka, r.kb, al, be);
     primary_ray(J, r.ka % J.width, r.ka / J.width, al, be, r.o, r.d);
     r.ell = 0.0;
   } else {
@@ -413,10 +416,9 @@ __global__ void __launch_bounds__(kRaygenBlock) k_raygen(BatchDev B) {
     const uint32_t u = find_unit(Us, B.n_units, k, false);
     RayState st;
     uint32_t ska = 0, skb = 0, kk;
-    double sal = 0.0, sbe = 0.0;
     F3 ro, rd;
-    gen_path(Us[u], UNI ? lds_job[0] : *Us[u].job, u, k, st, ska, skb, sal, sbe, ro, rd, kk);
-    store_first(B.Q[0], g0 + w, st, ska, skb, sal, sbe, ro, rd);
+    gen_path(Us[u], UNI ? lds_job[0] : *Us[u].job, u, k, st, ska, skb, ro, rd, kk);
+    store_first(B.Q[0], g0 + w, st, ska, skb, ro, rd);
   }
 }
 
@@ -532,7 +534,7 @@ struct Emit { bool on; };
 // finalises them until the compaction has given them their entry in the next
 // queue; this keeps the new state out of registers for the rest of the pass.
 struct StageLds {
-  uint32_t i[kBlock], slot[kBlock], unit[kBlock], meta[kBlock], ka[kBlock], kb[kBlock];
+  uint32_t slot[kBlock], unit[kBlock], meta[kBlock], ka[kBlock], kb[kBlock];
   unsigned long long sig[kBlock];
   float bpre[kBlock], wt[kBlock], beta[kBlock], L[kBlock], pdf[kBlock];
   double ox[kBlock], oy[kBlock], oz[kBlock], dx[kBlock], dy[kBlock], dz[kBlock], ell[kBlock];
@@ -542,7 +544,7 @@ struct StageLds {
 
 __device__ __forceinline__ void stage_put(StageLds &G, const RayState &r, F3 o, F3 d, int32_t excl, Emit &e) {
   const uint32_t t = threadIdx.x;
-  G.i[t] = r.i; G.slot[t] = r.slot; G.unit[t] = r.unit; G.meta[t] = r.meta;
+  G.slot[t] = r.slot; G.unit[t] = r.unit; G.meta[t] = r.meta;
   G.ka[t] = r.ka; G.kb[t] = r.kb;
   G.sig[t] = r.sig;
   G.bpre[t] = r.bpre; G.wt[t] = r.wt; G.beta[t] = r.beta; G.L[t] = r.L; G.pdf[t] = r.pdf;
@@ -557,11 +559,10 @@ __device__ __forceinline__ void stage_put(StageLds &G, const RayState &r, F3 o, 
   e.on = true;
 }
 
-// Entry k of queue Q from this lane's staged ray; the direction cosines come
-// from its entry in the source queue S.
+// Entry k of queue Q from this lane's staged ray.
 template <bool EXT>
-__device__ __forceinline__ void stage_store(const StageLds &G, const RayQueue &Q, uint32_t k, const RayQueue &S) {
-  const uint32_t t = threadIdx.x, i = G.i[t], meta = G.meta[t];
+__device__ __forceinline__ void stage_store(const StageLds &G, const RayQueue &Q, uint32_t k) {
+  const uint32_t t = threadIdx.x, meta = G.meta[t];
   Q.slot[k] = G.slot[t]; Q.unit[k] = G.unit[t]; Q.meta[k] = meta;
   Q.ka[k] = G.ka[t]; Q.kb[k] = G.kb[t];
   Q.sig[k] = G.sig[t];
@@ -570,7 +571,7 @@ __device__ __forceinline__ void stage_store(const StageLds &G, const RayQueue &Q
   if ((meta & 1u) == STAGE_PREFIX) {
     Q.ox[k] = G.ox[t]; Q.oy[k] = G.oy[t]; Q.oz[k] = G.oz[t];
     Q.dx[k] = G.dx[t]; Q.dy[k] = G.dy[t]; Q.dz[k] = G.dz[t];
-    Q.ell[k] = G.ell[t]; Q.al[k] = S.al[i]; Q.be[k] = S.be[i];
+    Q.ell[k] = G.ell[t];
   }
   Q.ray[2 * k] = make_float4(G.rox[t], G.roy[t], G.roz[t], kTmin);
   Q.ray[2 * k + 1] = make_float4(G.rdx[t], G.rdy[t], G.rdz[t], __int_as_float(G.excl[t]));
@@ -613,7 +614,8 @@ __device__ __forceinline__ void image_point(const BatchDev &B, const RayQueue &Q
   const uint32_t slot = st.slot;
   uint32_t gpix = st.ka;
   uint32_t px = gpix % J.width, py = gpix / J.width;
-  double al = Q.al[st.i], be = Q.be[st.i];
+  double al, be;
+  cone_cosines(U, J, st.ka, st.kb, al, be);
   double s = J.s_cone[U.ch];
   double r, qx, qy, u, v, rev;
   float W;
@@ -1018,7 +1020,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EXT
     }
     __syncthreads();
     const uint32_t before = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-    if (e.on) stage_store<EXT>(G, B.Q[qo], c * kBlock + wave_base[wv] + before, B.Q[q]);
+    if (e.on) stage_store<EXT>(G, B.Q[qo], c * kBlock + wave_base[wv] + before);
   }
 }
 

@@ -50,7 +50,7 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
 
 constexpr uint32_t kMaxUnitsPerBatch = 4096;
 // per path, in two sets: final signature, first hit, results; per queue
-// entry (two queues): state (40 B), FP64 prefix ray (72 B), FP32 ray (32 B),
+// entry (two queues): state (44 B), FP64 prefix ray (56 B), FP32 ray (32 B),
 // hit (8 B), index list (4 B; chunk counts and offsets: 8 B per 256 entries)
 #ifndef HPT_ACC_PARTS
 #define HPT_ACC_PARTS 3
@@ -58,7 +58,7 @@ constexpr uint32_t kMaxUnitsPerBatch = 4096;
 constexpr uint32_t kAccParts = HPT_ACC_PARTS;  // accumulation launches per batch
 static_assert(kAccParts >= 1 && kAccParts <= 4, "part k starts beside the next batch's traversal k + 1");
 
-constexpr size_t kBytesPerPath = 2 * (8 + 4 + 32 + 16) + 2 * (44 + 72 + 32 + 8 + 4 + 1);
+constexpr size_t kBytesPerPath = 2 * (8 + 4 + 32 + 16) + 2 * (44 + 56 + 32 + 8 + 4 + 1);
 
 struct Scene {
   uint64_t id = 0;
@@ -767,7 +767,7 @@ hpt_status alloc_batch(hpt_ctx *C) {
           A((void **)&Q.L, 4ull * N) && A((void **)&Q.pdf, 4ull * N);
     ok &= A((void **)&Q.ox, 8ull * N) && A((void **)&Q.oy, 8ull * N) && A((void **)&Q.oz, 8ull * N) &&
           A((void **)&Q.dx, 8ull * N) && A((void **)&Q.dy, 8ull * N) && A((void **)&Q.dz, 8ull * N) &&
-          A((void **)&Q.ell, 8ull * N) && A((void **)&Q.al, 8ull * N) && A((void **)&Q.be, 8ull * N);
+          A((void **)&Q.ell, 8ull * N);
     ok &= A((void **)&Q.ray, 32ull * N) && A((void **)&Q.t, 4ull * N) && A((void **)&Q.prim, 4ull * N);
     ok &= A((void **)&Q.idx, 4ull * N) && A((void **)&Q.cnt, 4ull * (N / 256 + 1)) &&
           A((void **)&Q.off, 4ull * (N / 256 + 1)) && A((void **)&Q.tile_sum, 4ull * 64);
