@@ -118,11 +118,13 @@ struct RayState {
   double ell;
 };
 
+// The path signature is carried only for jobs that keep per-path records
+// or signature sums (sig); the others never read it.
 template <bool EXT>
-__device__ __forceinline__ void load_state(const RayQueue &Q, uint32_t i, RayState &r) {
+__device__ __forceinline__ void load_state(const RayQueue &Q, uint32_t i, RayState &r, bool sig) {
   r.slot = Q.slot[i]; r.meta = Q.meta[i];
   r.ka = Q.ka[i]; r.kb = Q.kb[i];
-  r.sig = Q.sig[i];
+  r.sig = sig ? Q.sig[i] : kSigInit;
   r.bpre = Q.bpre[i]; r.wt = Q.wt[i]; r.beta = Q.beta[i]; r.L = Q.L[i];
   r.pdf = (EXT && (r.meta & 1u) == STAGE_TAIL) ? Q.pdf[i] : 0.f;
   if ((r.meta & 1u) == STAGE_PREFIX) {
@@ -527,7 +529,7 @@ __global__ void __launch_bounds__(kBlock) k_trace(BatchDev B, int q, int dense) 
 }
 
 // ------------------------------------------------------------------ shade
-struct Emit { bool on; };
+struct Emit { bool on, sig; };  // the ray continues; its signature is carried
 
 // A workgroup's continuing rays, staged in LDS (one column per lane, field by
 // field so that lanes never share a bank) from the point where shading
@@ -559,13 +561,14 @@ __device__ __forceinline__ void stage_put(StageLds &G, const RayState &r, F3 o, 
   e.on = true;
 }
 
-// Entry k of queue Q from this lane's staged ray.
+// Entry k of queue Q from this lane's staged ray (the signature only if
+// its job reads signatures).
 template <bool EXT>
-__device__ __forceinline__ void stage_store(const StageLds &G, const RayQueue &Q, uint32_t k) {
+__device__ __forceinline__ void stage_store(const StageLds &G, const RayQueue &Q, uint32_t k, bool sig) {
   const uint32_t t = threadIdx.x, meta = G.meta[t];
   Q.slot[k] = G.slot[t]; Q.unit[k] = G.unit[t]; Q.meta[k] = meta;
   Q.ka[k] = G.ka[t]; Q.kb[k] = G.kb[t];
-  Q.sig[k] = G.sig[t];
+  if (sig) Q.sig[k] = G.sig[t];
   Q.bpre[k] = G.bpre[t]; Q.wt[k] = G.wt[t]; Q.beta[k] = G.beta[t]; Q.L[k] = G.L[t];
   if (EXT) Q.pdf[k] = G.pdf[t];
   if ((meta & 1u) == STAGE_PREFIX) {
@@ -984,6 +987,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EXT
     const bool live = v < n;
     Emit e;
     e.on = false;
+    e.sig = false;
     if (live) {
       const uint32_t i = FIRST ? v : B.Q[q].idx[v];
       // the hit record is requested first: it is the longest chain
@@ -1001,8 +1005,9 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EXT
       if (hp >= 0) H = glb(S.hits)[hp];
       RayState st;
       st.unit = unit;
+      e.sig = (J.debug & 5u) != 0;
       if (FIRST) load_first(Qc, i, st, U, J);
-      else load_state<EXT>(Qc, i, st);
+      else load_state<EXT>(Qc, i, st, e.sig);
       shade_one<EXT>(B, q, i, st, G, U, J, S, M, t, hp, H, &St, e);
     }
     // compaction within the chunk: the continuing rays of chunk c take
@@ -1020,7 +1025,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EXT
     }
     __syncthreads();
     const uint32_t before = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-    if (e.on) stage_store<EXT>(G, B.Q[qo], c * kBlock + wave_base[wv] + before);
+    if (e.on) stage_store<EXT>(G, B.Q[qo], c * kBlock + wave_base[wv] + before, e.sig);
   }
 }
 
