@@ -125,8 +125,12 @@ __device__ __forceinline__ void load_state(const RayQueue &Q, uint32_t i, RaySta
   r.slot = Q.slot[i]; r.meta = Q.meta[i];
   r.ka = Q.ka[i]; r.kb = Q.kb[i];
   r.sig = sig ? Q.sig[i] : kSigInit;
-  r.bpre = Q.bpre[i]; r.wt = Q.wt[i]; r.beta = Q.beta[i]; r.L = Q.L[i];
-  r.pdf = (EXT && (r.meta & 1u) == STAGE_TAIL) ? Q.pdf[i] : 0.f;
+  r.bpre = Q.bpre[i]; r.wt = Q.wt[i];
+  // a prefix ray's tail throughput and radiance are 1 and 0: not stored
+  const bool tail = (r.meta & 1u) == STAGE_TAIL;
+  r.beta = tail ? Q.beta[i] : 1.f;
+  r.L = tail ? Q.L[i] : 0.f;
+  r.pdf = (EXT && tail) ? Q.pdf[i] : 0.f;
   if ((r.meta & 1u) == STAGE_PREFIX) {
     r.o = D3{Q.ox[i], Q.oy[i], Q.oz[i]};
     r.d = D3{Q.dx[i], Q.dy[i], Q.dz[i]};
@@ -569,8 +573,11 @@ __device__ __forceinline__ void stage_store(const StageLds &G, const RayQueue &Q
   Q.slot[k] = G.slot[t]; Q.unit[k] = G.unit[t]; Q.meta[k] = meta;
   Q.ka[k] = G.ka[t]; Q.kb[k] = G.kb[t];
   if (sig) Q.sig[k] = G.sig[t];
-  Q.bpre[k] = G.bpre[t]; Q.wt[k] = G.wt[t]; Q.beta[k] = G.beta[t]; Q.L[k] = G.L[t];
-  if (EXT) Q.pdf[k] = G.pdf[t];
+  Q.bpre[k] = G.bpre[t]; Q.wt[k] = G.wt[t];
+  if ((meta & 1u) == STAGE_TAIL) {  // a prefix ray's are 1 and 0
+    Q.beta[k] = G.beta[t]; Q.L[k] = G.L[t];
+    if (EXT) Q.pdf[k] = G.pdf[t];
+  }
   if ((meta & 1u) == STAGE_PREFIX) {
     Q.ox[k] = G.ox[t]; Q.oy[k] = G.oy[t]; Q.oz[k] = G.oz[t];
     Q.dx[k] = G.dx[t]; Q.dy[k] = G.dy[t]; Q.dz[k] = G.dz[t];
