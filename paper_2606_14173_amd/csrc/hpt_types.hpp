@@ -147,7 +147,6 @@ struct UnitDev {
 struct RayQueue {
   uint32_t *slot, *unit;
   uint32_t *meta;                  // stage | b << 1 | bP << 7
-  uint32_t *ka, *kb;               // Philox key words of the path
   unsigned long long *sig;         // path signature so far
   float *bpre;                     // beta_pre: product of the delta weights
   float *wt;                       // medium index in the prefix, then the weight W

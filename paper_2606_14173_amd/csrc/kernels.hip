@@ -82,6 +82,25 @@ __device__ __forceinline__ void slot_decode(const UnitDev &U, uint32_t slot, uin
   s_local = l - p_local * U.s_n;
 }
 
+// Philox key words of path slot `slot` of unit U: (global pixel index,
+// sample index) for a hologram path, (cell, bin << 16 | sample) for a cache
+// path. A function of the slot, so the ray queues do not carry them.
+__device__ __forceinline__ void path_keys(const UnitDev &U, const JobDev &J, uint32_t slot, uint32_t &ka,
+                                          uint32_t &kb) {
+  uint32_t p_local, s_local;
+  slot_decode(U, slot, p_local, s_local);
+  if (U.kind == UNIT_HOLO) {
+    uint32_t cx, cy;
+    crop_xy(J, U.p_lo + p_local, cx, cy);
+    ka = (J.crop_y0 + cy) * J.width + J.crop_x0 + cx;
+    kb = U.s_lo + s_local;
+  } else {
+    const uint32_t nb = J.cache_bins * J.cache_bins, e = U.p_lo + p_local, cell = e / nb;
+    ka = cell;
+    kb = ((e - cell * nb) << 16) | (U.s_lo + s_local);
+  }
+}
+
 __device__ __forceinline__ size_t rec_index(const JobDev &J, const UnitDev &U, uint32_t p_local,
                                             uint32_t s_local) {
   uint32_t cx, cy;
@@ -121,9 +140,10 @@ struct RayState {
 // The path signature is carried only for jobs that keep per-path records
 // or signature sums (sig); the others never read it.
 template <bool EXT>
-__device__ __forceinline__ void load_state(const RayQueue &Q, uint32_t i, RayState &r, bool sig) {
+__device__ __forceinline__ void load_state(const RayQueue &Q, uint32_t i, RayState &r, bool sig, const UnitDev &U,
+                                           const JobDev &J) {
   r.slot = Q.slot[i]; r.meta = Q.meta[i];
-  r.ka = Q.ka[i]; r.kb = Q.kb[i];
+  path_keys(U, J, r.slot, r.ka, r.kb);
   r.sig = sig ? Q.sig[i] : kSigInit;
   r.bpre = Q.bpre[i]; r.wt = Q.wt[i];
   // a prefix ray's tail throughput and radiance are 1 and 0: not stored
@@ -161,13 +181,12 @@ __device__ __forceinline__ void cone_cosines(const UnitDev &U, const JobDev &J, 
 }
 
 // Entry k of the first queue: what the first shading pass cannot rebuild
-// (slot, unit, key words) and the FP32 ray. The start state (signature,
-// throughputs, medium, stage) is the same for every path and the FP64
-// primary ray is a function of the pixel and the key words, so the first
-// shading pass rebuilds both (load_first) instead of reading them.
-__device__ __forceinline__ void store_first(const RayQueue &Q, uint32_t k, const RayState &r, uint32_t ka,
-                                            uint32_t kb, F3 o, F3 d) {
-  Q.slot[k] = r.slot; Q.unit[k] = r.unit; Q.ka[k] = ka; Q.kb[k] = kb;
+// (slot, unit) and the FP32 ray. The start state (signature, throughputs,
+// medium, stage) is the same for every path, and the key words and the FP64
+// primary ray are functions of the slot, so the first shading pass rebuilds
+// them (load_first) instead of reading them.
+__device__ __forceinline__ void store_first(const RayQueue &Q, uint32_t k, const RayState &r, F3 o, F3 d) {
+  Q.slot[k] = r.slot; Q.unit[k] = r.unit;
   Q.ray[2 * k] = make_float4(o.x, o.y, o.z, kTmin);
   Q.ray[2 * k + 1] = make_float4(d.x, d.y, d.z, __int_as_float(-1));
 }
@@ -311,7 +330,7 @@ __device__ __forceinline__ void gen_path(const UnitDev &U, const JobDev &J, uint
 __device__ __forceinline__ void load_first(const RayQueue &Q, uint32_t i, RayState &r, const UnitDev &U,
                                            const JobDev &J) {
   r.slot = Q.slot[i];
-  r.ka = Q.ka[i]; r.kb = Q.kb[i];
+  path_keys(U, J, r.slot, r.ka, r.kb);
   r.sig = kSigInit;
   r.bpre = 1.f; r.wt = 1.f; r.beta = 1.f; r.L = 0.f; r.pdf = 0.f;
   if (U.kind == UNIT_HOLO) {
@@ -424,7 +443,7 @@ __global__ void __launch_bounds__(kRaygenBlock) k_raygen(BatchDev B) {
     uint32_t ska = 0, skb = 0, kk;
     F3 ro, rd;
     gen_path(Us[u], UNI ? lds_job[0] : *Us[u].job, u, k, st, ska, skb, ro, rd, kk);
-    store_first(B.Q[0], g0 + w, st, ska, skb, ro, rd);
+    store_first(B.Q[0], g0 + w, st, ro, rd);
   }
 }
 
@@ -540,7 +559,7 @@ struct Emit { bool on, sig; };  // the ray continues; its signature is carried
 // finalises them until the compaction has given them their entry in the next
 // queue; this keeps the new state out of registers for the rest of the pass.
 struct StageLds {
-  uint32_t slot[kBlock], unit[kBlock], meta[kBlock], ka[kBlock], kb[kBlock];
+  uint32_t slot[kBlock], unit[kBlock], meta[kBlock];
   unsigned long long sig[kBlock];
   float bpre[kBlock], wt[kBlock], beta[kBlock], L[kBlock], pdf[kBlock];
   double ox[kBlock], oy[kBlock], oz[kBlock], dx[kBlock], dy[kBlock], dz[kBlock], ell[kBlock];
@@ -551,7 +570,6 @@ struct StageLds {
 __device__ __forceinline__ void stage_put(StageLds &G, const RayState &r, F3 o, F3 d, int32_t excl, Emit &e) {
   const uint32_t t = threadIdx.x;
   G.slot[t] = r.slot; G.unit[t] = r.unit; G.meta[t] = r.meta;
-  G.ka[t] = r.ka; G.kb[t] = r.kb;
   G.sig[t] = r.sig;
   G.bpre[t] = r.bpre; G.wt[t] = r.wt; G.beta[t] = r.beta; G.L[t] = r.L; G.pdf[t] = r.pdf;
   if ((r.meta & 1u) == STAGE_PREFIX) {
@@ -571,7 +589,6 @@ template <bool EXT>
 __device__ __forceinline__ void stage_store(const StageLds &G, const RayQueue &Q, uint32_t k, bool sig) {
   const uint32_t t = threadIdx.x, meta = G.meta[t];
   Q.slot[k] = G.slot[t]; Q.unit[k] = G.unit[t]; Q.meta[k] = meta;
-  Q.ka[k] = G.ka[t]; Q.kb[k] = G.kb[t];
   if (sig) Q.sig[k] = G.sig[t];
   Q.bpre[k] = G.bpre[t]; Q.wt[k] = G.wt[t];
   if ((meta & 1u) == STAGE_TAIL) {  // a prefix ray's are 1 and 0
@@ -1014,7 +1031,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EXT
       st.unit = unit;
       e.sig = (J.debug & 5u) != 0;
       if (FIRST) load_first(Qc, i, st, U, J);
-      else load_state<EXT>(Qc, i, st, e.sig);
+      else load_state<EXT>(Qc, i, st, e.sig, U, J);
       shade_one<EXT>(B, q, i, st, G, U, J, S, M, t, hp, H, &St, e);
     }
     // compaction within the chunk: the continuing rays of chunk c take

@@ -50,7 +50,7 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
 
 constexpr uint32_t kMaxUnitsPerBatch = 4096;
 // per path, in two sets: final signature, first hit, results; per queue
-// entry (two queues): state (44 B), FP64 prefix ray (56 B), FP32 ray (32 B),
+// entry (two queues): state (36 B), FP64 prefix ray (56 B), FP32 ray (32 B),
 // hit (8 B), index list (4 B; chunk counts and offsets: 8 B per 256 entries)
 #ifndef HPT_ACC_PARTS
 #define HPT_ACC_PARTS 3
@@ -58,7 +58,7 @@ constexpr uint32_t kMaxUnitsPerBatch = 4096;
 constexpr uint32_t kAccParts = HPT_ACC_PARTS;  // accumulation launches per batch
 static_assert(kAccParts >= 1 && kAccParts <= 4, "part k starts beside the next batch's traversal k + 1");
 
-constexpr size_t kBytesPerPath = 2 * (8 + 4 + 32 + 16) + 2 * (44 + 56 + 32 + 8 + 4 + 1);
+constexpr size_t kBytesPerPath = 2 * (8 + 4 + 32 + 16) + 2 * (36 + 56 + 32 + 8 + 4 + 1);
 
 struct Scene {
   uint64_t id = 0;
@@ -762,7 +762,7 @@ hpt_status alloc_batch(hpt_ctx *C) {
   for (int q = 0; q < 2 && ok; ++q) {
     RayQueue &Q = B.Q[q];
     ok &= A((void **)&Q.slot, 4ull * N) && A((void **)&Q.unit, 4ull * N) && A((void **)&Q.meta, 4ull * N) &&
-          A((void **)&Q.ka, 4ull * N) && A((void **)&Q.kb, 4ull * N) && A((void **)&Q.sig, 8ull * N) &&
+          A((void **)&Q.sig, 8ull * N) &&
           A((void **)&Q.bpre, 4ull * N) && A((void **)&Q.wt, 4ull * N) && A((void **)&Q.beta, 4ull * N) &&
           A((void **)&Q.L, 4ull * N) && A((void **)&Q.pdf, 4ull * N);
     ok &= A((void **)&Q.ox, 8ull * N) && A((void **)&Q.oy, 8ull * N) && A((void **)&Q.oz, 8ull * N) &&
