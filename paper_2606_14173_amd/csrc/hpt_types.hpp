@@ -43,6 +43,11 @@ constexpr float kTmin = 1e-7f;       // self-intersection guard (metres)
 constexpr double kTminD = 1e-7;
 
 enum Stage : uint32_t { STAGE_PREFIX = 0, STAGE_TAIL = 1 };
+// A queue entry's slot word: the path slot (batches hold at most 2^26
+// paths) | stage << 26 | bP << 27 (the interaction of the image point, at
+// most 31). The interaction count b of every ray in a queue is the pass
+// index, so it is not stored.
+constexpr uint32_t kSlotBits = 26, kSlotMask = (1u << kSlotBits) - 1u;
 enum UnitKind : uint32_t { UNIT_HOLO = 0, UNIT_CACHE = 1 };
 
 // Lanes per pixel in the accumulation: one per two frames.
@@ -146,7 +151,6 @@ struct UnitDev {
 // the coherent prefix.
 struct RayQueue {
   uint32_t *slot, *unit;
-  uint32_t *meta;                  // stage | b << 1 | bP << 7
   unsigned long long *sig;         // path signature so far
   float *bpre;                     // beta_pre: product of the delta weights
   float *wt;                       // medium index in the prefix, then the weight W

@@ -141,8 +141,10 @@ struct RayState {
 // or signature sums (sig); the others never read it.
 template <bool EXT>
 __device__ __forceinline__ void load_state(const RayQueue &Q, uint32_t i, RayState &r, bool sig, const UnitDev &U,
-                                           const JobDev &J) {
-  r.slot = Q.slot[i]; r.meta = Q.meta[i];
+                                           const JobDev &J, uint32_t b) {
+  const uint32_t w = Q.slot[i];
+  r.slot = w & kSlotMask;
+  r.meta = ((w >> kSlotBits) & 1u) | (b << 1) | ((w >> (kSlotBits + 1)) << 7);
   path_keys(U, J, r.slot, r.ka, r.kb);
   r.sig = sig ? Q.sig[i] : kSigInit;
   r.bpre = Q.bpre[i]; r.wt = Q.wt[i];
@@ -588,7 +590,8 @@ __device__ __forceinline__ void stage_put(StageLds &G, const RayState &r, F3 o, 
 template <bool EXT>
 __device__ __forceinline__ void stage_store(const StageLds &G, const RayQueue &Q, uint32_t k, bool sig) {
   const uint32_t t = threadIdx.x, meta = G.meta[t];
-  Q.slot[k] = G.slot[t]; Q.unit[k] = G.unit[t]; Q.meta[k] = meta;
+  Q.slot[k] = G.slot[t] | ((meta & 1u) << kSlotBits) | (((meta >> 7) & 31u) << (kSlotBits + 1));
+  Q.unit[k] = G.unit[t];
   if (sig) Q.sig[k] = G.sig[t];
   Q.bpre[k] = G.bpre[t]; Q.wt[k] = G.wt[t];
   if ((meta & 1u) == STAGE_TAIL) {  // a prefix ray's are 1 and 0
@@ -965,7 +968,7 @@ __device__ __forceinline__ void shade_one(const BatchDev &B, int q, uint32_t i, 
 // which has at most kLdsUnits units; its job, scene, material and unit
 // descriptors are read from LDS.
 template <bool FIRST, bool EXT, bool UNI>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EXT ? 2 : 3))) k_shade(BatchDev B, int q) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EXT ? 2 : 3))) k_shade(BatchDev B, int q, uint32_t pass) {
   // FIRST: queue 0 as ray generation wrote it (dense); else a compacted
   // queue, read through its index list
   __shared__ StageLds G;
@@ -1031,7 +1034,7 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(EXT
       st.unit = unit;
       e.sig = (J.debug & 5u) != 0;
       if (FIRST) load_first(Qc, i, st, U, J);
-      else load_state<EXT>(Qc, i, st, e.sig, U, J);
+      else load_state<EXT>(Qc, i, st, e.sig, U, J, pass);
       shade_one<EXT>(B, q, i, st, G, U, J, S, M, t, hp, H, &St, e);
     }
     // compaction within the chunk: the continuing rays of chunk c take
@@ -1598,14 +1601,15 @@ hipError_t launch_compact(const BatchDev &B, int q, hipStream_t st) {
 uint32_t shade_lds_mats() { return kLdsMats; }
 uint32_t shade_lds_units() { return kLdsUnits; }
 
-hipError_t launch_shade(const BatchDev &B, int q, bool first, bool ext, bool uni, hipStream_t st) {
+hipError_t launch_shade(const BatchDev &B, int q, uint32_t pass, bool ext, bool uni, hipStream_t st) {
+  const bool first = pass == 0;
   const uint32_t g = min(round8(grid_for(B.n_paths)), kShadeGridMax);
   const uint32_t gn = ext ? min(g, B.spill_threads / (uint32_t)kBlock) : g;  // one spill column per lane
   auto k = ext ? (first ? (uni ? k_shade<true, true, true> : k_shade<true, true, false>)
                         : (uni ? k_shade<false, true, true> : k_shade<false, true, false>))
                : (first ? (uni ? k_shade<true, false, true> : k_shade<true, false, false>)
                         : (uni ? k_shade<false, false, true> : k_shade<false, false, false>));
-  hipLaunchKernelGGL(k, dim3(gn), dim3(kBlock), 0, st, B, q);
+  hipLaunchKernelGGL(k, dim3(gn), dim3(kBlock), 0, st, B, q, pass);
   return hipGetLastError();
 }
 

@@ -24,7 +24,8 @@ uint32_t trace_block();
 // first: queue from k_raygen; ext: the batch's jobs use next-event estimation
 // or principled materials (extended shading kernel); uni: the batch has one
 // job, at most shade_lds_mats() materials and at most shade_lds_units() units
-hipError_t launch_shade(const BatchDev &B, int q, bool first, bool ext, bool uni, hipStream_t st);
+// shading pass `pass` (0: the first, over ray generation's queue)
+hipError_t launch_shade(const BatchDev &B, int q, uint32_t pass, bool ext, bool uni, hipStream_t st);
 uint32_t shade_lds_mats();
 uint32_t shade_lds_units();
 // accumulation lanes [lane0, lane_end) of the batch

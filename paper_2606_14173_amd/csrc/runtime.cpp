@@ -50,7 +50,7 @@ double ms_between(Clock::time_point a, Clock::time_point b) {
 
 constexpr uint32_t kMaxUnitsPerBatch = 4096;
 // per path, in two sets: final signature, first hit, results; per queue
-// entry (two queues): state (36 B), FP64 prefix ray (56 B), FP32 ray (32 B),
+// entry (two queues): state (32 B), FP64 prefix ray (56 B), FP32 ray (32 B),
 // hit (8 B), index list (4 B; chunk counts and offsets: 8 B per 256 entries)
 #ifndef HPT_ACC_PARTS
 #define HPT_ACC_PARTS 3
@@ -58,7 +58,7 @@ constexpr uint32_t kMaxUnitsPerBatch = 4096;
 constexpr uint32_t kAccParts = HPT_ACC_PARTS;  // accumulation launches per batch
 static_assert(kAccParts >= 1 && kAccParts <= 4, "part k starts beside the next batch's traversal k + 1");
 
-constexpr size_t kBytesPerPath = 2 * (8 + 4 + 32 + 16) + 2 * (36 + 56 + 32 + 8 + 4 + 1);
+constexpr size_t kBytesPerPath = 2 * (8 + 4 + 32 + 16) + 2 * (32 + 56 + 32 + 8 + 4 + 1);
 
 struct Scene {
   uint64_t id = 0;
@@ -542,7 +542,7 @@ hpt_status launch_batch(hpt_ctx *C, int si, int prev) {
   for (uint32_t it = 0; it <= max_b; ++it) {
     int q = (int)(it & 1u);
     timed_launch(L, HPT_K_TRACE, S, e, [&] { return launch_trace(B, q, it == 0, profile >= 2, S); });
-    timed_launch(L, HPT_K_SHADE, S, e, [&] { return launch_shade(B, q, it == 0, L.has_ext, uni, S); });
+    timed_launch(L, HPT_K_SHADE, S, e, [&] { return launch_shade(B, q, it, L.has_ext, uni, S); });
     // the last pass ends every path (interaction max_b + 1 exceeds the
     // budget), so only the earlier ones leave rays to order
     if (it < max_b) timed_launch(L, HPT_K_COMPACT, S, e, [&] { return launch_compact(B, q, S); });
@@ -761,7 +761,7 @@ hpt_status alloc_batch(hpt_ctx *C) {
   }
   for (int q = 0; q < 2 && ok; ++q) {
     RayQueue &Q = B.Q[q];
-    ok &= A((void **)&Q.slot, 4ull * N) && A((void **)&Q.unit, 4ull * N) && A((void **)&Q.meta, 4ull * N) &&
+    ok &= A((void **)&Q.slot, 4ull * N) && A((void **)&Q.unit, 4ull * N) &&
           A((void **)&Q.sig, 8ull * N) &&
           A((void **)&Q.bpre, 4ull * N) && A((void **)&Q.wt, 4ull * N) && A((void **)&Q.beta, 4ull * N) &&
           A((void **)&Q.L, 4ull * N) && A((void **)&Q.pdf, 4ull * N);
@@ -843,7 +843,7 @@ hpt_status hpt_create(int device, uint64_t budget, hpt_ctx **out) {
   auto batch_bytes = [](uint32_t n) {
     return (uint64_t)n * kBytesPerPath + (uint64_t)kStackSpill * 4 * trace_grid(n) * trace_block();
   };
-  uint32_t c = 1u << 26;
+  uint32_t c = 1u << kSlotBits;  // a queue entry's slot word holds slots below 2^kSlotBits
   while (c > (1u << 16) && batch_bytes(c) > C->budget / 4) c /= 2;
   if (batch_bytes(c) > C->budget) return fail(HPT_EBUDGET, "budget too small for path state");
   C->capacity = c;
