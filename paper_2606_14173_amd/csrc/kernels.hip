@@ -165,21 +165,31 @@ __device__ __forceinline__ void load_state(const RayQueue &Q, uint32_t i, RaySta
 // path's first two uniforms (FP32 phase draws them in FP32). A function of
 // the key words, so the passes that need the direction recompute it rather
 // than carrying it in the queues.
-__device__ __forceinline__ void cone_cosines(const UnitDev &U, const JobDev &J, uint32_t gpix, uint32_t smp,
-                                             double &al, double &be) {
-  const uint32_t comp = J.comp[U.ch];
-  const U4 w = philox(gpix, smp, 0u, comp << 16, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
+// The two Philox words the cone direction of path (gpix, smp) is drawn from.
+__device__ __forceinline__ U4 cone_words(const UnitDev &U, const JobDev &J, uint32_t gpix, uint32_t smp) {
+  return philox(gpix, smp, 0u, J.comp[U.ch] << 16, (uint32_t)J.seed, (uint32_t)(J.seed >> 32));
+}
+
+// (al, be) from those words.
+__device__ __forceinline__ void cone_from_words(const UnitDev &U, const JobDev &J, uint32_t wx, uint32_t wy,
+                                                double &al, double &be) {
   if (J.phase_mode != HPT_PHASE_FP32) {
-    const double rad = J.s_cone[U.ch] * sqrt(ud(w.x));
+    const double rad = J.s_cone[U.ch] * sqrt(ud(wx));
     double sn, cs;
-    sincospi(2.0 * ud(w.y), &sn, &cs);
+    sincospi(2.0 * ud(wy), &sn, &cs);
     al = rad * cs; be = rad * sn;
   } else {
-    const float rad = J.s_cone_f[U.ch] * sqrtf(uf(w.x));
+    const float rad = J.s_cone_f[U.ch] * sqrtf(uf(wx));
     float sn, cs;
-    sincospif(2.0f * uf(w.y), &sn, &cs);
+    sincospif(2.0f * uf(wy), &sn, &cs);
     al = rad * cs; be = rad * sn;
   }
+}
+
+__device__ __forceinline__ void cone_cosines(const UnitDev &U, const JobDev &J, uint32_t gpix, uint32_t smp,
+                                             double &al, double &be) {
+  const U4 w = cone_words(U, J, gpix, smp);
+  cone_from_words(U, J, w.x, w.y, al, be);
 }
 
 // Entry k of the first queue: what the first shading pass cannot rebuild
@@ -348,17 +358,22 @@ __device__ __forceinline__ void load_first(const RayQueue &Q, uint32_t i, RaySta
 
 // Direction-sort key of path slot i of unit u: for a hologram path the
 // 32x32 Morton cell of its cone direction cosines over s (from the same
-// uniforms as gen_path, in FP32: the key only orders the queue); for a
-// cache path the one gen_path gives.
-__device__ __forceinline__ uint32_t sort_key(const UnitDev &U, const JobDev &J, uint32_t u, uint32_t i) {
+// uniforms as gen_path, in FP32: the key only orders the queue), with the
+// pixel (px | py << 16) and the two Philox words of the direction, which ray
+// generation keeps for the path's second pass; for a cache path the key
+// gen_path gives.
+__device__ __forceinline__ uint32_t sort_key(const UnitDev &U, const JobDev &J, uint32_t u, uint32_t i,
+                                             uint32_t &pxy, uint32_t &wx, uint32_t &wy) {
   uint32_t p_local, s_local;
   slot_decode(U, i, p_local, s_local);
+  pxy = wx = wy = 0u;
   if (U.kind == UNIT_HOLO) {
     uint32_t cx, cy;
     crop_xy(J, U.p_lo + p_local, cx, cy);
-    const uint32_t gpix = (J.crop_y0 + cy) * J.width + J.crop_x0 + cx;
-    const U4 w = philox(gpix, U.s_lo + s_local, 0u, J.comp[U.ch] << 16, (uint32_t)J.seed,
-                        (uint32_t)(J.seed >> 32));
+    const uint32_t px = J.crop_x0 + cx, py = J.crop_y0 + cy;
+    const U4 w = cone_words(U, J, py * J.width + px, U.s_lo + s_local);
+    pxy = px | (py << 16);
+    wx = w.x; wy = w.y;
     const float rad = sqrtf(uf(w.x));
     float sn, cs;
     sincospif(2.0f * uf(w.y), &sn, &cs);
@@ -376,6 +391,11 @@ __global__ void __launch_bounds__(kRaygenBlock) k_raygen(BatchDev B) {
   static_assert(kSortBins <= kRaygenBlock, "one thread per sort bin");
   __shared__ uint32_t hist[kSortBins], wsum[kRaygenBlock / 64];
   __shared__ uint16_t perm[kRaygenWindow];
+  // what the first pass learnt of each slot of the window, for the second:
+  // unit, pixel, the Philox words of the cone direction (the workgroup is
+  // alone on its CU, so this LDS costs no occupancy)
+  __shared__ uint16_t s_unit[kRaygenWindow];
+  __shared__ uint32_t s_pxy[kRaygenWindow], s_wx[kRaygenWindow], s_wy[kRaygenWindow];
   __shared__ JobDev lds_job[1];
   __shared__ UnitDev lds_units[UNI ? kLdsUnits : 1];
   static_assert(kRaygenWindow <= 65536, "sorted positions fit 16 bits");
@@ -406,7 +426,9 @@ __global__ void __launch_bounds__(kRaygenBlock) k_raygen(BatchDev B) {
       const uint32_t u = find_unit(Us, B.n_units, i, false);
       const JobDev &Jr = UNI ? lds_job[0] : *Us[u].job;
       if (Jr.debug & 1u) B.s_first[i] = -1;
-      key[r] = sort_key(Us[u], Jr, u, i);
+      uint32_t pxy, wx, wy;
+      key[r] = sort_key(Us[u], Jr, u, i, pxy, wx, wy);
+      s_unit[w] = (uint16_t)u; s_pxy[w] = pxy; s_wx[w] = wx; s_wy[w] = wy;
       rank[r] = atomicAdd(&hist[key[r]], 1u);
     }
   }
@@ -433,18 +455,30 @@ __global__ void __launch_bounds__(kRaygenBlock) k_raygen(BatchDev B) {
     if (w < nv) perm[hist[key[r]] + rank[r]] = (uint16_t)w;
   }
   __syncthreads();
-  // entry g0 + w of the first queue: the path at sorted position w,
-  // generated again (its random numbers are a function of the path), so that
-  // the queue entries are written in order
+  // entry g0 + w of the first queue: the path at sorted position w, its
+  // ray built again from what the first pass kept (a hologram path) or
+  // generated again (a cache path), so that the queue entries are written in
+  // order
   for (uint32_t r = 0; r < kRaygenSlots; ++r) {
     const uint32_t w = r * blockDim.x + threadIdx.x;
     if (w >= nv) break;
-    const uint32_t k = g0 + perm[w];
-    const uint32_t u = find_unit(Us, B.n_units, k, false);
+    const uint32_t wi = perm[w], k = g0 + wi, u = s_unit[wi];
+    const UnitDev &U = Us[u];
+    const JobDev &J = UNI ? lds_job[0] : *U.job;
     RayState st;
-    uint32_t ska = 0, skb = 0, kk;
     F3 ro, rd;
-    gen_path(Us[u], UNI ? lds_job[0] : *Us[u].job, u, k, st, ska, skb, ro, rd, kk);
+    if (U.kind == UNIT_HOLO) {
+      double al, be;
+      cone_from_words(U, J, s_wx[wi], s_wy[wi], al, be);
+      const uint32_t pxy = s_pxy[wi];
+      D3 O, d;
+      primary_ray(J, pxy & 0xFFFFu, pxy >> 16, al, be, O, d);
+      st.slot = k; st.unit = u;
+      ro = to_f(O); rd = to_f(d);
+    } else {
+      uint32_t ska = 0, skb = 0, kk;
+      gen_path(U, J, u, k, st, ska, skb, ro, rd, kk);
+    }
     store_first(B.Q[0], g0 + w, st, ro, rd);
   }
 }
