@@ -157,13 +157,16 @@ def test_translation_transform(ctx):
     assert r["ok"]
 
 
-@pytest.mark.parametrize("shape", [(1, 1, 1), (37, 29, 3), (65, 3, 5)])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (37, 29, 3), (65, 3, 5), (300, 11, 2)])
 def test_ragged_sizes(ctx, shape):
-    """Crops that are not multiples of the wave size, one sample, T=1..5."""
+    """Crops that are not multiples of the wave size, five samples, T=1..5;
+    the 300-column crop ends in a 4-column tile and a 3-row band of the
+    pixel order."""
     w, h, T = shape
+    W = max(80, w + 8)
     sc = scenes.scene_tiny(0)
-    job = jobs.job_for_config(0, width=80, height=72, crop=(3, 5, w, h), T=T, spp=5,
-                              grf_w=96, grf_h=96,
+    job = jobs.job_for_config(0, width=W, height=72, crop=(3, 5, w, h), T=T, spp=5,
+                              grf_w=max(96, W), grf_h=96,
                               phase_mode=jobs.PHASE_SPLIT)
     sid = ctx.upload_scene(sc)
     r = compare(*gpu_run(ctx, sid, job), *oracle_run(sc, job))
