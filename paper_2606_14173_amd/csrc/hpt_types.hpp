@@ -27,6 +27,9 @@ constexpr int kTraceChunk = HPT_TRACE_CHUNK;  // queue entries a traversal wave 
 #ifndef HPT_TRACE_GRID
 #define HPT_TRACE_GRID 2048
 #endif
+#ifndef HPT_TRACE_PRIO
+#define HPT_TRACE_PRIO 2  // wave issue priority of the traversal (0..3)
+#endif
 #ifndef HPT_STRAGGLERS
 #define HPT_STRAGGLERS 24
 #endif

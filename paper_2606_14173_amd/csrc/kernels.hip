@@ -499,6 +499,10 @@ __global__ void __launch_bounds__(kRaygenBlock) k_raygen(BatchDev B) {
 // column of the global spill.
 template <bool COUNT>
 __global__ void __launch_bounds__(kBlock) k_trace(BatchDev B, int q, int dense) {
+  // issue priority over the previous batch's accumulation waves that share
+  // the SIMDs (the traversal is on the step's critical path, the
+  // accumulation beside it is not)
+  __builtin_amdgcn_s_setprio(HPT_TRACE_PRIO);
   __shared__ int32_t stack[kStackLds * kBlock];
   __shared__ v4f top_nodes[4 * (kLdsNodes ? kLdsNodes : 1)];
   // the top levels of the BVH (its first kLdsNodes nodes) in LDS, when every
