@@ -9,8 +9,11 @@ namespace hpt {
 
 constexpr int kMaxT = 64;
 constexpr int kStackMax = 64;        // BVH depth bound enforced by the builder
+// LDS per traversal workgroup: kStackLds x 256 entries of the stack plus
+// kLdsNodes 64-byte nodes (8 KB + 14 KB), so that seven workgroups share a
+// CU's 160 KB at seven waves per SIMD
 #ifndef HPT_STACK_LDS
-#define HPT_STACK_LDS 12
+#define HPT_STACK_LDS 8
 #endif
 #ifndef HPT_LDS_NODES
 #define HPT_LDS_NODES 224

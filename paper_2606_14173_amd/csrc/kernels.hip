@@ -496,9 +496,11 @@ __global__ void __launch_bounds__(kRaygenBlock) k_raygen(BatchDev B) {
 // queue is drained, however short the queue. The grid is a multiple of
 // kClaimClasses workgroups, so every class is drained.
 // The traversal stack is kStackLds entries per lane in LDS, then the lane's
-// column of the global spill.
+// column of the global spill. Seven waves per SIMD (72 VGPRs, a few spilled
+// to scratch outside the node loop) hide more of the node-fetch latency than
+// six with no spill.
 template <bool COUNT>
-__global__ void __launch_bounds__(kBlock) k_trace(BatchDev B, int q, int dense) {
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) k_trace(BatchDev B, int q, int dense) {
   // issue priority over the previous batch's accumulation waves that share
   // the SIMDs (the traversal is on the step's critical path, the
   // accumulation beside it is not)
