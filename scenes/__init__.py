@@ -11,6 +11,6 @@ from .generators import (  # noqa: F401
     scene_patch, scene_mirror_patch, scene_slab, scene_furnace_sphere,
     scene_lambert_plane, scene_single_tri, scene_translate, empty_scene, scene_lit_plane,
     scene_slab_emitter, scene_ggx_plane, scene_depth_rescaled, scene_point_emitters,
-    scene_emitter_box,
+    scene_emitter_box, scene_sheet_stack,
 )
 from .jobs import job_for_config, JOB_DEFAULTS  # noqa: F401

@@ -369,6 +369,21 @@ def scene_mirror_patch(z1, zm, half, center=(0.0, 0.0), mirror_half=5 * MM):
     return b.finish()
 
 
+def scene_sheet_stack(n=4096, z0=3 * MM, dz=0.5e-6, half0=50e-6, dhalf=0.1e-6, albedo=0.5, env=1.0):
+    """n parallel square Lambert sheets facing the SLM (-z), sheet k at depth
+    z0 + k dz with half-width half0 + k dhalf: a ray at lateral distance r
+    from the axis passes the nearer, smaller sheets and stops at the first one
+    wider than r. The BVH splits the stack along z, so a ray's descent meets
+    both children (both boxes span its path) at almost every level and keeps
+    a pending far child per level."""
+    b = _Builder()
+    m = b.material(LAMBERT, rgb=(albedo,) * 3)
+    for k in range(n):
+        h = half0 + k * dhalf
+        b.add_quad((-h, -h, z0 + k * dz), (0, 2 * h, 0), (2 * h, 0, 0), m)
+    return b.finish(env=(env,) * 3)
+
+
 def scene_slab(za, zb, zc, ior=1.5, half=5 * MM, albedo=0.5, env=0.0):
     """Dielectric slab between the planes z=za and z=zb (outward normals -z and
     +z) in front of a Lambert plane at z=zc."""

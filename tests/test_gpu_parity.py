@@ -157,6 +157,28 @@ def test_translation_transform(ctx):
     assert r["ok"]
 
 
+def test_deep_traversal_stack(ctx):
+    """4096 stacked sheets along the rays (8192 triangles, BVH depth 14):
+    each traversal descends through a z-split hierarchy in which both
+    children lie on its path and keeps a pending entry per level, up to 13;
+    about one primary ray in eleven holds more than the 8 stack entries kept
+    in LDS, so its deeper entries go through the global spill (a CPU model of
+    the descent on this scene gives these counts). Rays stop on sheets from
+    the first to deep inside the stack (the sheets widen with depth); GPU
+    against the oracle's brute-force hits."""
+    sc = scenes.scene_sheet_stack()
+    sid = ctx.upload_scene(sc)
+    info = ctx.scene_info(sid)
+    print("sheet stack: BVH depth %d, %d nodes" % (info["max_depth"], info["n_nodes"]))
+    assert info["max_depth"] >= 12
+    gw, gh = jobs.grf_size(16, 16, 2e-6, 520e-9, 6e-3)
+    job = _job(width=16, height=16, pitch=2e-6, lambdas=[520e-9], comps=[1], spp=16,
+               max_bounces=3, T=2, grf_w=gw, grf_h=gh, grf_seed=4, phase_mode=jobs.PHASE_SPLIT)
+    r = compare(*gpu_run(ctx, sid, job), *oracle_run(sc, job))
+    _say("sheet-stack", r)
+    assert r["ok"]
+
+
 @pytest.mark.parametrize("shape", [(1, 1, 1), (37, 29, 3), (65, 3, 5), (300, 11, 2)])
 def test_ragged_sizes(ctx, shape):
     """Crops that are not multiples of the wave size, five samples, T=1..5;
